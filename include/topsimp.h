@@ -1,0 +1,182 @@
+/*
+ * topsimp.h -- C ABI of the MI355X (gfx950) topological-simplification
+ * library.
+ *
+ * Method: Kissi, Pont, Levine, Tierny, "A Practical Solver for Scalar Data
+ * Topological Simplification" (arXiv 2407.12399).  The library computes the
+ * persistence diagram of a PL scalar field on the Freudenthal triangulation
+ * of a 3D regular grid (Sec. 2.1-2.2) with the discrete-gradient approach of
+ * Sec. 4.2, and runs the simplification solver of Alg. 1 with the direct
+ * gradient step of Sec. 4.1 and the still-pair assignment reuse of Sec. 4.3.
+ * Every step of the persistence map, the still-pair join and the update runs
+ * in the library's HIP kernels on one GPU; the exact reduced assignment
+ * (Eq. 1 with q = 2 on the pairs that are not still) runs on the host.
+ *
+ * Conventions
+ *  - Field: float32, layout [Lz][Ly][Lx] (x fastest), vertex id
+ *    v = x + Lx*(y + Ly*z).  dims = {Lx, Ly, Lz}, each >= 2, Lx*Ly*Lz <= 2^25.
+ *  - Triangulation: Freudenthal/Kuhn.  A cell anchored at vertex u is
+ *    {u + c0, ..., u + ck} with 0 = c0 < c1 < ... < ck <= (1,1,1) a chain of
+ *    unit-cube corners (corner mask bit0 = x, bit1 = y, bit2 = z).  Canonical
+ *    ids: edge 7u+t, triangle 12u+t, tetrahedron 6u+t with types
+ *      edge t:      c1 = t+1
+ *      triangle t:  (c1,c2) in (1,3)(2,3)(1,5)(4,5)(2,6)(4,6)
+ *                              (1,7)(2,7)(3,7)(4,7)(5,7)(6,7)
+ *      tet t:       (c1,c2,7) with (c1,c2) in (1,3)(1,5)(2,3)(2,6)(4,5)(4,6)
+ *  - Vertex order (Sec. 2.1-2.2): (value, id) ascending, -0.0 equal to +0.0.
+ *  - Lexicographic filtration (Sec. 2.2): cells compare by the ranks of their
+ *    vertices sorted decreasingly, a proper prefix first.
+ *
+ * Memory and streams
+ *  - A context owns a HIP stream (the caller's, or the null stream) and a
+ *    device workspace that grows on demand and is freed by ts_destroy.
+ *  - Pointers marked "device or host" are read as device pointers when
+ *    `inputs_on_device` (options) / `on_device` (arguments) is 1, otherwise as
+ *    host pointers.  Device pointers must be valid on the context's device and
+ *    are accessed in order on the context's stream.
+ *  - Calls are synchronous: on return every output is written.
+ *  - A context is not thread-safe; use one context per host thread.
+ *
+ * Status codes: every function returns one of the TS_* codes below; the
+ * message of the last error is available from ts_last_error.
+ */
+#ifndef TOPSIMP_H
+#define TOPSIMP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TS_OK = 0,
+  TS_WARN_NOT_CANCELLED = 1, /* j_max reached before the stop rule held */
+  TS_ERR_ARG = -1,           /* null pointer, bad dims, aliasing, bad option */
+  TS_ERR_NONFINITE = -2,     /* NaN or Inf in the field */
+  TS_ERR_OOM = -3,           /* device allocation failed */
+  TS_ERR_HIP = -4,           /* HIP runtime error */
+  TS_ERR_CAPACITY = -5,      /* output buffer too small (*n_out = required) */
+  TS_ERR_INTERNAL = -6       /* an internal consistency check failed */
+};
+
+/* One persistence pair (Sec. 2.2), 48 bytes. */
+typedef struct {
+  int32_t dim;        /* 0 min-saddle, 1 saddle-saddle, 2 saddle-max */
+  int32_t essential;  /* 1: the infinite class (dim 0); death_cell = -1,
+                         v_death = last vertex of the order */
+  int64_t birth_cell; /* canonical id of the birth simplex (dimension dim) */
+  int64_t death_cell; /* canonical id of the death simplex (dimension dim+1) */
+  int64_t v_birth;    /* highest vertex of the birth simplex */
+  int64_t v_death;    /* highest vertex of the death simplex */
+  float birth;        /* f(v_birth) */
+  float death;        /* f(v_death) */
+} ts_pair;
+
+/* Signal selection (Sec. 3): which pairs of D(f0) are kept. */
+typedef struct {
+  int32_t mode;                /* 0: persistence threshold, 1: explicit list */
+  float threshold_rel;         /* threshold = threshold_rel * (max f0 - min f0) */
+  uint32_t nonsignal_dim_mask; /* bit k set: dim-k pairs below the threshold are
+                                  non-signal; pairs of other dims are signal */
+  int32_t ties_signal;         /* persistence == threshold: 1 signal, 0 non-signal */
+  const ts_pair* signal;       /* mode 1: host array of signal pairs, matched on
+                                  (dim, birth_cell, death_cell); others non-signal */
+  int64_t n_signal;
+} ts_signal;
+
+/* Solver options (Sec. 4.1, Sec. 5). */
+typedef struct {
+  float alpha_b, alpha_d;  /* step sizes of the birth / death gradients (0.5, 0.5) */
+  int32_t j_max;           /* iteration cap (1000) */
+  int32_t stop_mode;       /* 0: every diagonal-assigned point has persistence
+                                 < cancel_tol_rel * range (full cancellation)
+                              1: loss <= loss_ratio_s * loss at iteration 0 */
+  float cancel_tol_rel;    /* 1e-6 */
+  float loss_ratio_s;      /* 0.01 */
+  int32_t inputs_on_device; /* f and g are device pointers */
+} ts_options;
+
+typedef struct {
+  int32_t iterations;       /* gradient steps performed */
+  int32_t cancelled;        /* 1 if the stop rule held */
+  double loss0, loss;       /* loss at iteration 0 / at the end */
+  double energy;            /* loss + diagonal cost of unmatched targets */
+  double linf, l2;          /* ||f-g||_inf, ||f-g||_2 */
+  double max_nonsignal_pers; /* largest persistence among diagonal-assigned points */
+  double max_signal_disp;   /* largest distance of a target-assigned point to its target */
+  double range;             /* max(f0) - min(f0) */
+  int64_t n_pairs[3];       /* final diagram size per dimension (finite pairs) */
+  int64_t n_still;          /* still pairs at the last iteration */
+  int64_t n_reduced;        /* points of the last reduced assignment problem */
+  int64_t n_targets;        /* |D_T| */
+  double total_s;           /* wall time of the call */
+  double persistence_s;     /* time in the persistence map (all iterations) */
+  double assign_s;          /* time in the still join + assignment */
+  double update_s;          /* time in the gradient step */
+} ts_report;
+
+typedef struct ts_ctx ts_ctx;
+
+/* Creates a context on HIP device `device` using `hip_stream` (a hipStream_t,
+ * may be NULL for the null stream).  *out receives the context. */
+int ts_create(ts_ctx** out, int device, void* hip_stream);
+
+/* Frees the context and its workspace.  NULL is accepted. */
+int ts_destroy(ts_ctx* ctx);
+
+/* Message of the last error on this context (never NULL). */
+const char* ts_last_error(const ts_ctx* ctx);
+
+/* Persistence diagram D(f) (Sec. 2.2): the pairs with v_birth != v_death and
+ * the essential class at (f(v_min), f(v_max)), in diagram order (Sec. 2.4):
+ * by rank of v_birth, then rank of v_death, dim, and the birth simplex's
+ * lexicographic key.
+ *   f:        n floats, device or host (on_device)
+ *   out:      host array of `capacity` records
+ *   n_out:    receives |D(f)|; TS_ERR_CAPACITY if it exceeds capacity */
+int ts_diagram(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+               ts_pair* out, int64_t capacity, int64_t* n_out);
+
+/* Topological simplification (Alg. 1 with Sec. 4.1 and 4.3).
+ *   f:  n floats (input, never modified), device or host (opt->inputs_on_device)
+ *   g:  n floats (output), same memory kind as f, must not overlap f
+ *   rep: receives the report
+ * Returns TS_OK when the stop rule held, TS_WARN_NOT_CANCELLED when j_max
+ * was reached first, or an error. */
+int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
+                const ts_options* opt, float* g, ts_report* rep);
+
+/* ---- stage entry points (for per-stage checks and profiling) ----------- */
+
+/* Vertex order: order[i] = i-th lowest vertex, rank[order[i]] = i.
+ * f, order, rank: n entries each, device or host (on_device). */
+int ts_order(ts_ctx* ctx, const float* f, int64_t n, int32_t on_device, int32_t* order,
+             int32_t* rank);
+
+/* Discrete gradient (Sec. 4.2) as dense partner arrays over canonical ids
+ * (host arrays): vup[v] = edge paired with vertex v, eup[e] = triangle paired
+ * with edge e, tup[t] = tetrahedron paired with triangle t; -1 when the cell
+ * is not paired with a coface, -2 when the id is not a cell of the grid.
+ * Sizes n, 7n, 12n. */
+int ts_gradient(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+                int32_t* vup, int32_t* eup, int32_t* tup);
+
+/* Critical cells sorted by (dim, lexicographic key): host arrays out_dim,
+ * out_id of `capacity` entries; counts[4] receives the per-dim counts. */
+int ts_critical(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+                int32_t* out_dim, int64_t* out_id, int64_t capacity, int64_t counts[4]);
+
+/* All pairs of the critical cells, including zero-persistence ones, plus the
+ * essential class, sorted by (dim, birth_cell, death_cell); host output. */
+int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+             ts_pair* out, int64_t capacity, int64_t* n_out);
+
+/* Per-kernel device time (ms) of the last ts_diagram / ts_simplify call,
+ * measured with HIP events on the context's stream: stage_ms[i] for the
+ * stage named stage_names[i] (NULL-terminated list).  Returns the count. */
+int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

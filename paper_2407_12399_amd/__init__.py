@@ -1,0 +1,291 @@
+"""Python binding of the topsimp C ABI (include/topsimp.h).
+
+Argument marshalling only: every step runs in libtopsimp.so (HIP kernels
+for gfx950 plus the host-side exact assignment).  PyTorch is used for device
+memory and the current HIP stream.  Importing this package does not load the
+library; the first call does, and raises if it is missing.
+
+Fields are float32 arrays of shape (Lz, Ly, Lx) (x fastest): a torch CUDA
+tensor (used in place on its device and current stream) or anything numpy
+accepts (copied through host memory).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtopsimp.so")
+
+PAIR_DTYPE = np.dtype([
+    ("dim", "<i4"), ("essential", "<i4"),
+    ("birth_cell", "<i8"), ("death_cell", "<i8"),
+    ("v_birth", "<i8"), ("v_death", "<i8"),
+    ("birth", "<f4"), ("death", "<f4"),
+])
+
+TS_OK, TS_WARN_NOT_CANCELLED = 0, 1
+ERRORS = {-1: "TS_ERR_ARG", -2: "TS_ERR_NONFINITE", -3: "TS_ERR_OOM", -4: "TS_ERR_HIP",
+          -5: "TS_ERR_CAPACITY", -6: "TS_ERR_INTERNAL"}
+
+
+class TopsimpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Signal(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("threshold_rel", ctypes.c_float),
+                ("nonsignal_dim_mask", ctypes.c_uint32), ("ties_signal", ctypes.c_int32),
+                ("signal", ctypes.c_void_p), ("n_signal", ctypes.c_int64)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("alpha_b", ctypes.c_float), ("alpha_d", ctypes.c_float),
+                ("j_max", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
+                ("cancel_tol_rel", ctypes.c_float), ("loss_ratio_s", ctypes.c_float),
+                ("inputs_on_device", ctypes.c_int32)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("cancelled", ctypes.c_int32),
+                ("loss0", ctypes.c_double), ("loss", ctypes.c_double),
+                ("energy", ctypes.c_double), ("linf", ctypes.c_double),
+                ("l2", ctypes.c_double), ("max_nonsignal_pers", ctypes.c_double),
+                ("max_signal_disp", ctypes.c_double), ("range", ctypes.c_double),
+                ("n_pairs", ctypes.c_int64 * 3), ("n_still", ctypes.c_int64),
+                ("n_reduced", ctypes.c_int64), ("n_targets", ctypes.c_int64),
+                ("total_s", ctypes.c_double), ("persistence_s", ctypes.c_double),
+                ("assign_s", ctypes.c_double), ("update_s", ctypes.c_double)]
+
+
+_lib = None
+_ctx = {}
+
+EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_simplify",
+           "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_stage_times"]
+
+
+def lib():
+    """Load libtopsimp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it first (__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.ts_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+        L.ts_destroy.argtypes = [P]
+        L.ts_last_error.argtypes = [P]
+        L.ts_last_error.restype = ctypes.c_char_p
+        L.ts_diagram.argtypes = [P, P, P, i32, P, i64, P]
+        L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
+        L.ts_order.argtypes = [P, P, i64, i32, P, P]
+        L.ts_gradient.argtypes = [P, P, P, i32, P, P, P]
+        L.ts_critical.argtypes = [P, P, P, i32, P, P, i64, P]
+        L.ts_pairs.argtypes = [P, P, P, i32, P, i64, P]
+        L.ts_stage_times.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_char_p)),
+                                     ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+        for fn in EXPORTS:
+            if fn != "ts_last_error":
+                getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def context(device=None):
+    """Context bound to (device, current torch stream)."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("topsimp needs a ROCm GPU (torch.cuda.is_available() is False)")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    if key not in _ctx:
+        h = ctypes.c_void_p()
+        rc = lib().ts_create(ctypes.byref(h), dev, ctypes.c_void_p(stream))
+        if rc != 0:
+            raise TopsimpError(rc, "ts_create failed")
+        _ctx[key] = h
+    return _ctx[key]
+
+
+def _check(ctx, rc, allow=(0,)):
+    if rc not in allow:
+        msg = lib().ts_last_error(ctx)
+        raise TopsimpError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _as_field(field):
+    """(pointer, dims, on_device, keepalive)"""
+    torch = _torch()
+    if isinstance(field, torch.Tensor):
+        if field.dtype != torch.float32 or field.dim() != 3:
+            raise ValueError("field must be a 3D float32 tensor (Lz, Ly, Lx)")
+        t = field.contiguous()
+        dims = np.array([t.shape[2], t.shape[1], t.shape[0]], np.int64)
+        if t.is_cuda:
+            return ctypes.c_void_p(t.data_ptr()), dims, 1, t
+        a = t.numpy()
+    else:
+        a = np.ascontiguousarray(field, dtype=np.float32)
+        if a.ndim != 3:
+            raise ValueError("field must have shape (Lz, Ly, Lx)")
+        dims = np.array([a.shape[2], a.shape[1], a.shape[0]], np.int64)
+    return a.ctypes.data_as(ctypes.c_void_p), dims, 0, a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pairs_call(fn, field):
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    cap = 4096
+    while True:
+        out = np.empty(cap, PAIR_DTYPE)
+        n = np.zeros(1, np.int64)
+        rc = fn(ctx, fp, _ptr(dims), on_dev, _ptr(out), cap, _ptr(n))
+        if rc == -5:
+            cap = int(n[0]) + 1
+            continue
+        _check(ctx, rc)
+        return out[: int(n[0])].copy()
+
+
+def diagram(field) -> np.ndarray:
+    """Persistence diagram D(f) in diagram order (structured array)."""
+    return _pairs_call(lib().ts_diagram, field)
+
+
+def pairs(field) -> np.ndarray:
+    """All pairs of critical cells incl. zero-persistence ones, plus the
+    essential class, sorted by (dim, birth_cell, death_cell)."""
+    return _pairs_call(lib().ts_pairs, field)
+
+
+def order(field):
+    """(order, rank) int32 arrays of the vertex order."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    n = int(np.prod(dims))
+    torch = _torch()
+    if on_dev:
+        o = torch.empty(n, dtype=torch.int32, device=keep.device)
+        r = torch.empty(n, dtype=torch.int32, device=keep.device)
+        _check(ctx, lib().ts_order(ctx, fp, n, 1, ctypes.c_void_p(o.data_ptr()),
+                                   ctypes.c_void_p(r.data_ptr())))
+        return o, r
+    o = np.empty(n, np.int32)
+    r = np.empty(n, np.int32)
+    _check(ctx, lib().ts_order(ctx, fp, n, 0, _ptr(o), _ptr(r)))
+    return o, r
+
+
+def gradient(field):
+    """Dense partner arrays (vup[n], eup[7n], tup[12n]) of the gradient."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    n = int(np.prod(dims))
+    vup = np.empty(n, np.int32)
+    eup = np.empty(7 * n, np.int32)
+    tup = np.empty(12 * n, np.int32)
+    _check(ctx, lib().ts_gradient(ctx, fp, _ptr(dims), on_dev, _ptr(vup), _ptr(eup), _ptr(tup)))
+    return vup, eup, tup
+
+
+def critical(field):
+    """Critical cell ids per dimension (4 int64 arrays), sorted by lex key."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    counts = np.zeros(4, np.int64)
+    cap = 4096
+    while True:
+        od = np.empty(cap, np.int32)
+        oi = np.empty(cap, np.int64)
+        rc = lib().ts_critical(ctx, fp, _ptr(dims), on_dev, _ptr(od), _ptr(oi), cap, _ptr(counts))
+        if rc == -5:
+            cap = int(counts.sum()) + 1
+            continue
+        _check(ctx, rc)
+        m = int(counts.sum())
+        od, oi = od[:m], oi[:m]
+        return [oi[od == d].copy() for d in range(4)]
+
+
+def stage_times():
+    """{stage name: device ms} of the last call on the current context."""
+    ctx = context()
+    names = ctypes.POINTER(ctypes.c_char_p)()
+    ms = ctypes.POINTER(ctypes.c_double)()
+    k = lib().ts_stage_times(ctx, ctypes.byref(names), ctypes.byref(ms))
+    return {names[i].decode(): ms[i] for i in range(max(k, 0))}
+
+
+@dataclass
+class Report:
+    iterations: int
+    cancelled: int
+    loss0: float
+    loss: float
+    energy: float
+    linf: float
+    l2: float
+    max_nonsignal_pers: float
+    max_signal_disp: float
+    range: float
+    n_pairs: tuple
+    n_still: int
+    n_reduced: int
+    n_targets: int
+    total_s: float
+    persistence_s: float
+    assign_s: float
+    update_s: float
+    status: int
+
+
+def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
+             alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
+             signal_pairs=None, out=None):
+    """Topological simplification; returns (g, Report).  g has the kind of
+    the input (torch CUDA tensor in, torch CUDA tensor out)."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    sig = _Signal()
+    if signal_pairs is not None:
+        sp = np.ascontiguousarray(signal_pairs, dtype=PAIR_DTYPE)
+        sig.mode, sig.signal, sig.n_signal = 1, sp.ctypes.data, len(sp)
+    else:
+        sig.mode = 0
+        sig.threshold_rel = threshold
+        sig.nonsignal_dim_mask = sum(1 << d for d in nonsignal_dims)
+        sig.ties_signal = ties_signal
+    opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev)
+    rep = _Report()
+    torch = _torch()
+    if on_dev:
+        g = out if out is not None else torch.empty_like(keep)
+        gp = ctypes.c_void_p(g.data_ptr())
+    else:
+        g = np.empty_like(keep)
+        gp = _ptr(g)
+    rc = lib().ts_simplify(ctx, fp, _ptr(dims), ctypes.byref(sig), ctypes.byref(opt), gp,
+                           ctypes.byref(rep))
+    _check(ctx, rc, allow=(0, 1))
+    r = Report(rep.iterations, rep.cancelled, rep.loss0, rep.loss, rep.energy, rep.linf, rep.l2,
+               rep.max_nonsignal_pers, rep.max_signal_disp, rep.range, tuple(rep.n_pairs),
+               rep.n_still, rep.n_reduced, rep.n_targets, rep.total_s, rep.persistence_s,
+               rep.assign_s, rep.update_s, rc)
+    return g, r

@@ -1,0 +1,373 @@
+// api.cpp -- C ABI of the topsimp library (context, workspace, stage calls).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "persistence.h"
+#include "solver.h"
+
+namespace ts {
+
+void* Workspace::get(const std::string& name, size_t bytes) {
+  Buf& b = bufs[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) {
+    // previous users on the stream must be done before the memory is reused
+    TS_HIP(hipDeviceSynchronize());
+    TS_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  want = (want + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    throw Error(TS_ERR_OOM, "hipMalloc(" + std::to_string(want) + ") for " + name + ": " +
+                                hipGetErrorString(e));
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+void Workspace::release() {
+  for (auto& kv : bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  bufs.clear();
+}
+
+size_t Workspace::total_bytes() const {
+  size_t s = 0;
+  for (const auto& kv : bufs) s += kv.second.bytes;
+  return s;
+}
+
+void Timer::reset() {
+  for (auto& e : begin) (void)hipEventDestroy(e);
+  for (auto& e : end) (void)hipEventDestroy(e);
+  begin.clear();
+  end.clear();
+  names.clear();
+  open.clear();
+}
+
+void Timer::start(const std::string& name) {
+  if (!enabled) return;
+  hipEvent_t a, b;
+  TS_HIP(hipEventCreate(&a));
+  TS_HIP(hipEventCreate(&b));
+  TS_HIP(hipEventRecord(a, stream));
+  begin.push_back(a);
+  end.push_back(b);
+  names.push_back(name);
+  open.push_back(name);
+}
+
+void Timer::stop() {
+  if (!enabled || open.empty()) return;
+  TS_HIP(hipEventRecord(end.back(), stream));
+  open.pop_back();
+}
+
+void Timer::collect(std::vector<std::string>* names_out, std::vector<double>* ms_out) {
+  names_out->clear();
+  ms_out->clear();
+  if (begin.empty()) return;
+  TS_HIP(hipStreamSynchronize(stream));
+  for (size_t i = 0; i < begin.size(); ++i) {
+    float ms = 0.f;
+    TS_HIP(hipEventElapsedTime(&ms, begin[i], end[i]));
+    auto it = std::find(names_out->begin(), names_out->end(), names[i]);
+    if (it == names_out->end()) {
+      names_out->push_back(names[i]);
+      ms_out->push_back(ms);
+    } else {
+      (*ms_out)[it - names_out->begin()] += ms;
+    }
+  }
+}
+
+void Timer::destroy() { reset(); }
+
+Grid make_grid(const int64_t dims[3]) {
+  if (!dims) throw Error(TS_ERR_ARG, "dims is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (dims[i] < 2) throw Error(TS_ERR_ARG, "every dimension must be >= 2");
+  const int64_t n = dims[0] * dims[1] * dims[2];
+  if (dims[0] > (1 << 25) || dims[1] > (1 << 25) || dims[2] > (1 << 25) || n > (int64_t(1) << 25))
+    throw Error(TS_ERR_ARG, "grid larger than 2^25 vertices");
+  Grid g;
+  g.Lx = int(dims[0]);
+  g.Ly = int(dims[1]);
+  g.Lz = int(dims[2]);
+  g.n = int(n);
+  return g;
+}
+
+// Device copy of the field (or the caller's device pointer).
+const float* device_field(ts_ctx* ctx, const float* f, int64_t n, int on_device) {
+  if (!f) throw Error(TS_ERR_ARG, "field pointer is NULL");
+  if (on_device) return f;
+  float* d = ctx->ws.get<float>("api.field", n);
+  TS_HIP(hipMemcpyAsync(d, f, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  return d;
+}
+
+void finish_timing(ts_ctx* ctx) {
+  ctx->timer.collect(&ctx->stage_names_store, &ctx->stage_ms);
+  ctx->stage_names.clear();
+  for (const auto& s : ctx->stage_names_store) ctx->stage_names.push_back(s.c_str());
+  ctx->stage_names.push_back(nullptr);
+}
+
+// Host records of the pairs (all, or the diagram subset in diagram order).
+void pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev, bool diagram_only,
+                   std::vector<ts_pair>* out) {
+  hipStream_t s = ctx->stream;
+  const int64_t np = R.npairs;
+  std::vector<int32_t> dim(np), birth(np), death(np), order(R.g.n);
+  std::vector<uint64_t> bkey(np), dkey(np);
+  std::vector<float> f(R.g.n);
+  TS_HIP(hipMemcpyAsync(dim.data(), R.pdim, np * 4, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(birth.data(), R.pbirth, np * 4, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(death.data(), R.pdeath, np * 4, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(bkey.data(), R.pbkey, np * 8, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(dkey.data(), R.pdkey, np * 8, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(order.data(), R.order, size_t(R.g.n) * 4, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipMemcpyAsync(f.data(), f_dev, size_t(R.g.n) * 4, hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> diag;
+  if (diagram_only) {
+    diag.resize(R.ndiag);
+    if (R.ndiag)
+      TS_HIP(hipMemcpyAsync(diag.data(), R.diag, R.ndiag * 4, hipMemcpyDeviceToHost, s));
+  }
+  TS_HIP(hipStreamSynchronize(s));
+  auto rec = [&](int64_t i) {
+    ts_pair p;
+    p.dim = dim[i];
+    p.essential = death[i] < 0 ? 1 : 0;
+    p.birth_cell = birth[i];
+    p.death_cell = death[i];
+    p.v_birth = order[bkey[i] >> 12];
+    p.v_death = order[dkey[i] >> 12];
+    p.birth = f[p.v_birth];
+    p.death = f[p.v_death];
+    return p;
+  };
+  out->clear();
+  if (diagram_only) {
+    for (uint32_t i : diag) out->push_back(rec(i));
+  } else {
+    for (int64_t i = 0; i < np; ++i) out->push_back(rec(i));
+    std::sort(out->begin(), out->end(), [](const ts_pair& a, const ts_pair& b) {
+      if (a.dim != b.dim) return a.dim < b.dim;
+      if (a.birth_cell != b.birth_cell) return a.birth_cell < b.birth_cell;
+      return a.death_cell < b.death_cell;
+    });
+  }
+}
+
+template <class F>
+int guarded(ts_ctx* ctx, F&& fn) {
+  if (!ctx) return TS_ERR_ARG;
+  try {
+    TS_HIP(hipSetDevice(ctx->device));
+    ctx->err.clear();
+    return fn();
+  } catch (const Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return TS_ERR_OOM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return TS_ERR_INTERNAL;
+  }
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" {
+
+int ts_create(ts_ctx** out, int device, void* hip_stream) {
+  if (!out) return TS_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return TS_ERR_HIP;
+  if (device < 0 || device >= count) return TS_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return TS_ERR_HIP;
+  ts_ctx* c = new (std::nothrow) ts_ctx;
+  if (!c) return TS_ERR_OOM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->timer.stream = c->stream;
+  *out = c;
+  return TS_OK;
+}
+
+int ts_destroy(ts_ctx* ctx) {
+  if (!ctx) return TS_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->timer.destroy();
+  ctx->ws.release();
+  delete ctx;
+  return TS_OK;
+}
+
+const char* ts_last_error(const ts_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+int ts_order(ts_ctx* ctx, const float* f, int64_t n, int32_t on_device, int32_t* order,
+             int32_t* rank) {
+  return guarded(ctx, [&]() {
+    if (!order || !rank || n < 1 || n > (int64_t(1) << 25))
+      throw Error(TS_ERR_ARG, "bad arguments");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, n, on_device);
+    int32_t* od = on_device ? order : ctx->ws.get<int32_t>("api.order", n);
+    int32_t* rd = on_device ? rank : ctx->ws.get<int32_t>("api.rank", n);
+    compute_order(ctx, fd, int(n), od, rd);
+    if (!on_device) {
+      TS_HIP(hipMemcpyAsync(order, od, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+      TS_HIP(hipMemcpyAsync(rank, rd, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    TS_HIP(hipStreamSynchronize(ctx->stream));
+    finish_timing(ctx);
+    return TS_OK;
+  });
+}
+
+int ts_gradient(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+                int32_t* vup, int32_t* eup, int32_t* tup) {
+  return guarded(ctx, [&]() {
+    const Grid g = make_grid(dims);
+    if (!vup || !eup || !tup) throw Error(TS_ERR_ARG, "null output");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, g.n, on_device);
+    PersistenceResult R;
+    compute_persistence(ctx, fd, g, &R);
+    int32_t* v = ctx->ws.get<int32_t>("api.vup", g.n);
+    int32_t* e = ctx->ws.get<int32_t>("api.eup", 7 * int64_t(g.n));
+    int32_t* t = ctx->ws.get<int32_t>("api.tup", 12 * int64_t(g.n));
+    decode_gradient(ctx, R, v, e, t);
+    TS_HIP(hipMemcpyAsync(vup, v, size_t(g.n) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    TS_HIP(hipMemcpyAsync(eup, e, size_t(g.n) * 28, hipMemcpyDeviceToHost, ctx->stream));
+    TS_HIP(hipMemcpyAsync(tup, t, size_t(g.n) * 48, hipMemcpyDeviceToHost, ctx->stream));
+    TS_HIP(hipStreamSynchronize(ctx->stream));
+    finish_timing(ctx);
+    return TS_OK;
+  });
+}
+
+int ts_critical(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+                int32_t* out_dim, int64_t* out_id, int64_t capacity, int64_t counts[4]) {
+  return guarded(ctx, [&]() {
+    const Grid g = make_grid(dims);
+    if (!counts) throw Error(TS_ERR_ARG, "counts is NULL");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, g.n, on_device);
+    PersistenceResult R;
+    compute_persistence(ctx, fd, g, &R);
+    int64_t total = 0;
+    for (int d = 0; d < 4; ++d) {
+      counts[d] = R.ncrit[d];
+      total += R.ncrit[d];
+    }
+    finish_timing(ctx);
+    if (total > capacity) {
+      ctx->err = "capacity too small";
+      return int(TS_ERR_CAPACITY);
+    }
+    if (!out_dim || !out_id) throw Error(TS_ERR_ARG, "null output");
+    int64_t k = 0;
+    for (int d = 0; d < 4; ++d) {
+      std::vector<int32_t> ids(R.ncrit[d]);
+      if (R.ncrit[d])
+        TS_HIP(hipMemcpy(ids.data(), R.cid[d], R.ncrit[d] * 4, hipMemcpyDeviceToHost));
+      for (int32_t id : ids) {
+        out_dim[k] = d;
+        out_id[k++] = id;
+      }
+    }
+    return int(TS_OK);
+  });
+}
+
+int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+             ts_pair* out, int64_t capacity, int64_t* n_out) {
+  return guarded(ctx, [&]() {
+    const Grid g = make_grid(dims);
+    if (!n_out) throw Error(TS_ERR_ARG, "n_out is NULL");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, g.n, on_device);
+    PersistenceResult R;
+    compute_persistence(ctx, fd, g, &R);
+    std::vector<ts_pair> P;
+    pairs_to_host(ctx, R, fd, false, &P);
+    finish_timing(ctx);
+    *n_out = int64_t(P.size());
+    if (int64_t(P.size()) > capacity) {
+      ctx->err = "capacity too small";
+      return int(TS_ERR_CAPACITY);
+    }
+    if (!out && !P.empty()) throw Error(TS_ERR_ARG, "out is NULL");
+    std::copy(P.begin(), P.end(), out);
+    return int(TS_OK);
+  });
+}
+
+int ts_diagram(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
+               ts_pair* out, int64_t capacity, int64_t* n_out) {
+  return guarded(ctx, [&]() {
+    const Grid g = make_grid(dims);
+    if (!n_out) throw Error(TS_ERR_ARG, "n_out is NULL");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, g.n, on_device);
+    PersistenceResult R;
+    compute_persistence(ctx, fd, g, &R);
+    std::vector<ts_pair> P;
+    pairs_to_host(ctx, R, fd, true, &P);
+    finish_timing(ctx);
+    *n_out = int64_t(P.size());
+    if (int64_t(P.size()) > capacity) {
+      ctx->err = "capacity too small";
+      return int(TS_ERR_CAPACITY);
+    }
+    if (!out && !P.empty()) throw Error(TS_ERR_ARG, "out is NULL");
+    std::copy(P.begin(), P.end(), out);
+    return int(TS_OK);
+  });
+}
+
+int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
+                const ts_options* opt, float* g, ts_report* rep) {
+  return guarded(ctx, [&]() {
+    const Grid grid = make_grid(dims);
+    if (!sig || !opt || !g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
+    if (f == g) throw Error(TS_ERR_ARG, "g must not alias f");
+    if (opt->j_max < 0 || opt->stop_mode < 0 || opt->stop_mode > 1)
+      throw Error(TS_ERR_ARG, "bad options");
+    if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
+    if (sig->mode == 1 && sig->n_signal > 0 && !sig->signal)
+      throw Error(TS_ERR_ARG, "signal list is NULL");
+    ctx->timer.reset();
+    const int rc = simplify(ctx, f, grid, *sig, *opt, g, rep);
+    finish_timing(ctx);
+    return rc;
+  });
+}
+
+int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** ms) {
+  if (!ctx || !names || !ms) return TS_ERR_ARG;
+  *names = ctx->stage_names.empty() ? nullptr : ctx->stage_names.data();
+  *ms = ctx->stage_ms.data();
+  return int(ctx->stage_ms.size());
+}
+
+}  // extern "C"

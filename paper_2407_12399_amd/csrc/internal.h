@@ -1,0 +1,88 @@
+// internal.h -- shared host-side declarations of the topsimp library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/topsimp.h"
+
+namespace ts {
+
+// Error carrying a TS_* status code.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TS_HIP(call)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw ::ts::Error(e_ == hipErrorOutOfMemory ? TS_ERR_OOM : TS_ERR_HIP,    \
+                        std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// Device workspace: named grow-only buffers owned by the context.
+struct Workspace {
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  void* get(const std::string& name, size_t bytes);
+  template <class T>
+  T* get(const std::string& name, size_t count) {
+    return static_cast<T*>(get(name, count * sizeof(T) + 16));
+  }
+  void release();
+  size_t total_bytes() const;
+};
+
+// Per-stage device timing with HIP events on the context stream.
+struct Timer {
+  hipStream_t stream = nullptr;
+  bool enabled = true;
+  std::vector<std::string> names;
+  std::vector<hipEvent_t> begin, end;
+  std::vector<std::string> open;
+  void reset();
+  void start(const std::string& name);
+  void stop();
+  // Accumulated ms per stage name (in first-seen order).
+  void collect(std::vector<std::string>* names_out, std::vector<double>* ms_out);
+  void destroy();
+};
+
+struct Grid {
+  int Lx, Ly, Lz;
+  int n;
+};
+
+// Sorting and scanning primitives (sort.hip).
+void scan_exclusive_u32(Workspace& ws, const uint32_t* in, uint32_t* out, size_t n,
+                        hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
+// The result is left in keys/vals; tmp buffers are taken from the workspace.
+void radix_sort_u64(Workspace& ws, uint64_t* keys, uint32_t* vals, size_t n, int begin_bit,
+                    int end_bit, hipStream_t s);
+void radix_sort_u32(Workspace& ws, uint32_t* keys, uint32_t* vals, size_t n, int begin_bit,
+                    int end_bit, hipStream_t s);
+
+}  // namespace ts
+
+struct ts_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  ts::Workspace ws;
+  ts::Timer timer;
+  std::vector<std::string> stage_names_store;
+  std::vector<const char*> stage_names;
+  std::vector<double> stage_ms;
+};

@@ -1,0 +1,48 @@
+// persistence.h -- device-resident persistence map of a field on the
+// Freudenthal triangulation (host-side interface of persistence.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace ts {
+
+// Everything the persistence map leaves on the device.  Pointers live in the
+// context workspace and stay valid until the next call that reuses it.
+struct PersistenceResult {
+  Grid g{};
+  // vertex order (Sec. 2.2)
+  int32_t* order = nullptr;  // [n]
+  int32_t* rank = nullptr;   // [n]
+  // lower-star gradient (Sec. 4.2): per-vertex pairing code and the vertex
+  // reached by the descending gradient step (itself for a minimum)
+  uint4* code = nullptr;     // [n]
+  int32_t* down = nullptr;   // [n]
+  // critical cells per dim, sorted by lexicographic key
+  int64_t ncrit[4] = {0, 0, 0, 0};
+  uint64_t* ckey[4] = {};    // key = rank(highest vertex) << 12 | local key
+  int32_t* cid[4] = {};      // canonical ids
+  // persistence pairs of critical cells (+ the essential class, last)
+  int64_t npairs = 0;
+  int32_t* pdim = nullptr;
+  int32_t* pbirth = nullptr;  // canonical id
+  int32_t* pdeath = nullptr;  // canonical id, -1 for the essential class
+  uint64_t* pbkey = nullptr;  // lexicographic key of the birth cell
+  uint64_t* pdkey = nullptr;  // of the death cell (n-1 << 12 for the essential)
+  // diagram: pair indices in diagram order, v_birth != v_death or essential
+  int64_t ndiag = 0;
+  uint32_t* diag = nullptr;
+  // round counts of the iterative stages (diagnostics)
+  int rounds_d0 = 0, rounds_d2 = 0, rounds_d1 = 0;
+};
+
+// Vertex order only (K1 + K2).
+void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* rank);
+
+// The whole persistence map (K1..K8) of a device field.
+void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R);
+
+// Dense gradient partner arrays (device outputs of sizes n, 7n, 12n).
+void decode_gradient(ts_ctx* ctx, const PersistenceResult& R, int32_t* vup, int32_t* eup,
+                     int32_t* tup);
+
+}  // namespace ts

@@ -1,0 +1,1680 @@
+// persistence.hip -- the persistence map on gfx950 (Sec. 2.2 and 4.2).
+//
+//   K1/K2  vertex order: monotone 32-bit keys of (value), stable LSD radix
+//          sort of (key, id) pairs, rank scatter.
+//   K3     lower-star discrete gradient: one lane per vertex.  The cells of
+//          the lower star are generated directly in lexicographic order
+//          (grouped by their highest other vertex), so that both priority
+//          queues of the lower-star algorithm become 128-bit masks over
+//          sorted slots and "pop min" is a find-first-set.  Per vertex the
+//          lane writes a 16-byte pairing code, its descending neighbour and
+//          its critical cells with their lexicographic keys.
+//   K4     critical cells: block-aggregated compaction inside K3, then a
+//          radix sort per dimension by key.
+//   K5     min-saddle pairs: critical edges join the minima their descending
+//          paths reach; union-find over minima processed in rounds where
+//          every component hooks to its lowest outgoing edge and the edges
+//          that are the lowest outgoing edge of both their components merge
+//          (those merges are exactly the next Kruskal steps, so the elder
+//          rule applies to them as in the sequential sweep).
+//   K6     saddle-max pairs: the same on the dual graph (tetrahedra and the
+//          outside of the box) in decreasing order.
+//   K7     saddle-saddle pairs: Morse boundaries of the remaining critical
+//          triangles by mod-2 expansion along gradient paths, then a
+//          parallel Z2 reduction (every column whose pivot is not its own
+//          adds the column of the lowest owner of that pivot, in rounds).
+//   K8     diagram: v_birth != v_death filter, diagram-order sort.
+#include <algorithm>
+#include <array>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "persistence.h"
+
+namespace ts {
+namespace {
+
+// ======================================================================
+// Star tables of a vertex in the Freudenthal triangulation
+// ======================================================================
+
+struct StarTables {
+  int8_t nb[14][3];          // neighbour offsets: k<7: +corner(k+1), k>=7: -corner(k-6)
+  uint16_t tri_nbm[36];      // the two neighbours of star triangle t (14-bit mask)
+  uint8_t tri_nb[36][2];
+  uint16_t tet_nbm[24];      // the three neighbours of star tet q
+  uint8_t tet_nb[24][3];
+  uint64_t tet_trim[24];     // its three facets through the centre (36-bit mask)
+  uint8_t tri_tet[36][2];    // the two star tets containing t
+  uint64_t edge_trim[14];    // star triangles containing neighbour k
+  uint32_t tri_tetm[36];     // star tets containing t (24-bit mask)
+  uint8_t pair_tri[14][14];  // star triangle on neighbours (a,b), 255 if none
+  int8_t tri_anc[36][3];     // anchor (lowest vertex) offset of the canonical cell
+  uint8_t tri_type[36];
+  int8_t tet_anc[24][3];
+  uint8_t tet_type[24];
+  uint8_t tri_local[12][3];  // canonical triangle type, chain position -> star index
+  uint8_t tet_local[6][4];   // canonical tet type, chain position -> star index
+  uint8_t tri_chain[12][3];  // corner masks of the canonical chains
+  uint16_t negx, posx, negy, posy, negz, posz;  // neighbours leaving the box side
+};
+
+__constant__ StarTables c_st;
+
+// Canonical Kuhn chains (corner masks, bit0 = x, bit1 = y, bit2 = z).
+const int kTriChains[12][3] = {{0, 1, 3}, {0, 2, 3}, {0, 1, 5}, {0, 4, 5},
+                               {0, 2, 6}, {0, 4, 6}, {0, 1, 7}, {0, 2, 7},
+                               {0, 3, 7}, {0, 4, 7}, {0, 5, 7}, {0, 6, 7}};
+const int kTetChains[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7},
+                              {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+
+struct V3 {
+  int x, y, z;
+};
+V3 corner3(int m) { return {m & 1, (m >> 1) & 1, (m >> 2) & 1}; }
+
+int nb_of_offset(V3 d) {
+  const bool pos = d.x >= 0 && d.y >= 0 && d.z >= 0;
+  const bool neg = d.x <= 0 && d.y <= 0 && d.z <= 0;
+  if (pos) {
+    const int m = d.x | (d.y << 1) | (d.z << 2);
+    return m == 0 ? -1 : m - 1;
+  }
+  if (neg) {
+    const int m = (-d.x) | ((-d.y) << 1) | ((-d.z) << 2);
+    return 7 + m - 1;
+  }
+  return -1;
+}
+
+// If the offsets (relative to the centre, which is included as (0,0,0)) form
+// a Kuhn simplex, returns its anchor offset, canonical type and the corner
+// masks of the points relative to the anchor.
+bool kuhn_cell(const std::vector<V3>& pts, V3* anc, int* type) {
+  V3 a = pts[0];
+  for (const V3& p : pts) {
+    a.x = std::min(a.x, p.x);
+    a.y = std::min(a.y, p.y);
+    a.z = std::min(a.z, p.z);
+  }
+  std::vector<int> masks;
+  for (const V3& p : pts) {
+    const int dx = p.x - a.x, dy = p.y - a.y, dz = p.z - a.z;
+    if (dx > 1 || dy > 1 || dz > 1) return false;
+    masks.push_back(dx | (dy << 1) | (dz << 2));
+  }
+  std::sort(masks.begin(), masks.end(),
+            [](int u, int v) { return __builtin_popcount(u) < __builtin_popcount(v); });
+  if (masks[0] != 0) return false;
+  for (size_t i = 1; i < masks.size(); ++i)
+    if ((masks[i - 1] & masks[i]) != masks[i - 1] || masks[i - 1] == masks[i]) return false;
+  *anc = a;
+  const int dim = int(pts.size()) - 1;
+  if (dim == 2) {
+    for (int t = 0; t < 12; ++t)
+      if (kTriChains[t][1] == masks[1] && kTriChains[t][2] == masks[2]) {
+        *type = t;
+        return true;
+      }
+    return false;
+  }
+  for (int t = 0; t < 6; ++t)
+    if (kTetChains[t][1] == masks[1] && kTetChains[t][2] == masks[2] && masks[3] == 7) {
+      *type = t;
+      return true;
+    }
+  return false;
+}
+
+StarTables build_tables() {
+  StarTables T;
+  std::memset(&T, 0, sizeof(T));
+  std::memset(T.pair_tri, 255, sizeof(T.pair_tri));
+  std::memset(T.tri_tet, 255, sizeof(T.tri_tet));
+  V3 nb[14];
+  for (int k = 0; k < 14; ++k) {
+    V3 c = corner3(k % 7 + 1);
+    if (k >= 7) c = {-c.x, -c.y, -c.z};
+    nb[k] = c;
+    T.nb[k][0] = int8_t(c.x);
+    T.nb[k][1] = int8_t(c.y);
+    T.nb[k][2] = int8_t(c.z);
+    if (c.x < 0) T.negx |= 1u << k;
+    if (c.x > 0) T.posx |= 1u << k;
+    if (c.y < 0) T.negy |= 1u << k;
+    if (c.y > 0) T.posy |= 1u << k;
+    if (c.z < 0) T.negz |= 1u << k;
+    if (c.z > 0) T.posz |= 1u << k;
+  }
+  int nt = 0;
+  for (int a = 0; a < 14; ++a)
+    for (int b = a + 1; b < 14; ++b) {
+      V3 anc;
+      int type;
+      if (!kuhn_cell({{0, 0, 0}, nb[a], nb[b]}, &anc, &type)) continue;
+      if (nt >= 36) throw Error(TS_ERR_INTERNAL, "star tables: too many triangles");
+      T.tri_nb[nt][0] = uint8_t(a);
+      T.tri_nb[nt][1] = uint8_t(b);
+      T.tri_nbm[nt] = uint16_t((1u << a) | (1u << b));
+      T.pair_tri[a][b] = T.pair_tri[b][a] = uint8_t(nt);
+      T.tri_anc[nt][0] = int8_t(anc.x);
+      T.tri_anc[nt][1] = int8_t(anc.y);
+      T.tri_anc[nt][2] = int8_t(anc.z);
+      T.tri_type[nt] = uint8_t(type);
+      T.edge_trim[a] |= 1ull << nt;
+      T.edge_trim[b] |= 1ull << nt;
+      ++nt;
+    }
+  int nq = 0;
+  for (int a = 0; a < 14; ++a)
+    for (int b = a + 1; b < 14; ++b)
+      for (int c = b + 1; c < 14; ++c) {
+        V3 anc;
+        int type;
+        if (!kuhn_cell({{0, 0, 0}, nb[a], nb[b], nb[c]}, &anc, &type)) continue;
+        if (nq >= 24) throw Error(TS_ERR_INTERNAL, "star tables: too many tets");
+        T.tet_nb[nq][0] = uint8_t(a);
+        T.tet_nb[nq][1] = uint8_t(b);
+        T.tet_nb[nq][2] = uint8_t(c);
+        T.tet_nbm[nq] = uint16_t((1u << a) | (1u << b) | (1u << c));
+        T.tet_anc[nq][0] = int8_t(anc.x);
+        T.tet_anc[nq][1] = int8_t(anc.y);
+        T.tet_anc[nq][2] = int8_t(anc.z);
+        T.tet_type[nq] = uint8_t(type);
+        const int tris[3] = {T.pair_tri[a][b], T.pair_tri[a][c], T.pair_tri[b][c]};
+        for (int i = 0; i < 3; ++i) {
+          const int t = tris[i];
+          if (t == 255) throw Error(TS_ERR_INTERNAL, "star tables: tet facet missing");
+          T.tet_trim[nq] |= 1ull << t;
+          T.tri_tetm[t] |= 1u << nq;
+          if (T.tri_tet[t][0] == 255) T.tri_tet[t][0] = uint8_t(nq);
+          else T.tri_tet[t][1] = uint8_t(nq);
+        }
+        ++nq;
+      }
+  if (nt != 36 || nq != 24) throw Error(TS_ERR_INTERNAL, "star tables: wrong star size");
+  for (int t = 0; t < 36; ++t)
+    if (T.tri_tet[t][1] == 255) throw Error(TS_ERR_INTERNAL, "star tables: open triangle");
+  for (int k = 0; k < 14; ++k)  // edge codes 0..5 name one of at most 6 triangles
+    if (__builtin_popcountll(T.edge_trim[k]) > 6)
+      throw Error(TS_ERR_INTERNAL, "star tables: edge of degree > 6");
+  // canonical cell -> star index at each of its vertices
+  for (int type = 0; type < 12; ++type) {
+    for (int k = 0; k < 3; ++k) T.tri_chain[type][k] = uint8_t(kTriChains[type][k]);
+    for (int p = 0; p < 3; ++p) {
+      const V3 c = corner3(kTriChains[type][p]);
+      int ks[2], m = 0;
+      for (int q = 0; q < 3; ++q)
+        if (q != p) {
+          const V3 o = corner3(kTriChains[type][q]);
+          ks[m++] = nb_of_offset({o.x - c.x, o.y - c.y, o.z - c.z});
+        }
+      const int t = T.pair_tri[ks[0]][ks[1]];
+      if (t == 255) throw Error(TS_ERR_INTERNAL, "star tables: triangle inverse");
+      T.tri_local[type][p] = uint8_t(t);
+    }
+  }
+  for (int type = 0; type < 6; ++type)
+    for (int p = 0; p < 4; ++p) {
+      const V3 c = corner3(kTetChains[type][p]);
+      uint32_t m = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != p) {
+          const V3 o = corner3(kTetChains[type][q]);
+          m |= 1u << nb_of_offset({o.x - c.x, o.y - c.y, o.z - c.z});
+        }
+      int found = -1;
+      for (int l = 0; l < 24; ++l)
+        if (T.tet_nbm[l] == m) found = l;
+      if (found < 0) throw Error(TS_ERR_INTERNAL, "star tables: tet inverse");
+      T.tet_local[type][p] = uint8_t(found);
+    }
+  return T;
+}
+
+void upload_tables(int device) {
+  static bool done[64] = {false};
+  if (device >= 0 && device < 64 && done[device]) return;
+  static const StarTables T = build_tables();
+  TS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_st), &T, sizeof(T)));
+  if (device >= 0 && device < 64) done[device] = true;
+}
+
+// ======================================================================
+// Device helpers
+// ======================================================================
+
+struct NbOff {
+  int o[14];
+};
+
+NbOff make_offsets(const Grid& g) {
+  NbOff r;
+  for (int k = 0; k < 14; ++k) {
+    V3 c = corner3(k % 7 + 1);
+    if (k >= 7) c = {-c.x, -c.y, -c.z};
+    r.o[k] = c.x + g.Lx * (c.y + g.Ly * c.z);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void coords(const Grid& g, int v, int* x, int* y, int* z) {
+  const int t = v / g.Lx;
+  *x = v - t * g.Lx;
+  *y = t % g.Ly;
+  *z = t / g.Ly;
+}
+
+__device__ __forceinline__ uint32_t valid_nbs(const Grid& g, int x, int y, int z) {
+  uint32_t m = 0x3FFFu;
+  if (x == 0) m &= ~uint32_t(c_st.negx);
+  if (x == g.Lx - 1) m &= ~uint32_t(c_st.posx);
+  if (y == 0) m &= ~uint32_t(c_st.negy);
+  if (y == g.Ly - 1) m &= ~uint32_t(c_st.posy);
+  if (z == 0) m &= ~uint32_t(c_st.negz);
+  if (z == g.Lz - 1) m &= ~uint32_t(c_st.posz);
+  return m;
+}
+
+__device__ __forceinline__ int lin(const Grid& g, int dx, int dy, int dz) {
+  return dx + g.Lx * (dy + g.Ly * dz);
+}
+
+__device__ __forceinline__ uint32_t nib(uint64_t packed, int i) {
+  return uint32_t(packed >> (4 * i)) & 15u;
+}
+
+// code layout: w0,w1[0:10) = 14 edge codes of 3 bits; w1[10:18) = triangle
+// codes 32..35; w2,w3 = triangle codes 0..31 (2 bits each).
+//   edge code: 0..5 paired with the j-th star triangle containing the edge,
+//              6 critical, 7 paired with the centre vertex
+//   triangle code: 0 paired with a facet (or not in the lower star),
+//              1 critical, 2/3 paired with tri_tet[t][0/1]
+__device__ __forceinline__ uint32_t edge_code(const uint4& c, int k) {
+  const uint64_t e = uint64_t(c.x) | (uint64_t(c.y & 0x3FFu) << 32);
+  return uint32_t(e >> (3 * k)) & 7u;
+}
+__device__ __forceinline__ uint32_t tri_code(const uint4& c, int t) {
+  if (t < 32) {
+    const uint64_t e = uint64_t(c.z) | (uint64_t(c.w) << 32);
+    return uint32_t(e >> (2 * t)) & 3u;
+  }
+  return (c.y >> (10 + 2 * (t - 32))) & 3u;
+}
+
+__device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+__device__ __forceinline__ int ffs32(uint32_t m) { return __ffs(m) - 1; }
+
+// ======================================================================
+// K1 / K2: vertex order
+// ======================================================================
+
+__global__ void k_order_keys(const float* __restrict__ f, int n, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t b = __float_as_uint(f[i]);
+  if ((b & 0x7F800000u) == 0x7F800000u) atomicOr(bad, 1);  // NaN or Inf
+  if ((b & 0x7FFFFFFFu) == 0u) b = 0u;                     // -0 -> +0
+  keys[i] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  vals[i] = uint32_t(i);
+}
+
+__global__ void k_rank_scatter(const uint32_t* __restrict__ order, int n, int32_t* __restrict__ rank,
+                               int32_t* __restrict__ order_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t v = order[i];
+  rank[v] = i;
+  if (order_out) order_out[i] = int32_t(v);
+}
+
+// ======================================================================
+// K3: lower-star gradient
+// ======================================================================
+
+struct CritOut {
+  uint64_t* key[4];
+  int32_t* id[4];
+  unsigned long long* count;  // [4]
+  int64_t cap[4];
+};
+
+constexpr int kGradThreads = 256;
+constexpr int kSlotBytes = 80;  // >= 74 lower-star cells (excluding the centre)
+constexpr int kCellBytes = 74;  // 14 edges, 36 triangles, 24 tets
+
+__global__ void __launch_bounds__(kGradThreads)
+k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restrict__ code_out,
+           int32_t* __restrict__ down_out, CritOut co) {
+  __shared__ uint8_t s_slot_cell[kSlotBytes * kGradThreads];
+  __shared__ uint8_t s_cell_slot[kCellBytes * kGradThreads];
+  __shared__ unsigned int s_cnt[4];
+  __shared__ unsigned long long s_base[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  uint8_t* slot_cell = s_slot_cell + tid;  // element i at [i * kGradThreads]
+  uint8_t* cell_slot = s_cell_slot + tid;
+#define SLOT_CELL(i) slot_cell[(i) * kGradThreads]
+#define CELL_SLOT(i) cell_slot[(i) * kGradThreads]
+
+  const int v = blockIdx.x * kGradThreads + tid;
+  const bool active = v < g.n;
+  int rx = 0;
+  uint32_t low = 0;
+  uint64_t pos = 0;  // nibble k: position of neighbour k among lower neighbours
+  uint32_t critE = 0, critQ = 0;
+  uint64_t critT = 0;
+  uint64_t ecode = 0;          // 3 bits per neighbour
+  uint64_t tcode0 = 0;         // 2 bits per triangle 0..31
+  uint32_t tcode1 = 0;         // triangles 32..35
+  if (active) {
+    int x, y, z;
+    coords(g, v, &x, &y, &z);
+    const uint32_t valid = valid_nbs(g, x, y, z);
+    rx = rank[v];
+    int r[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) {
+      r[k] = INT_MAX;
+      if ((valid >> k) & 1u) {
+        r[k] = rank[v + off.o[k]];
+        if (r[k] < rx) low |= 1u << k;
+      }
+    }
+    uint64_t bypos = 0;  // nibble p: neighbour at position p
+#pragma unroll
+    for (int k = 0; k < 14; ++k) {
+      if ((low >> k) & 1u) {
+        uint32_t p = 0;
+#pragma unroll
+        for (int j = 0; j < 14; ++j) p += (((low >> j) & 1u) && r[j] < r[k]) ? 1u : 0u;
+        pos |= uint64_t(p) << (4 * k);
+        bypos |= uint64_t(k) << (4 * p);
+      }
+    }
+    if (low == 0) {
+      down_out[v] = v;
+    } else {
+      const int k0 = int(nib(bypos, 0));
+      down_out[v] = v + off.o[k0];
+      uint64_t Lt = 0;
+      uint32_t Lq = 0;
+#pragma unroll
+      for (int t = 0; t < 36; ++t)
+        if ((uint32_t(c_st.tri_nbm[t]) & low) == uint32_t(c_st.tri_nbm[t])) Lt |= 1ull << t;
+#pragma unroll
+      for (int q = 0; q < 24; ++q)
+        if ((uint32_t(c_st.tet_nbm[q]) & low) == uint32_t(c_st.tet_nbm[q])) Lq |= 1u << q;
+
+      // lower-star cells in lexicographic order: by highest other vertex P,
+      // then the triangle (P,Q) for increasing Q followed by its tets (P,Q,R)
+      // for increasing R
+      const int cnt = __popc(low);
+      int s = 0;
+      uint64_t eslot0 = 0, eslot1 = 0;
+      for (int P = 0; P < cnt; ++P) {
+        const int a = int(nib(bypos, P));
+        SLOT_CELL(s) = uint8_t((1u << 6) | a);
+        CELL_SLOT(a) = uint8_t(s);
+        if (s < 64) eslot0 |= 1ull << s;
+        else eslot1 |= 1ull << (s - 64);
+        ++s;
+        for (int Q = 0; Q < P; ++Q) {
+          const int b = int(nib(bypos, Q));
+          const int t = c_st.pair_tri[a][b];
+          if (t == 255) continue;
+          SLOT_CELL(s) = uint8_t((2u << 6) | t);
+          CELL_SLOT(14 + t) = uint8_t(s);
+          ++s;
+          // tets on triangle t whose third neighbour is lower than b
+          int qa = -1, qb = -1;
+          uint32_t ra = 0, rb = 0;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int q = c_st.tri_tet[t][i];
+            if (!((Lq >> q) & 1u)) continue;
+            const uint32_t third = uint32_t(c_st.tet_nbm[q]) & ~uint32_t(c_st.tri_nbm[t]);
+            const uint32_t rp = nib(pos, ffs32(third));
+            if (rp >= uint32_t(Q)) continue;
+            if (qa < 0) {
+              qa = q;
+              ra = rp;
+            } else {
+              qb = q;
+              rb = rp;
+            }
+          }
+          if (qb >= 0 && rb < ra) {
+            const int tq = qa;
+            qa = qb;
+            qb = tq;
+          }
+          if (qa >= 0) {
+            SLOT_CELL(s) = uint8_t((3u << 6) | qa);
+            CELL_SLOT(50 + qa) = uint8_t(s);
+            ++s;
+          }
+          if (qb >= 0) {
+            SLOT_CELL(s) = uint8_t((3u << 6) | qb);
+            CELL_SLOT(50 + qb) = uint8_t(s);
+            ++s;
+          }
+        }
+      }
+
+      uint32_t Ec = 1u << k0, Qc = 0;
+      uint64_t Tc = 0;
+      uint64_t O0 = 0, O1 = 0, Z0 = eslot0 & ~1ull, Z1 = eslot1;
+      ecode |= 7ull << (3 * k0);
+
+      auto set_slot = [&](uint64_t& m0, uint64_t& m1, int sl) {
+        if (sl < 64) m0 |= 1ull << sl;
+        else m1 |= 1ull << (sl - 64);
+      };
+      auto push_edge_cof = [&](int k) {
+        uint64_t m = c_st.edge_trim[k] & Lt;
+        while (m) {
+          const int t = ffs64(m);
+          m &= m - 1;
+          if (__popc(uint32_t(c_st.tri_nbm[t]) & ~Ec) == 1)
+            set_slot(O0, O1, CELL_SLOT(14 + t));
+        }
+      };
+      auto push_tri_cof = [&](int t) {
+        uint32_t m = c_st.tri_tetm[t] & Lq;
+        while (m) {
+          const int q = ffs32(m);
+          m &= m - 1;
+          if (__popcll(c_st.tet_trim[q] & ~Tc) == 1) set_slot(O0, O1, CELL_SLOT(50 + q));
+        }
+      };
+      auto set_tcode = [&](int t, uint32_t c) {
+        if (t < 32) tcode0 |= uint64_t(c) << (2 * t);
+        else tcode1 |= c << (2 * (t - 32));
+      };
+
+      push_edge_cof(k0);
+      for (;;) {
+        while (O0 | O1) {
+          int sl;
+          if (O0) {
+            sl = ffs64(O0);
+            O0 &= O0 - 1;
+          } else {
+            sl = 64 + ffs64(O1);
+            O1 &= O1 - 1;
+          }
+          const uint32_t cc = SLOT_CELL(sl);
+          const int dim = int(cc >> 6), idx = int(cc & 63u);
+          if (dim == 2) {
+            if ((Tc >> idx) & 1ull) continue;
+            const uint32_t u = uint32_t(c_st.tri_nbm[idx]) & ~Ec;
+            if (u == 0) {
+              set_slot(Z0, Z1, sl);
+              continue;
+            }
+            const int k = ffs32(u);
+            Ec |= 1u << k;
+            Tc |= 1ull << idx;
+            const uint32_t j = __popcll(c_st.edge_trim[k] & ((1ull << idx) - 1ull));
+            ecode |= uint64_t(j) << (3 * k);
+            push_tri_cof(idx);
+            push_edge_cof(k);
+          } else {
+            if ((Qc >> idx) & 1u) continue;
+            const uint64_t u = c_st.tet_trim[idx] & ~Tc;
+            if (u == 0) {
+              set_slot(Z0, Z1, sl);
+              continue;
+            }
+            const int t = ffs64(u);
+            Tc |= 1ull << t;
+            Qc |= 1u << idx;
+            set_tcode(t, c_st.tri_tet[t][0] == idx ? 2u : 3u);
+            push_tri_cof(t);
+          }
+        }
+        if (!(Z0 | Z1)) break;
+        int sl;
+        if (Z0) {
+          sl = ffs64(Z0);
+          Z0 &= Z0 - 1;
+        } else {
+          sl = 64 + ffs64(Z1);
+          Z1 &= Z1 - 1;
+        }
+        const uint32_t cc = SLOT_CELL(sl);
+        const int dim = int(cc >> 6), idx = int(cc & 63u);
+        if (dim == 1) {
+          if ((Ec >> idx) & 1u) continue;
+          Ec |= 1u << idx;
+          critE |= 1u << idx;
+          ecode |= 6ull << (3 * idx);
+          push_edge_cof(idx);
+        } else if (dim == 2) {
+          if ((Tc >> idx) & 1ull) continue;
+          Tc |= 1ull << idx;
+          critT |= 1ull << idx;
+          set_tcode(idx, 1u);
+          push_tri_cof(idx);
+        } else {
+          if ((Qc >> idx) & 1u) continue;
+          Qc |= 1u << idx;
+          critQ |= 1u << idx;
+        }
+      }
+    }
+    uint4 c;
+    c.x = uint32_t(ecode);
+    c.y = uint32_t(ecode >> 32) | (tcode1 << 10);
+    c.z = uint32_t(tcode0);
+    c.w = uint32_t(tcode0 >> 32);
+    code_out[v] = c;
+  }
+#undef SLOT_CELL
+#undef CELL_SLOT
+
+  // ---- emit critical cells (block-aggregated) ----
+  const unsigned int nv = (active && low == 0) ? 1u : 0u;
+  const unsigned int ne = __popc(critE), nt = __popcll(critT), nq = __popc(critQ);
+  __syncthreads();
+  unsigned int o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+  if (nv) o0 = atomicAdd(&s_cnt[0], nv);
+  if (ne) o1 = atomicAdd(&s_cnt[1], ne);
+  if (nt) o2 = atomicAdd(&s_cnt[2], nt);
+  if (nq) o3 = atomicAdd(&s_cnt[3], nq);
+  __syncthreads();
+  if (tid < 4) s_base[tid] = s_cnt[tid] ? atomicAdd(&co.count[tid], (unsigned long long)s_cnt[tid]) : 0ull;
+  __syncthreads();
+  if (!active) return;
+  const uint64_t rk = uint64_t(rx) << 12;
+  if (nv) {
+    const unsigned long long p = s_base[0] + o0;
+    if ((int64_t)p < co.cap[0]) {
+      co.key[0][p] = rk;
+      co.id[0][p] = v;
+    }
+  }
+  if (ne) {
+    unsigned long long p = s_base[1] + o1;
+    uint32_t m = critE;
+    while (m) {
+      const int k = ffs32(m);
+      m &= m - 1;
+      if ((int64_t)p < co.cap[1]) {
+        const int anchor = k < 7 ? v : v + off.o[k];
+        co.key[1][p] = rk | (uint64_t(nib(pos, k) + 1) << 8);
+        co.id[1][p] = 7 * anchor + (k % 7);
+      }
+      ++p;
+    }
+  }
+  if (nt) {
+    unsigned long long p = s_base[2] + o2;
+    uint64_t m = critT;
+    while (m) {
+      const int t = ffs64(m);
+      m &= m - 1;
+      if ((int64_t)p < co.cap[2]) {
+        const uint32_t pa = nib(pos, c_st.tri_nb[t][0]), pb = nib(pos, c_st.tri_nb[t][1]);
+        const uint32_t hi = max(pa, pb), lo = min(pa, pb);
+        const int anchor = v + lin(g, c_st.tri_anc[t][0], c_st.tri_anc[t][1], c_st.tri_anc[t][2]);
+        co.key[2][p] = rk | (uint64_t(hi + 1) << 8) | (uint64_t(lo + 1) << 4);
+        co.id[2][p] = 12 * anchor + c_st.tri_type[t];
+      }
+      ++p;
+    }
+  }
+  if (nq) {
+    unsigned long long p = s_base[3] + o3;
+    uint32_t m = critQ;
+    while (m) {
+      const int q = ffs32(m);
+      m &= m - 1;
+      if ((int64_t)p < co.cap[3]) {
+        uint32_t a = nib(pos, c_st.tet_nb[q][0]), b = nib(pos, c_st.tet_nb[q][1]),
+                 c = nib(pos, c_st.tet_nb[q][2]);
+        // sort descending
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        if (b < c) { const uint32_t t = b; b = c; c = t; }
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        const int anchor = v + lin(g, c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
+        co.key[3][p] = rk | (uint64_t(a + 1) << 8) | (uint64_t(b + 1) << 4) | uint64_t(c + 1);
+        co.id[3][p] = 6 * anchor + c_st.tet_type[q];
+      }
+      ++p;
+    }
+  }
+}
+
+// ======================================================================
+// Lookup helpers
+// ======================================================================
+
+__global__ void k_iota(uint32_t* a, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = uint32_t(i);
+}
+
+__global__ void k_gather_ids(const int32_t* __restrict__ ids, const uint32_t* __restrict__ perm,
+                             int64_t n, uint32_t* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = uint32_t(ids[perm[i]]);
+}
+
+// index of `id` in the id-sorted array, -1 if absent
+__device__ __forceinline__ int64_t find_id(const uint32_t* sorted_ids, int64_t n, uint32_t id) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sorted_ids[mid] < id) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && sorted_ids[lo] == id) ? lo : -1;
+}
+
+// ======================================================================
+// K5: min-saddle pairs
+// ======================================================================
+
+__global__ void k_min_index(const int32_t* __restrict__ min_ids, int64_t nmin,
+                            int32_t* __restrict__ min_idx) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nmin) min_idx[min_ids[i]] = int32_t(i);
+}
+
+// endpoints of critical edge i -> components (indices of the minima reached)
+__global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Grid g,
+                          const int32_t* __restrict__ down, const int32_t* __restrict__ min_idx,
+                          int32_t* __restrict__ ca, int32_t* __restrict__ cb,
+                          uint32_t* __restrict__ list, int* __restrict__ err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  const int id = edge_ids[i];
+  const int u = id / 7, t = id - 7 * (id / 7);
+  const int m = t + 1;
+  const int w = u + lin(g, m & 1, (m >> 1) & 1, (m >> 2) & 1);
+  int ends[2] = {u, w};
+  int comp[2];
+  for (int e = 0; e < 2; ++e) {
+    int a = ends[e];
+    int steps = 0;
+    while (true) {
+      const int d = down[a];
+      if (d == a) break;
+      a = d;
+      if (++steps > g.n) {
+        atomicOr(err, 1);
+        break;
+      }
+    }
+    comp[e] = min_idx[a];
+  }
+  ca[i] = comp[0];
+  cb[i] = comp[1];
+  list[i] = uint32_t(i);
+}
+
+// One hooking round of the union-find with the elder rule.
+// prio(i) = i (ascending order) or nedges-1-i (descending order).
+__global__ void k_uf_hook(const uint32_t* __restrict__ list, const unsigned int* __restrict__ nlist,
+                          int32_t* __restrict__ ca, int32_t* __restrict__ cb,
+                          const int32_t* __restrict__ parent, unsigned int* __restrict__ best,
+                          uint8_t* __restrict__ state, int descending, int64_t nedges) {
+  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= *nlist) return;
+  const uint32_t i = list[j];
+  const int a = parent[ca[i]], b = parent[cb[i]];
+  ca[i] = a;
+  cb[i] = b;
+  if (a == b) {
+    state[i] = 1;  // closes a cycle: no merge
+    return;
+  }
+  const unsigned int pr = descending ? unsigned(nedges - 1 - i) : i;
+  atomicMin(&best[a], pr);
+  atomicMin(&best[b], pr);
+}
+
+struct PairOut {
+  int32_t* dim;
+  int32_t* birth;
+  int32_t* death;
+  uint64_t* bkey;
+  uint64_t* dkey;
+  unsigned long long* count;
+  int64_t cap;
+};
+
+// Merge along the edges that are the lowest outgoing edge of both of their
+// components; the younger component's representative dies.
+//   dual == 0: nodes are minima (index 0 = oldest); pair (min, edge)
+//   dual == 1: nodes are maxima by increasing key and the outside (index
+//              nnodes-1, oldest); pair (triangle, max tet)
+__global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int* __restrict__ nlist,
+                          const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
+                          int32_t* __restrict__ parent, const unsigned int* __restrict__ best,
+                          uint8_t* __restrict__ state, uint32_t* __restrict__ next,
+                          unsigned int* __restrict__ nnext, int dual, int64_t nedges,
+                          const int32_t* __restrict__ cell_id, const uint64_t* __restrict__ cell_key,
+                          const int32_t* __restrict__ node_id, const uint64_t* __restrict__ node_key,
+                          int64_t outside, PairOut po) {
+  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= *nlist) return;
+  const uint32_t i = list[j];
+  if (state[i] != 0) return;
+  const int a = ca[i], b = cb[i];
+  const unsigned int pr = dual ? unsigned(nedges - 1 - i) : i;
+  if (best[a] == pr && best[b] == pr) {
+    int younger, elder;
+    if (!dual) {
+      younger = max(a, b);
+      elder = min(a, b);
+    } else {
+      younger = min(a, b);
+      elder = max(a, b);
+    }
+    parent[younger] = elder;
+    state[i] = 2;
+    const unsigned long long p = atomicAdd(po.count, 1ull);
+    if ((int64_t)p < po.cap) {
+      if (!dual) {
+        po.dim[p] = 0;
+        po.birth[p] = node_id[younger];
+        po.death[p] = cell_id[i];
+        po.bkey[p] = node_key[younger];
+        po.dkey[p] = cell_key[i];
+      } else {
+        po.dim[p] = 2;
+        po.birth[p] = cell_id[i];
+        po.death[p] = node_id[younger];
+        po.bkey[p] = cell_key[i];
+        po.dkey[p] = node_key[younger];
+      }
+    }
+    (void)outside;
+  } else {
+    const unsigned int q = atomicAdd(nnext, 1u);
+    next[q] = i;
+  }
+}
+
+__global__ void k_uf_reset(int32_t* __restrict__ parent, unsigned int* __restrict__ best,
+                           int64_t nnodes) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nnodes) return;
+  best[c] = 0xFFFFFFFFu;
+  parent[c] = parent[parent[c]];
+}
+
+__global__ void k_uf_init(int32_t* __restrict__ parent, unsigned int* __restrict__ best,
+                          int64_t nnodes) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nnodes) return;
+  best[c] = 0xFFFFFFFFu;
+  parent[c] = int32_t(c);
+}
+
+// ======================================================================
+// K6: saddle-max pairs (ascending gradient paths)
+// ======================================================================
+
+// Follows the ascending gradient path from star tet l of vertex y to a
+// maximum; returns the canonical id of the maximum, or -1 for the outside.
+__device__ int ascend(const Grid& g, const NbOff& off, const int32_t* __restrict__ rank,
+                      const uint4* __restrict__ code, int y, int l, int* err) {
+  int steps = 0;
+  while (true) {
+    if (++steps > 6 * g.n) {
+      atomicOr(err, 2);
+      return -1;
+    }
+    const uint4 c = code[y];
+    int paired_t = -1, side = 0;
+    uint64_t fm = c_st.tet_trim[l];
+    while (fm) {
+      const int t = ffs64(fm);
+      fm &= fm - 1;
+      const uint32_t tc = tri_code(c, t);
+      if (tc >= 2 && c_st.tri_tet[t][tc - 2] == l) {
+        paired_t = t;
+        side = int(tc - 2);
+      }
+    }
+    if (paired_t < 0) {
+      const int anchor = y + lin(g, c_st.tet_anc[l][0], c_st.tet_anc[l][1], c_st.tet_anc[l][2]);
+      return 6 * anchor + c_st.tet_type[l];
+    }
+    const int other = c_st.tri_tet[paired_t][1 - side];
+    const uint32_t third = uint32_t(c_st.tet_nbm[other]) & ~uint32_t(c_st.tri_nbm[paired_t]);
+    const int k = ffs32(third);
+    int x, yy, z;
+    coords(g, y, &x, &yy, &z);
+    const uint32_t valid = valid_nbs(g, x, yy, z);
+    if (!((valid >> k) & 1u)) return -1;  // the facet lies on the box boundary
+    const int cv = y + off.o[k];
+    if (rank[cv] < rank[y]) {
+      l = other;
+    } else {
+      // the next tet belongs to the lower star of its new apex cv
+      const int anchor =
+          y + lin(g, c_st.tet_anc[other][0], c_st.tet_anc[other][1], c_st.tet_anc[other][2]);
+      const int type = c_st.tet_type[other];
+      int ax, ay, az, cx, cy, cz;
+      coords(g, anchor, &ax, &ay, &az);
+      coords(g, cv, &cx, &cy, &cz);
+      const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
+      l = c_st.tet_local[type][__popc(mask)];
+      y = cv;
+    }
+  }
+}
+
+__global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
+                          int64_t nt, Grid g, NbOff off, const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ order, const uint4* __restrict__ code,
+                          const uint32_t* __restrict__ max_ids_sorted,
+                          const uint32_t* __restrict__ max_pos, int64_t nmax,
+                          int32_t* __restrict__ ca, int32_t* __restrict__ cb,
+                          uint32_t* __restrict__ list, int* __restrict__ err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const int id = tri_ids[i];
+  const int y = order[tri_keys[i] >> 12];  // highest vertex of the triangle
+  const int anchor = id / 12, type = id - 12 * (id / 12);
+  int ax, ay, az, cx, cy, cz;
+  coords(g, anchor, &ax, &ay, &az);
+  coords(g, y, &cx, &cy, &cz);
+  const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
+  const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
+  const int lt = c_st.tri_local[type][p];
+  int x, yy, z;
+  coords(g, y, &x, &yy, &z);
+  const uint32_t valid = valid_nbs(g, x, yy, z);
+  int comp[2];
+  for (int s = 0; s < 2; ++s) {
+    const int q = c_st.tri_tet[lt][s];
+    if ((uint32_t(c_st.tet_nbm[q]) & valid) != uint32_t(c_st.tet_nbm[q])) {
+      comp[s] = int(nmax);  // outside of the box
+      continue;
+    }
+    // the tet is in the lower star of y unless its third vertex is higher
+    const uint32_t third = uint32_t(c_st.tet_nbm[q]) & ~uint32_t(c_st.tri_nbm[lt]);
+    const int k = ffs32(third);
+    const int cv = y + off.o[k];
+    int yv = y, l = q;
+    if (rank[cv] > rank[y]) {
+      const int anc = y + lin(g, c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
+      const int qt = c_st.tet_type[q];
+      int bx, by, bz, vx, vy, vz;
+      coords(g, anc, &bx, &by, &bz);
+      coords(g, cv, &vx, &vy, &vz);
+      const int m2 = (vx - bx) | ((vy - by) << 1) | ((vz - bz) << 2);
+      l = c_st.tet_local[qt][__popc(m2)];
+      yv = cv;
+    }
+    const int mid = ascend(g, off, rank, code, yv, l, err);
+    if (mid < 0) {
+      comp[s] = int(nmax);
+    } else {
+      const int64_t f = find_id(max_ids_sorted, nmax, uint32_t(mid));
+      if (f < 0) {
+        atomicOr(err, 4);
+        comp[s] = int(nmax);
+      } else {
+        comp[s] = int(max_pos[f]);
+      }
+    }
+  }
+  ca[i] = comp[0];
+  cb[i] = comp[1];
+  list[i] = uint32_t(i);
+}
+
+// ======================================================================
+// K7: saddle-saddle pairs
+// ======================================================================
+
+// Edge given by its higher vertex h and the star index k of the other vertex.
+__device__ __forceinline__ int nb_index(int dx, int dy, int dz) {
+  if (dx >= 0 && dy >= 0 && dz >= 0) return (dx | (dy << 1) | (dz << 2)) - 1;
+  return 7 + ((-dx) | ((-dy) << 1) | ((-dz) << 2)) - 1;
+}
+
+struct EdgeRef {
+  uint64_t key;  // rank(h) << 32 | rank(other)
+  uint32_t ref;  // h << 4 | k
+};
+
+__device__ __forceinline__ EdgeRef make_edge(const Grid& g, const int32_t* __restrict__ rank, int a,
+                                             int b) {
+  const int ra = rank[a], rb = rank[b];
+  const int h = ra > rb ? a : b, o = ra > rb ? b : a;
+  int hx, hy, hz, ox, oy, oz;
+  coords(g, h, &hx, &hy, &hz);
+  coords(g, o, &ox, &oy, &oz);
+  EdgeRef e;
+  e.key = (uint64_t(uint32_t(max(ra, rb))) << 32) | uint32_t(min(ra, rb));
+  e.ref = (uint32_t(h) << 4) | uint32_t(nb_index(ox - hx, oy - hy, oz - hz));
+  return e;
+}
+
+// toggle `e` in the ascending-key array a[0..*len) (keys unique); returns false on overflow
+__device__ __forceinline__ bool toggle_edge(uint64_t* keys, uint32_t* refs, int* len, int cap,
+                                            const EdgeRef& e) {
+  int lo = 0, hi = *len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < e.key) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < *len && keys[lo] == e.key) {
+    for (int i = lo; i + 1 < *len; ++i) {
+      keys[i] = keys[i + 1];
+      refs[i] = refs[i + 1];
+    }
+    --*len;
+    return true;
+  }
+  if (*len >= cap) return false;
+  for (int i = *len; i > lo; --i) {
+    keys[i] = keys[i - 1];
+    refs[i] = refs[i - 1];
+  }
+  keys[lo] = e.key;
+  refs[lo] = e.ref;
+  ++*len;
+  return true;
+}
+
+__device__ __forceinline__ bool toggle_row(uint32_t* rows, int* len, int cap, uint32_t r) {
+  int lo = 0, hi = *len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rows[mid] < r) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < *len && rows[lo] == r) {
+    for (int i = lo; i + 1 < *len; ++i) rows[i] = rows[i + 1];
+    --*len;
+    return true;
+  }
+  if (*len >= cap) return false;
+  for (int i = *len; i > lo; --i) rows[i] = rows[i - 1];
+  rows[lo] = r;
+  ++*len;
+  return true;
+}
+
+struct ColPool {
+  uint32_t* data;
+  unsigned long long* top;
+  int64_t cap;
+};
+
+// Morse boundary of critical triangle column c (mod 2, restricted to the
+// critical edges that do not die in dimension 0), written descending.
+__global__ void k_d1_boundary(const uint32_t* __restrict__ cols, int64_t ncols,
+                              const int32_t* __restrict__ tri_ids,
+                              const uint64_t* __restrict__ tri_keys, Grid g, NbOff off,
+                              const int32_t* __restrict__ rank, const int32_t* __restrict__ order,
+                              const uint4* __restrict__ code,
+                              const uint32_t* __restrict__ edge_ids_sorted,
+                              const uint32_t* __restrict__ edge_pos, int64_t nedges,
+                              const uint8_t* __restrict__ edge_state, uint64_t* __restrict__ wkeys,
+                              uint32_t* __restrict__ wrefs, uint32_t* __restrict__ wrows, int wcap,
+                              int rcap, ColPool pool, uint64_t* __restrict__ col_desc,
+                              uint8_t* __restrict__ overflow, int* __restrict__ err,
+                              int64_t nthreads) {
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= nthreads) return;  // scratch is sized for exactly nthreads lanes
+  uint64_t* K = wkeys + tid * wcap;
+  uint32_t* Rf = wrefs + tid * wcap;
+  uint32_t* Rows = wrows + tid * rcap;
+  for (int64_t c = tid; c < ncols; c += nthreads) {
+    if (overflow[c] == 0 && col_desc[c] != ~0ull) continue;  // already done
+    const uint32_t ti = cols[c];
+    const int id = tri_ids[ti];
+    const int y = order[tri_keys[ti] >> 12];
+    const int anchor = id / 12, type = id - 12 * (id / 12);
+    int ax, ay, az, cx, cy, cz;
+    coords(g, anchor, &ax, &ay, &az);
+    coords(g, y, &cx, &cy, &cz);
+    const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
+    const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
+    const int lt = c_st.tri_local[type][p];
+    const int va = y + off.o[c_st.tri_nb[lt][0]], vb = y + off.o[c_st.tri_nb[lt][1]];
+    int wl = 0, rl = 0;
+    bool ok = toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, y, va)) &&
+              toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, y, vb)) &&
+              toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, va, vb));
+    int guard = 0;
+    while (ok && wl > 0) {
+      if (++guard > 64 * g.n) {
+        atomicOr(err, 8);
+        ok = false;
+        break;
+      }
+      --wl;
+      const uint32_t ref = Rf[wl];
+      const int h = int(ref >> 4), k = int(ref & 15u);
+      const uint32_t ec = edge_code(code[h], k);
+      if (ec == 7u) continue;  // paired with its vertex: the path ends
+      if (ec == 6u) {          // critical edge
+        const int lo = h + off.o[k];
+        const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
+        const int64_t f = find_id(edge_ids_sorted, nedges, uint32_t(eid));
+        if (f < 0) {
+          atomicOr(err, 16);
+          continue;
+        }
+        const uint32_t row = edge_pos[f];
+        if (edge_state[row] != 1) continue;  // dies in dimension 0: dropped
+        if (!toggle_row(Rows, &rl, rcap, row)) {
+          ok = false;
+          break;
+        }
+        continue;
+      }
+      // paired with the ec-th star triangle containing the edge
+      uint64_t m = c_st.edge_trim[k];
+      for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
+      if (m == 0) {
+        atomicOr(err, 128);
+        ok = false;
+        break;
+      }
+      const int t = ffs64(m);
+      const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
+      const int lo = h + off.o[k], n2 = h + off.o[k2];
+      EdgeRef e1;
+      e1.key = (uint64_t(uint32_t(rank[h])) << 32) | uint32_t(rank[n2]);
+      e1.ref = (uint32_t(h) << 4) | uint32_t(k2);
+      ok = toggle_edge(K, Rf, &wl, wcap, e1) && toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, lo, n2));
+    }
+    if (!ok) {
+      overflow[c] = 1;
+      continue;
+    }
+    overflow[c] = 0;
+    if (rl == 0) {
+      atomicOr(err, 32);  // a negative triangle must have a non-empty boundary
+      col_desc[c] = 0;
+      continue;
+    }
+    const unsigned long long at = atomicAdd(pool.top, (unsigned long long)rl);
+    if ((int64_t)(at + rl) > pool.cap) {
+      overflow[c] = 2;  // pool full: retried after growing the pool
+      continue;
+    }
+    for (int i = 0; i < rl; ++i) pool.data[at + i] = Rows[rl - 1 - i];  // descending
+    col_desc[c] = (uint64_t(at) << 24) | uint64_t(rl);
+  }
+}
+
+// Parallel reduction round: owner[p] = lowest column with pivot p.
+__global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, int64_t ncols,
+                           const uint32_t* __restrict__ pool, unsigned int* __restrict__ owner) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const uint64_t d = col_desc[c];
+  const uint32_t len = uint32_t(d & 0xFFFFFFu);
+  if (len == 0) return;
+  const uint32_t piv = pool[d >> 24];
+  atomicMin(&owner[piv], uint32_t(c));
+}
+
+__global__ void k_d1_reduce(uint64_t* __restrict__ col_desc, int64_t ncols, uint32_t* __restrict__ pool,
+                            ColPool pc, const unsigned int* __restrict__ owner,
+                            unsigned int* __restrict__ nconflict, int* __restrict__ err,
+                            int* __restrict__ pool_full) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const uint64_t d = col_desc[c];
+  const uint32_t len = uint32_t(d & 0xFFFFFFu);
+  if (len == 0) return;
+  const uint64_t off_c = d >> 24;
+  const uint32_t piv = pool[off_c];
+  const unsigned int o = owner[piv];
+  if (o == uint32_t(c)) return;
+  atomicAdd(nconflict, 1u);
+  const uint64_t od = col_desc[o];
+  const uint32_t olen = uint32_t(od & 0xFFFFFFu);
+  const uint64_t off_o = od >> 24;
+  const unsigned long long at = atomicAdd(pc.top, (unsigned long long)(len + olen));
+  if ((int64_t)(at + len + olen) > pc.cap) {
+    atomicOr(pool_full, 1);
+    return;  // retried next round after the pool has grown
+  }
+  // symmetric difference of two descending lists
+  uint32_t i = 0, j = 0, w = 0;
+  while (i < len || j < olen) {
+    if (j >= olen || (i < len && pool[off_c + i] > pool[off_o + j])) {
+      pool[at + w++] = pool[off_c + i++];
+    } else if (i >= len || pool[off_o + j] > pool[off_c + i]) {
+      pool[at + w++] = pool[off_o + j++];
+    } else {
+      ++i;
+      ++j;
+    }
+  }
+  if (w == 0) atomicOr(err, 64);
+  col_desc[c] = (uint64_t(at) << 24) | uint64_t(w);
+}
+
+__global__ void k_fill_u32(unsigned int* a, int64_t n, unsigned int v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* a, int64_t n, uint64_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* a, int64_t n, uint8_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_collect_cols(const uint8_t* __restrict__ tri_state, int64_t nt,
+                               uint32_t* __restrict__ cols, unsigned int* __restrict__ ncols) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  if (tri_state[i] == 1) cols[atomicAdd(ncols, 1u)] = uint32_t(i);
+}
+
+__global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
+                           const uint32_t* __restrict__ cols, const uint32_t* __restrict__ pool,
+                           const int32_t* __restrict__ edge_ids, const uint64_t* __restrict__ edge_keys,
+                           const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
+                           PairOut po) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const uint64_t d = col_desc[c];
+  if ((d & 0xFFFFFFu) == 0) return;
+  const uint32_t row = pool[d >> 24];
+  const uint32_t ti = cols[c];
+  const unsigned long long p = atomicAdd(po.count, 1ull);
+  if ((int64_t)p < po.cap) {
+    po.dim[p] = 1;
+    po.birth[p] = edge_ids[row];
+    po.death[p] = tri_ids[ti];
+    po.bkey[p] = edge_keys[row];
+    po.dkey[p] = tri_keys[ti];
+  }
+}
+
+// ======================================================================
+// K8: diagram
+// ======================================================================
+
+__global__ void k_diag_keys(const int32_t* __restrict__ pdim, const uint64_t* __restrict__ bkey,
+                            const uint64_t* __restrict__ dkey, int64_t np, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ idx, unsigned int* __restrict__ nd) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const uint64_t rb = bkey[i] >> 12, rd = dkey[i] >> 12;
+  if (rb == rd) return;  // zero persistence
+  const unsigned int p = atomicAdd(nd, 1u);
+  keys[p] = (rb << 39) | (rd << 14) | (uint64_t(pdim[i]) << 12) | (bkey[i] & 0xFFFu);
+  idx[p] = uint32_t(i);
+}
+
+// ======================================================================
+// gradient decode (dense partner arrays)
+// ======================================================================
+
+__global__ void k_valid_cells(Grid g, int32_t* __restrict__ eup, int32_t* __restrict__ tup) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.n) return;
+  int x, y, z;
+  coords(g, v, &x, &y, &z);
+  for (int t = 0; t < 7; ++t) {
+    const int m = t + 1;
+    const bool ok = x + (m & 1) < g.Lx && y + ((m >> 1) & 1) < g.Ly && z + ((m >> 2) & 1) < g.Lz;
+    eup[7 * v + t] = ok ? -1 : -2;
+  }
+  for (int t = 0; t < 12; ++t) {
+    const int m = c_st.tri_chain[t][2];
+    const bool ok = x + (m & 1) < g.Lx && y + ((m >> 1) & 1) < g.Ly && z + ((m >> 2) & 1) < g.Lz;
+    tup[12 * v + t] = ok ? -1 : -2;
+  }
+}
+
+__global__ void k_decode(Grid g, NbOff off, const int32_t* __restrict__ rank,
+                         const uint4* __restrict__ code, int32_t* __restrict__ vup,
+                         int32_t* __restrict__ eup, int32_t* __restrict__ tup) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.n) return;
+  int x, y, z;
+  coords(g, v, &x, &y, &z);
+  const uint32_t valid = valid_nbs(g, x, y, z);
+  const int rx = rank[v];
+  uint32_t low = 0;
+  for (int k = 0; k < 14; ++k)
+    if (((valid >> k) & 1u) && rank[v + off.o[k]] < rx) low |= 1u << k;
+  const uint4 c = code[v];
+  vup[v] = -1;
+  auto edge_id = [&](int k) { return k < 7 ? 7 * v + k : 7 * (v + off.o[k]) + (k - 7); };
+  auto tri_id = [&](int t) {
+    return 12 * (v + lin(g, c_st.tri_anc[t][0], c_st.tri_anc[t][1], c_st.tri_anc[t][2])) +
+           c_st.tri_type[t];
+  };
+  auto tet_id = [&](int q) {
+    return 6 * (v + lin(g, c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2])) +
+           c_st.tet_type[q];
+  };
+  for (int k = 0; k < 14; ++k) {
+    if (!((low >> k) & 1u)) continue;
+    const uint32_t ec = edge_code(c, k);
+    if (ec == 7u) {
+      vup[v] = edge_id(k);
+    } else if (ec < 6u) {
+      uint64_t m = c_st.edge_trim[k];
+      for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
+      eup[edge_id(k)] = tri_id(ffs64(m));
+    }
+  }
+  for (int t = 0; t < 36; ++t) {
+    if ((uint32_t(c_st.tri_nbm[t]) & low) != uint32_t(c_st.tri_nbm[t])) continue;
+    const uint32_t tc = tri_code(c, t);
+    if (tc >= 2u) tup[tri_id(t)] = tet_id(c_st.tri_tet[t][tc - 2]);
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+template <class T>
+T read_scalar(const T* dptr, hipStream_t s) {
+  T v;
+  TS_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  TS_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// Union-find rounds shared by K5 and K6.
+int union_find_rounds(ts_ctx* ctx, int64_t nedges, int64_t nnodes, int32_t* ca, int32_t* cb,
+                      uint8_t* state, int dual, const int32_t* cell_id, const uint64_t* cell_key,
+                      const int32_t* node_id, const uint64_t* node_key, PairOut po,
+                      const char* tag) {
+  hipStream_t s = ctx->stream;
+  Workspace& ws = ctx->ws;
+  const std::string t(tag);
+  int32_t* parent = ws.get<int32_t>(t + ".parent", nnodes + 1);
+  unsigned int* best = ws.get<unsigned int>(t + ".best", nnodes + 1);
+  uint32_t* listA = ws.get<uint32_t>(t + ".listA", nedges + 1);
+  uint32_t* listB = ws.get<uint32_t>(t + ".listB", nedges + 1);
+  unsigned int* cnt = ws.get<unsigned int>(t + ".cnt", 4);
+  k_uf_init<<<blocks_for(nnodes), 256, 0, s>>>(parent, best, nnodes);
+  unsigned int h_n = unsigned(nedges);
+  k_fill_u32<<<1, 1, 0, s>>>(cnt, 1, h_n);
+  // listA already holds 0..nedges-1 (written by the init kernel)
+  int rounds = 0;
+  uint32_t* cur = listA;
+  uint32_t* nxt = listB;
+  unsigned int* ncur = cnt;
+  unsigned int* nnxt = cnt + 1;
+  while (h_n > 0) {
+    ++rounds;
+    TS_HIP(hipMemsetAsync(nnxt, 0, sizeof(unsigned int), s));
+    k_uf_hook<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, dual, nedges);
+    k_uf_link<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, nxt, nnxt,
+                                              dual, nedges, cell_id, cell_key, node_id, node_key,
+                                              nnodes - 1, po);
+    k_uf_reset<<<blocks_for(nnodes), 256, 0, s>>>(parent, best, nnodes);
+    TS_HIP(hipGetLastError());
+    h_n = read_scalar(nnxt, s);
+    std::swap(cur, nxt);
+    std::swap(ncur, nnxt);
+    if (rounds > nedges + 2) throw Error(TS_ERR_INTERNAL, "union-find did not converge");
+  }
+  return rounds;
+}
+
+}  // namespace
+
+// ======================================================================
+// Host orchestration
+// ======================================================================
+
+void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* rank) {
+  hipStream_t s = ctx->stream;
+  Workspace& ws = ctx->ws;
+  uint32_t* keys = ws.get<uint32_t>("ord.keys", n);
+  uint32_t* vals = ws.get<uint32_t>("ord.vals", n);
+  int* bad = ws.get<int>("ord.bad", 1);
+  TS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  ctx->timer.start("K1 order keys");
+  k_order_keys<<<blocks_for(n), 256, 0, s>>>(f, n, keys, vals, bad);
+  ctx->timer.stop();
+  ctx->timer.start("K1 radix sort");
+  radix_sort_u32(ws, keys, vals, n, 0, 32, s);
+  ctx->timer.stop();
+  ctx->timer.start("K2 rank");
+  k_rank_scatter<<<blocks_for(n), 256, 0, s>>>(vals, n, rank, order);
+  ctx->timer.stop();
+  TS_HIP(hipGetLastError());
+  if (read_scalar(bad, s)) throw Error(TS_ERR_NONFINITE, "field contains NaN or Inf");
+}
+
+void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R) {
+  upload_tables(ctx->device);
+  hipStream_t s = ctx->stream;
+  Workspace& ws = ctx->ws;
+  const int n = g.n;
+  R->g = g;
+  R->order = ws.get<int32_t>("pm.order", n);
+  R->rank = ws.get<int32_t>("pm.rank", n);
+  R->code = ws.get<uint4>("pm.code", n);
+  R->down = ws.get<int32_t>("pm.down", n);
+  compute_order(ctx, f, n, R->order, R->rank);
+  const NbOff off = make_offsets(g);
+
+  // ---- K3 + K4: gradient and critical cells ----
+  unsigned long long* ccount = ws.get<unsigned long long>("pm.ccount", 4);
+  static int64_t cap_hint[4] = {0, 0, 0, 0};
+  int64_t cap[4];
+  for (int d = 0; d < 4; ++d) cap[d] = std::max<int64_t>(cap_hint[d], std::max<int64_t>(1024, n / 4));
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    CritOut co;
+    for (int d = 0; d < 4; ++d) {
+      co.key[d] = ws.get<uint64_t>("pm.ckey" + std::to_string(d), cap[d]);
+      co.id[d] = ws.get<int32_t>("pm.cid" + std::to_string(d), cap[d]);
+      co.cap[d] = cap[d];
+    }
+    co.count = ccount;
+    TS_HIP(hipMemsetAsync(ccount, 0, 4 * sizeof(unsigned long long), s));
+    ctx->timer.start("K3 gradient");
+    k_gradient<<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(R->rank, g, off, R->code,
+                                                                    R->down, co);
+    ctx->timer.stop();
+    TS_HIP(hipGetLastError());
+    unsigned long long h[4];
+    TS_HIP(hipMemcpyAsync(h, ccount, sizeof(h), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipStreamSynchronize(s));
+    bool fits = true;
+    for (int d = 0; d < 4; ++d) {
+      R->ncrit[d] = int64_t(h[d]);
+      if (R->ncrit[d] > cap[d]) {
+        fits = false;
+        cap[d] = R->ncrit[d] + R->ncrit[d] / 8 + 1024;
+      }
+      cap_hint[d] = std::max(cap_hint[d], cap[d]);
+    }
+    if (fits) {
+      for (int d = 0; d < 4; ++d) {
+        R->ckey[d] = co.key[d];
+        R->cid[d] = co.id[d];
+      }
+      break;
+    }
+    if (attempt == 2) throw Error(TS_ERR_INTERNAL, "critical-cell buffers did not fit");
+  }
+  if (R->ncrit[0] - R->ncrit[1] + R->ncrit[2] - R->ncrit[3] != 1)
+    throw Error(TS_ERR_INTERNAL, "Euler characteristic of the critical cells is not 1");
+  const int64_t nmin = R->ncrit[0], ne = R->ncrit[1], ntri = R->ncrit[2], nmax = R->ncrit[3];
+
+  // sort every list by key; keep an id-sorted index for lookups
+  ctx->timer.start("K4 sort critical");
+  const int keybits = 12 + 32 - __builtin_clz(uint32_t(std::max(n - 1, 1)));
+  for (int d = 0; d < 4; ++d) {
+    if (R->ncrit[d] <= 1) continue;
+    uint32_t* perm = ws.get<uint32_t>("pm.perm", R->ncrit[d]);
+    k_iota<<<blocks_for(R->ncrit[d]), 256, 0, s>>>(perm, R->ncrit[d]);
+    radix_sort_u64(ws, R->ckey[d], perm, R->ncrit[d], 0, keybits, s);
+    int32_t* ids2 = ws.get<int32_t>("pm.cid_sorted" + std::to_string(d), R->ncrit[d]);
+    k_gather_ids<<<blocks_for(R->ncrit[d]), 256, 0, s>>>(R->cid[d], perm, R->ncrit[d],
+                                                         reinterpret_cast<uint32_t*>(ids2));
+    R->cid[d] = ids2;
+  }
+  // id-sorted lookups for edges (rows) and tets (maxima)
+  auto id_index = [&](int d, uint32_t** ids_sorted, uint32_t** pos) {
+    const int64_t m = R->ncrit[d];
+    *ids_sorted = ws.get<uint32_t>("pm.idsort" + std::to_string(d), m);
+    *pos = ws.get<uint32_t>("pm.idpos" + std::to_string(d), m);
+    if (m == 0) return;
+    TS_HIP(hipMemcpyAsync(*ids_sorted, R->cid[d], m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    k_iota<<<blocks_for(m), 256, 0, s>>>(*pos, m);
+    radix_sort_u32(ws, *ids_sorted, *pos, m, 0, 32, s);
+  };
+  uint32_t *edge_ids_sorted, *edge_pos, *max_ids_sorted, *max_pos;
+  id_index(1, &edge_ids_sorted, &edge_pos);
+  id_index(3, &max_ids_sorted, &max_pos);
+  ctx->timer.stop();
+
+  // pair output
+  const int64_t pcap = nmin + nmax + ne + 16;
+  PairOut po;
+  po.dim = ws.get<int32_t>("pm.pdim", pcap);
+  po.birth = ws.get<int32_t>("pm.pbirth", pcap);
+  po.death = ws.get<int32_t>("pm.pdeath", pcap);
+  po.bkey = ws.get<uint64_t>("pm.pbkey", pcap);
+  po.dkey = ws.get<uint64_t>("pm.pdkey", pcap);
+  po.count = ws.get<unsigned long long>("pm.pcount", 1);
+  po.cap = pcap;
+  TS_HIP(hipMemsetAsync(po.count, 0, sizeof(unsigned long long), s));
+  int* err = ws.get<int>("pm.err", 1);
+  TS_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+
+  // ---- K5: min-saddle ----
+  uint8_t* estate = ws.get<uint8_t>("pm.estate", ne + 1);
+  if (ne > 0) {
+    ctx->timer.start("K5 d0 paths");
+    int32_t* min_idx = ws.get<int32_t>("pm.minidx", n);
+    int32_t* ca = ws.get<int32_t>("pm.ca", ne);
+    int32_t* cb = ws.get<int32_t>("pm.cb", ne);
+    uint32_t* listA = ws.get<uint32_t>("uf0.listA", ne + 1);
+    k_min_index<<<blocks_for(nmin), 256, 0, s>>>(R->cid[0], nmin, min_idx);
+    k_fill_u8<<<blocks_for(ne), 256, 0, s>>>(estate, ne, 0);
+    k_d0_init<<<blocks_for(ne), 256, 0, s>>>(R->cid[1], ne, g, R->down, min_idx, ca, cb, listA, err);
+    ctx->timer.stop();
+    ctx->timer.start("K5 d0 union-find");
+    R->rounds_d0 = union_find_rounds(ctx, ne, nmin, ca, cb, estate, 0, R->cid[1], R->ckey[1],
+                                     R->cid[0], R->ckey[0], po, "uf0");
+    ctx->timer.stop();
+  }
+
+  // ---- K6: saddle-max ----
+  uint8_t* tstate = ws.get<uint8_t>("pm.tstate", ntri + 1);
+  if (ntri > 0) {
+    ctx->timer.start("K6 d2 paths");
+    int32_t* ca = ws.get<int32_t>("pm.ca", std::max(ne, ntri));
+    int32_t* cb = ws.get<int32_t>("pm.cb", std::max(ne, ntri));
+    uint32_t* listA = ws.get<uint32_t>("uf2.listA", ntri + 1);
+    k_fill_u8<<<blocks_for(ntri), 256, 0, s>>>(tstate, ntri, 0);
+    k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, g, off, R->rank,
+                                               R->order, R->code, max_ids_sorted, max_pos, nmax,
+                                               ca, cb, listA, err);
+    ctx->timer.stop();
+    ctx->timer.start("K6 d2 union-find");
+    // node ids/keys of maxima; the outside (index nmax) never dies
+    R->rounds_d2 = union_find_rounds(ctx, ntri, nmax + 1, ca, cb, tstate, 1, R->cid[2],
+                                     R->ckey[2], R->cid[3], R->ckey[3], po, "uf2");
+    ctx->timer.stop();
+  }
+  {
+    const int h_err = read_scalar(err, s);
+    if (h_err) throw Error(TS_ERR_INTERNAL, "gradient path error " + std::to_string(h_err));
+  }
+
+  // ---- K7: saddle-saddle ----
+  unsigned int* ncols_d = ws.get<unsigned int>("d1.ncols", 1);
+  TS_HIP(hipMemsetAsync(ncols_d, 0, sizeof(unsigned int), s));
+  uint32_t* cols = ws.get<uint32_t>("d1.cols", ntri + 1);
+  if (ntri > 0) {
+    k_collect_cols<<<blocks_for(ntri), 256, 0, s>>>(tstate, ntri, cols, ncols_d);
+  }
+  const int64_t ncols = read_scalar(ncols_d, s);
+  if (ncols > 0) {
+    // columns in increasing key order
+    ctx->timer.start("K7 d1 boundary");
+    {
+      uint32_t* ckeys = ws.get<uint32_t>("d1.ckeys", ncols);
+      TS_HIP(hipMemcpyAsync(ckeys, cols, ncols * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+      radix_sort_u32(ws, ckeys, cols, ncols, 0, 32, s);
+    }
+    uint64_t* col_desc = ws.get<uint64_t>("d1.desc", ncols);
+    uint8_t* overflow = ws.get<uint8_t>("d1.ovf", ncols);
+    k_fill_u64<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, ~0ull);
+    k_fill_u8<<<blocks_for(ncols), 256, 0, s>>>(overflow, ncols, 0);
+    static int64_t pool_hint = 0;
+    int64_t pool_cap = std::max<int64_t>(pool_hint, std::max<int64_t>(1 << 20, 16 * ncols));
+    ColPool pool;
+    pool.data = ws.get<uint32_t>("d1.pool", pool_cap);
+    pool.top = ws.get<unsigned long long>("d1.top", 1);
+    pool.cap = pool_cap;
+    TS_HIP(hipMemsetAsync(pool.top, 0, sizeof(unsigned long long), s));
+    int wcap = 128, rcap = 64;
+    for (int pass = 0;; ++pass) {
+      const int64_t nthreads = std::min<int64_t>(ncols, pass == 0 ? 65536 : 4096);
+      uint64_t* wk = ws.get<uint64_t>("d1.wk", nthreads * wcap);
+      uint32_t* wr = ws.get<uint32_t>("d1.wr", nthreads * wcap);
+      uint32_t* rr = ws.get<uint32_t>("d1.rr", nthreads * rcap);
+      k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(
+          cols, ncols, R->cid[2], R->ckey[2], g, off, R->rank, R->order, R->code, edge_ids_sorted,
+          edge_pos, ne, estate, wk, wr, rr, wcap, rcap, pool, col_desc, overflow, err, nthreads);
+      TS_HIP(hipGetLastError());
+      // any column left to do?
+      std::vector<uint8_t> h_ovf(ncols);
+      TS_HIP(hipMemcpyAsync(h_ovf.data(), overflow, ncols, hipMemcpyDeviceToHost, s));
+      TS_HIP(hipStreamSynchronize(s));
+      bool any = false, pool_full = false;
+      for (uint8_t o : h_ovf) {
+        any = any || o != 0;
+        pool_full = pool_full || o == 2;
+      }
+      if (!any) break;
+      if (pass > 12) throw Error(TS_ERR_INTERNAL, "boundary extraction did not finish");
+      if (pool_full) {
+        // grow the pool keeping its contents
+        const int64_t used = int64_t(read_scalar(pool.top, s));
+        const int64_t ncap = std::max<int64_t>(2 * pool_cap, used + 16 * ncols);
+        uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
+        TS_HIP(hipMemcpyAsync(np, pool.data, std::min(used, pool_cap) * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, s));
+        std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
+        pool.data = np;
+        pool_cap = ncap;
+        pool.cap = ncap;
+        unsigned long long top = std::min(used, pool_cap);
+        TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
+        TS_HIP(hipStreamSynchronize(s));
+      } else {
+        wcap *= 4;
+        rcap *= 4;
+      }
+    }
+    pool_hint = std::max(pool_hint, pool_cap);
+    ctx->timer.stop();
+
+    ctx->timer.start("K7 d1 reduction");
+    unsigned int* owner = ws.get<unsigned int>("d1.owner", ne + 1);
+    unsigned int* nconf = ws.get<unsigned int>("d1.nconf", 1);
+    int* pool_full = ws.get<int>("d1.full", 1);
+    int rounds = 0;
+    for (;;) {
+      ++rounds;
+      k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
+      TS_HIP(hipMemsetAsync(nconf, 0, sizeof(unsigned int), s));
+      TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
+      k_d1_claim<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, pool.data, owner);
+      k_d1_reduce<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, pool.data, pool, owner, nconf,
+                                                    err, pool_full);
+      TS_HIP(hipGetLastError());
+      const unsigned int h_conf = read_scalar(nconf, s);
+      if (h_conf == 0) break;
+      if (read_scalar(pool_full, s)) {
+        // compact live columns into a larger pool
+        std::vector<uint64_t> desc(ncols);
+        TS_HIP(hipMemcpyAsync(desc.data(), col_desc, ncols * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+        int64_t live = 0;
+        for (uint64_t d : desc) live += int64_t(d & 0xFFFFFFu);
+        const int64_t ncap = std::max<int64_t>(2 * pool_cap, 4 * live + (1 << 20));
+        uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
+        int64_t at = 0;
+        for (int64_t c = 0; c < ncols; ++c) {
+          const int64_t len = int64_t(desc[c] & 0xFFFFFFu);
+          if (len > 0)
+            TS_HIP(hipMemcpyAsync(np + at, pool.data + (desc[c] >> 24), len * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+          desc[c] = (uint64_t(at) << 24) | uint64_t(len);
+          at += len;
+        }
+        TS_HIP(hipMemcpyAsync(col_desc, desc.data(), ncols * sizeof(uint64_t),
+                              hipMemcpyHostToDevice, s));
+        TS_HIP(hipStreamSynchronize(s));
+        std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
+        pool.data = np;
+        pool_cap = ncap;
+        pool.cap = ncap;
+        unsigned long long top = at;
+        TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
+        TS_HIP(hipStreamSynchronize(s));
+        pool_hint = std::max(pool_hint, pool_cap);
+      }
+      if (rounds > 100000) throw Error(TS_ERR_INTERNAL, "saddle-saddle reduction did not converge");
+    }
+    R->rounds_d1 = rounds;
+    k_d1_pairs<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, cols, pool.data, R->cid[1],
+                                                 R->ckey[1], R->cid[2], R->ckey[2], po);
+    ctx->timer.stop();
+  }
+  {
+    const int h_err = read_scalar(err, s);
+    if (h_err) throw Error(TS_ERR_INTERNAL, "persistence error " + std::to_string(h_err));
+  }
+
+  // ---- essential class and counts ----
+  int64_t np = int64_t(read_scalar(po.count, s));
+  if (np + 1 > pcap) throw Error(TS_ERR_INTERNAL, "pair buffer overflow");
+  {
+    const int32_t dim0 = 0, death = -1;
+    int32_t gmin;
+    TS_HIP(hipMemcpyAsync(&gmin, R->cid[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipStreamSynchronize(s));
+    const uint64_t bk = 0, dk = uint64_t(n - 1) << 12;
+    TS_HIP(hipMemcpyAsync(po.dim + np, &dim0, 4, hipMemcpyHostToDevice, s));
+    TS_HIP(hipMemcpyAsync(po.birth + np, &gmin, 4, hipMemcpyHostToDevice, s));
+    TS_HIP(hipMemcpyAsync(po.death + np, &death, 4, hipMemcpyHostToDevice, s));
+    TS_HIP(hipMemcpyAsync(po.bkey + np, &bk, 8, hipMemcpyHostToDevice, s));
+    TS_HIP(hipMemcpyAsync(po.dkey + np, &dk, 8, hipMemcpyHostToDevice, s));
+    TS_HIP(hipStreamSynchronize(s));
+    ++np;
+  }
+  if (np - 1 != nmin - 1 + nmax + (ne - (nmin - 1)))
+    throw Error(TS_ERR_INTERNAL, "pair count does not match the critical cells");
+  R->npairs = np;
+  R->pdim = po.dim;
+  R->pbirth = po.birth;
+  R->pdeath = po.death;
+  R->pbkey = po.bkey;
+  R->pdkey = po.dkey;
+
+  // ---- K8: diagram order ----
+  ctx->timer.start("K8 diagram");
+  uint64_t* dkeys = ws.get<uint64_t>("pm.dkeys", np);
+  R->diag = ws.get<uint32_t>("pm.diag", np);
+  unsigned int* nd = ws.get<unsigned int>("pm.nd", 1);
+  TS_HIP(hipMemsetAsync(nd, 0, sizeof(unsigned int), s));
+  k_diag_keys<<<blocks_for(np), 256, 0, s>>>(po.dim, po.bkey, po.dkey, np, dkeys, R->diag, nd);
+  R->ndiag = read_scalar(nd, s);
+  radix_sort_u64(ws, dkeys, R->diag, R->ndiag, 0, 64, s);
+  ctx->timer.stop();
+  TS_HIP(hipGetLastError());
+}
+
+void decode_gradient(ts_ctx* ctx, const PersistenceResult& R, int32_t* vup, int32_t* eup,
+                     int32_t* tup) {
+  hipStream_t s = ctx->stream;
+  const NbOff off = make_offsets(R.g);
+  k_valid_cells<<<blocks_for(R.g.n), 256, 0, s>>>(R.g, eup, tup);
+  k_decode<<<blocks_for(R.g.n), 256, 0, s>>>(R.g, off, R.rank, R.code, vup, eup, tup);
+  TS_HIP(hipGetLastError());
+}
+
+}  // namespace ts

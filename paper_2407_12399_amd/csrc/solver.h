@@ -1,0 +1,23 @@
+// solver.h -- simplification loop (Alg. 1 with Sec. 4.1 and Sec. 4.3).
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace ts {
+
+Grid make_grid(const int64_t dims[3]);
+
+// Runs the solver; f and g are device pointers when opt.inputs_on_device.
+int simplify(ts_ctx* ctx, const float* f, const Grid& grid, const ts_signal& sig,
+             const ts_options& opt, float* g, ts_report* rep);
+
+// Exact W2^2 assignment of one dimension on the augmented diagrams
+// (Eq. 1, q = 2): match[i] = target index or -1 (diagonal).  Pairs with
+// c(p,q) >= diag(p) + diag(q) are excluded.  Returns the optimal cost.
+double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd,
+                    const std::vector<double>& qb, const std::vector<double>& qd,
+                    std::vector<int>* match);
+
+}  // namespace ts
