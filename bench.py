@@ -1,0 +1,186 @@
+"""Benchmark: the simplification solver's hot path on one MI355X.
+
+Workload: the 256^3 filament field (32 random tubes + N(0, 0.02^2) noise,
+seed 0); non-signal pairs are the saddle-saddle pairs with persistence below
+0.1 * range, every other pair is signal.
+
+A step is one solver iteration (Alg. 1): gradient step, persistence map
+(order, lower-star gradient, critical cells, the three pairings, diagram),
+still-pair join and exact assignment.  The timed region runs `--steps`
+iterations from the input field with the field already resident in HBM
+(one ts_simplify call with j_max = steps; the initial diagram is inside
+the timed region).  value = vertices * steps / time (Mverts/s).
+
+Also reported: the persistence-map throughput (vertices / device time of
+the persistence kernels per map), the per-stage device times (HIP events on
+the library's stream), the roofline of the dominant kernel, and the CPU
+oracle timed on a bounded crop of the same field.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cancel] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "filament_256"
+
+# Algorithmic HBM bytes per vertex of each persistence-map stage (per launch
+# = per map): what the stage must read and write at minimum.
+ALGO_BYTES_PER_VERTEX = {
+    "K1 order keys": 4 + 8,      # read f, write (key, id)
+    "K1 radix sort": 8 + 8,      # read (key, id), write sorted (key, id)
+    "K2 rank": 4 + 8,            # read sorted id, write rank and order
+    "K3 gradient": 4 + 16 + 4,   # read rank, write 16-byte code and descending neighbour
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--dims", type=int, nargs=3, default=None)
+    ap.add_argument("--cancel", action="store_true",
+                    help="also run the solver to full cancellation (or j_max)")
+    ap.add_argument("--j-max", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-crop", type=int, default=48)
+    ap.add_argument("--diag-reps", type=int, default=3)
+    return ap.parse_args()
+
+
+def cpu_baseline(f, crop, signal):
+    """The oracle on a crop of the field: per-iteration time of its solver
+    (two iterations minus the initial diagram), single-threaded."""
+    import oracle
+    oracle.build()
+    c = np.ascontiguousarray(f[:crop, :crop, :crop])
+    thr, mask, ties = signal
+    dims = [d for d in range(3) if (mask >> d) & 1]
+    t0 = time.perf_counter()
+    oracle.simplify(c, threshold=thr, nonsignal_dims=dims, ties_signal=ties, j_max=0)
+    t1 = time.perf_counter()
+    _, rep = oracle.simplify(c, threshold=thr, nonsignal_dims=dims, ties_signal=ties, j_max=2)
+    t2 = time.perf_counter()
+    iters = max(rep.iterations, 1)
+    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / iters
+    return {"value": c.size / per_iter / 1e6, "unit": "Mverts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{crop}^3 crop of the same field, {iters} solver iterations "
+                      f"(time of 2 iterations minus the initial diagram)",
+            "persistence_map_mverts_s": c.size / (t1 - t0) / 1e6}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2407_12399_amd as ts
+    from paper_2407_12399_amd import fields
+
+    torch.cuda.set_device(0)
+    w = fields.WORKLOADS[WORKLOAD]
+    dims = tuple(args.dims) if args.dims else w["dims"]
+    print(f"[bench] generating {WORKLOAD} {dims} seed {args.seed}", file=sys.stderr, flush=True)
+    f = fields.workload(WORKLOAD, args.seed, dims=dims)
+    n = f.size
+    ft = torch.from_numpy(f).cuda()
+    thr, mask, ties = w["signal"]
+    sig = dict(threshold=thr, nonsignal_dims=[d for d in range(3) if (mask >> d) & 1],
+               ties_signal=ties)
+    torch.cuda.synchronize()
+
+    # persistence map alone (device time of the persistence stages per map)
+    print("[bench] persistence map", file=sys.stderr, flush=True)
+    ts.diagram(ft)  # warm-up: workspace allocation, table upload
+    diag_stage = {}
+    wall = []
+    for _ in range(args.diag_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D = ts.diagram(ft)
+        torch.cuda.synchronize()
+        wall.append(time.perf_counter() - t0)
+        for k, v in ts.stage_times().items():
+            diag_stage.setdefault(k, []).append(v)
+    stage_ms = {k: float(np.median(v)) for k, v in diag_stage.items()}
+    pm_ms = sum(stage_ms.values())
+    n_pairs = [int((D["dim"] == d).sum() - (D["essential"] if d == 0 else 0).sum())
+               if d == 0 else int((D["dim"] == d).sum()) for d in range(3)]
+
+    # solver steps
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        ts.simplify(ft, j_max=args.warmup, **sig)
+    torch.cuda.synchronize()
+    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g, rep = ts.simplify(ft, j_max=args.steps, **sig)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = rep.iterations
+    solver_stage = ts.stage_times()
+    value = n * steps / dt / 1e6 if steps > 0 else 0.0
+
+    # dominant persistence kernel and its roofline
+    dom = max((k for k in stage_ms if k in ALGO_BYTES_PER_VERTEX), key=lambda k: stage_ms[k])
+    algo_bytes = ALGO_BYTES_PER_VERTEX[dom] * n
+    achieved = algo_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": stage_ms[dom]}
+
+    out = {
+        "metric": "time to full non-signal cancellation (s) + persistence-map Mverts/s at 256^3",
+        "value": value, "unit": "Mverts/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": dt / max(steps, 1) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "dims": list(dims), "seed": args.seed,
+                   "signal": "non-signal = saddle-saddle pairs with persistence < 0.1 range",
+                   "step": "one solver iteration (update + persistence map + assignment)"},
+        "persistence_map_mverts_s": n / (pm_ms * 1e-3) / 1e6,
+        "persistence_map_ms": pm_ms,
+        "persistence_map_wall_ms": float(np.median(wall)) * 1e3,
+        "diagram_pairs": {"d0": n_pairs[0], "d1": n_pairs[1], "d2": n_pairs[2]},
+        "stage_ms": stage_ms,
+        "solver": {"iterations": steps, "loss0": rep.loss0, "loss": rep.loss,
+                   "max_nonsignal_pers_rel": rep.max_nonsignal_pers / rep.range,
+                   "persistence_s": rep.persistence_s, "assign_s": rep.assign_s,
+                   "update_s": rep.update_s, "n_reduced_last": rep.n_reduced,
+                   "n_still_last": rep.n_still, "n_targets": rep.n_targets,
+                   "stage_ms_total": solver_stage},
+        "roofline": roofline,
+    }
+    if args.cancel:
+        print(f"[bench] full solve (j_max {args.j_max})", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, rc = ts.simplify(ft, j_max=args.j_max, **sig)
+        torch.cuda.synchronize()
+        out["time_to_cancel_s"] = time.perf_counter() - t0 if rc.cancelled else None
+        out["cancel_run"] = {"iterations": rc.iterations, "cancelled": rc.cancelled,
+                             "wall_s": time.perf_counter() - t0,
+                             "max_nonsignal_pers_rel": rc.max_nonsignal_pers / rc.range,
+                             "linf": rc.linf, "max_signal_disp": rc.max_signal_disp}
+    if not args.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(f, args.cpu_crop, w["signal"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

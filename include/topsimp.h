@@ -171,6 +171,16 @@ int ts_critical(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_d
 int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
              ts_pair* out, int64_t capacity, int64_t* n_out);
 
+/* Exact W2^2 assignment of one dimension (Eq. 1 with q = 2 on the augmented
+ * diagrams, Sec. 2.3 and 4.3), as used by ts_simplify for the pairs that are
+ * not still.  Host arrays: points (pb[i], pd[i]), targets (qb[j], qd[j]);
+ * match[i] receives the target index or -1 (diagonal); *cost the optimal
+ * total (matched squared distances + diagonal costs of everything else).
+ * A point and a target with c(p,q) >= diag(p) + diag(q) are never matched.
+ * Needs no context and no GPU. */
+int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
+              const double* qd, int32_t* match, double* cost);
+
 /* Per-kernel device time (ms) of the last ts_diagram / ts_simplify call,
  * measured with HIP events on the context's stream: stage_ms[i] for the
  * stage named stage_names[i] (NULL-terminated list).  Returns the count. */

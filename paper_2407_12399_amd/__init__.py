@@ -67,7 +67,7 @@ _lib = None
 _ctx = {}
 
 EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_simplify",
-           "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_stage_times"]
+           "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_stage_times"]
 
 
 def lib():
@@ -88,6 +88,7 @@ def lib():
         L.ts_gradient.argtypes = [P, P, P, i32, P, P, P]
         L.ts_critical.argtypes = [P, P, P, i32, P, P, i64, P]
         L.ts_pairs.argtypes = [P, P, P, i32, P, i64, P]
+        L.ts_assign.argtypes = [i64, P, P, i64, P, P, P, P]
         L.ts_stage_times.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_char_p)),
                                      ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
         for fn in EXPORTS:
@@ -222,6 +223,18 @@ def critical(field):
         m = int(counts.sum())
         od, oi = od[:m], oi[:m]
         return [oi[od == d].copy() for d in range(4)]
+
+
+def assign(pb, pd, qb, qd):
+    """Exact one-dimension assignment (host only): (match, cost)."""
+    pb, pd, qb, qd = (np.ascontiguousarray(a, dtype=np.float64) for a in (pb, pd, qb, qd))
+    match = np.empty(max(len(pb), 1), np.int32)
+    cost = np.zeros(1, np.float64)
+    rc = lib().ts_assign(len(pb), _ptr(pb), _ptr(pd), len(qb), _ptr(qb), _ptr(qd), _ptr(match),
+                         _ptr(cost))
+    if rc != 0:
+        raise TopsimpError(rc, "ts_assign failed")
+    return match[: len(pb)].copy(), float(cost[0])
 
 
 def stage_times():

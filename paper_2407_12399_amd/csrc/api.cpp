@@ -363,6 +363,24 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
   });
 }
 
+int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
+              const double* qd, int32_t* match, double* cost) {
+  if (n_pts < 0 || n_tgt < 0 || !match || !cost) return TS_ERR_ARG;
+  if ((n_pts > 0 && (!pb || !pd)) || (n_tgt > 0 && (!qb || !qd))) return TS_ERR_ARG;
+  try {
+    std::vector<double> PB(pb, pb + n_pts), PD(pd, pd + n_pts), QB(qb, qb + n_tgt),
+        QD(qd, qd + n_tgt);
+    std::vector<int> m;
+    *cost = assign_reduced(PB, PD, QB, QD, &m);
+    for (int64_t i = 0; i < n_pts; ++i) match[i] = m[i];
+    return TS_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return TS_ERR_INTERNAL;
+  }
+}
+
 int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** ms) {
   if (!ctx || !names || !ms) return TS_ERR_ARG;
   *names = ctx->stage_names.empty() ? nullptr : ctx->stage_names.data();

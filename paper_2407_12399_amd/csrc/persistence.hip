@@ -27,6 +27,8 @@
 #include <algorithm>
 #include <array>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -653,6 +655,11 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
 // Lookup helpers
 // ======================================================================
 
+__global__ void k_iota_from(uint32_t* a, int64_t n, uint32_t base) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = base + uint32_t(i);
+}
+
 __global__ void k_iota(uint32_t* a, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = uint32_t(i);
@@ -717,16 +724,32 @@ __global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Grid
   list[i] = uint32_t(i);
 }
 
-// One hooking round of the union-find with the elder rule.
-// prio(i) = i (ascending order) or nedges-1-i (descending order).
+// Union-find with the elder rule, in rounds.  Every component finds its
+// lowest outgoing edge (hook); then every component whose lowest outgoing
+// edge leads to a component with an older representative joins it, and its
+// representative dies at that edge (link).  That is the sequential sweep's
+// decision: any path from the representative to an older node leaves its
+// component through an edge no lower than the lowest outgoing one, and the
+// other side reaches its older representative through edges no higher than
+// it.  prio(i) = i (increasing order) or nedges-1-i (decreasing order).
+__device__ __forceinline__ int uf_find(int32_t* parent, int x) {
+  while (true) {
+    const int p = parent[x];
+    if (p == x) return x;
+    const int gp = parent[p];
+    if (gp != p) parent[x] = gp;  // path halving (any ancestor is a valid parent)
+    x = gp;
+  }
+}
+
 __global__ void k_uf_hook(const uint32_t* __restrict__ list, const unsigned int* __restrict__ nlist,
                           int32_t* __restrict__ ca, int32_t* __restrict__ cb,
-                          const int32_t* __restrict__ parent, unsigned int* __restrict__ best,
+                          int32_t* __restrict__ parent, unsigned int* __restrict__ best,
                           uint8_t* __restrict__ state, int descending, int64_t nedges) {
   const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= *nlist) return;
   const uint32_t i = list[j];
-  const int a = parent[ca[i]], b = parent[cb[i]];
+  const int a = uf_find(parent, ca[i]), b = uf_find(parent, cb[i]);
   ca[i] = a;
   cb[i] = b;
   if (a == b) {
@@ -748,11 +771,10 @@ struct PairOut {
   int64_t cap;
 };
 
-// Merge along the edges that are the lowest outgoing edge of both of their
-// components; the younger component's representative dies.
-//   dual == 0: nodes are minima (index 0 = oldest); pair (min, edge)
+//   dual == 0: nodes are minima by increasing key (smaller index = older);
+//              pair (min, edge)
 //   dual == 1: nodes are maxima by increasing key and the outside (index
-//              nnodes-1, oldest); pair (triangle, max tet)
+//              nnodes-1); larger index = older; pair (triangle, max tet)
 __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int* __restrict__ nlist,
                           const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
                           int32_t* __restrict__ parent, const unsigned int* __restrict__ best,
@@ -760,22 +782,18 @@ __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int*
                           unsigned int* __restrict__ nnext, int dual, int64_t nedges,
                           const int32_t* __restrict__ cell_id, const uint64_t* __restrict__ cell_key,
                           const int32_t* __restrict__ node_id, const uint64_t* __restrict__ node_key,
-                          int64_t outside, PairOut po) {
+                          PairOut po) {
   const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= *nlist) return;
   const uint32_t i = list[j];
   if (state[i] != 0) return;
   const int a = ca[i], b = cb[i];
   const unsigned int pr = dual ? unsigned(nedges - 1 - i) : i;
-  if (best[a] == pr && best[b] == pr) {
-    int younger, elder;
-    if (!dual) {
-      younger = max(a, b);
-      elder = min(a, b);
-    } else {
-      younger = min(a, b);
-      elder = max(a, b);
-    }
+  // the younger endpoint component may join the older one along its lowest edge
+  const bool a_older = dual ? (a > b) : (a < b);
+  const int younger = a_older ? b : a;
+  const int elder = a_older ? a : b;
+  if (best[younger] == pr) {
     parent[younger] = elder;
     state[i] = 2;
     const unsigned long long p = atomicAdd(po.count, 1ull);
@@ -794,7 +812,6 @@ __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int*
         po.dkey[p] = node_key[younger];
       }
     }
-    (void)outside;
   } else {
     const unsigned int q = atomicAdd(nnext, 1u);
     next[q] = i;
@@ -806,7 +823,7 @@ __global__ void k_uf_reset(int32_t* __restrict__ parent, unsigned int* __restric
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nnodes) return;
   best[c] = 0xFFFFFFFFu;
-  parent[c] = parent[parent[c]];
+  uf_find(parent, int(c));
 }
 
 __global__ void k_uf_init(int32_t* __restrict__ parent, unsigned int* __restrict__ best,
@@ -1114,40 +1131,50 @@ __global__ void k_d1_boundary(const uint32_t* __restrict__ cols, int64_t ncols,
   }
 }
 
-// Parallel reduction round: owner[p] = lowest column with pivot p.
-__global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, int64_t ncols,
-                           const uint32_t* __restrict__ pool, unsigned int* __restrict__ owner) {
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// Parallel Z2 reduction.  owner[p] is the lowest column whose current pivot
+// is p (never reset: a column only changes while it does not own its pivot).
+// A round: every active column claims its pivot (atomicMin); an owner that
+// loses its pivot to a lower column becomes active again; then every active
+// column that does not own its pivot adds the owner's column (a column of
+// lower index, so the result is a valid left-to-right reduction whose pivots
+// are those of the standard algorithm).
+
+__device__ __forceinline__ void d1_claim_one(uint32_t c, const uint64_t* __restrict__ col_desc,
+                                             const uint32_t* __restrict__ pool,
+                                             unsigned int* __restrict__ owner,
+                                             unsigned int* __restrict__ mark, unsigned int round,
+                                             uint32_t* __restrict__ list,
+                                             unsigned int* __restrict__ nlist) {
   const uint64_t d = col_desc[c];
-  const uint32_t len = uint32_t(d & 0xFFFFFFu);
-  if (len == 0) return;
+  if ((d & 0xFFFFFFu) == 0) return;
   const uint32_t piv = pool[d >> 24];
-  atomicMin(&owner[piv], uint32_t(c));
+  const unsigned int old = atomicMin(&owner[piv], c);
+  if (old != 0xFFFFFFFFu && old > c) {
+    // `old` lost its pivot: it joins this round's active set once
+    if (atomicExch(&mark[old], round) != round) list[atomicAdd(nlist, 1u)] = old;
+  }
 }
 
-__global__ void k_d1_reduce(uint64_t* __restrict__ col_desc, int64_t ncols, uint32_t* __restrict__ pool,
-                            ColPool pc, const unsigned int* __restrict__ owner,
-                            unsigned int* __restrict__ nconflict, int* __restrict__ err,
-                            int* __restrict__ pool_full) {
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// returns 1 if the column still has to be reduced further, 0 if it owns its
+// pivot; 2 if the pool is full (column unchanged)
+__device__ __forceinline__ int d1_reduce_one(uint32_t c, uint64_t* __restrict__ col_desc,
+                                             uint32_t* __restrict__ pool, const ColPool& pc,
+                                             const unsigned int* __restrict__ owner,
+                                             int* __restrict__ err, uint32_t lo) {
+ for (;;) {
   const uint64_t d = col_desc[c];
   const uint32_t len = uint32_t(d & 0xFFFFFFu);
-  if (len == 0) return;
+  if (len == 0) return 0;
   const uint64_t off_c = d >> 24;
   const uint32_t piv = pool[off_c];
   const unsigned int o = owner[piv];
-  if (o == uint32_t(c)) return;
-  atomicAdd(nconflict, 1u);
+  if (o == c) return 0;
+  if (o > c) return 1;  // unowned, or owned by a later column: claim it next round
   const uint64_t od = col_desc[o];
   const uint32_t olen = uint32_t(od & 0xFFFFFFu);
   const uint64_t off_o = od >> 24;
   const unsigned long long at = atomicAdd(pc.top, (unsigned long long)(len + olen));
-  if ((int64_t)(at + len + olen) > pc.cap) {
-    atomicOr(pool_full, 1);
-    return;  // retried next round after the pool has grown
-  }
+  if ((int64_t)(at + len + olen) > pc.cap) return 2;
   // symmetric difference of two descending lists
   uint32_t i = 0, j = 0, w = 0;
   while (i < len || j < olen) {
@@ -1160,8 +1187,103 @@ __global__ void k_d1_reduce(uint64_t* __restrict__ col_desc, int64_t ncols, uint
       ++j;
     }
   }
-  if (w == 0) atomicOr(err, 64);
+  if (w == 0) atomicOr(err, 64);  // a negative column cannot vanish
   col_desc[c] = (uint64_t(at) << 24) | uint64_t(w);
+  if (o >= lo || w == 0) return 1;
+  // `o` belongs to an earlier, finished block: its column is final, so keep
+  // reducing against final owners without waiting for the next round
+ }
+}
+
+// Every member of the active list carries the current round in mark[].
+__global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
+                           unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                           unsigned int round, uint32_t* __restrict__ list,
+                           unsigned int* __restrict__ nlist, unsigned int n0) {
+  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n0) return;
+  d1_claim_one(list[j], col_desc, pool, owner, mark, round, list, nlist);
+}
+
+__global__ void k_d1_reduce(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
+                            const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                            unsigned int round, const uint32_t* __restrict__ list,
+                            const unsigned int* __restrict__ nlist, uint32_t* __restrict__ next,
+                            unsigned int* __restrict__ nnext, int* __restrict__ err,
+                            int* __restrict__ pool_full, uint32_t lo) {
+  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= *nlist) return;
+  const uint32_t c = list[j];
+  const int r = d1_reduce_one(c, col_desc, pool, pc, owner, err, lo);
+  if (r == 2) atomicOr(pool_full, 1);
+  if (r != 0) {
+    mark[c] = round + 1;
+    next[atomicAdd(nnext, 1u)] = c;
+  }
+}
+
+// The tail of the reduction in one workgroup: same rounds, workgroup
+// barriers instead of kernel boundaries.  Exits when no column is active,
+// when the pool is full (resumable) or after max_rounds (error flag).
+__global__ void __launch_bounds__(1024)
+k_d1_tail(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
+          unsigned int* __restrict__ owner, unsigned int* __restrict__ mark, unsigned int round0,
+          uint32_t* __restrict__ listA, uint32_t* __restrict__ listB, unsigned int* __restrict__ counts,
+          int* __restrict__ err, int* __restrict__ pool_full, int max_rounds,
+          unsigned int* __restrict__ rounds_out, uint32_t lo) {
+  __shared__ unsigned int s_na, s_nb, s_n0;
+  __shared__ int s_full;
+  uint32_t* A = listA;
+  uint32_t* B = listB;
+  if (threadIdx.x == 0) {
+    s_na = counts[0];
+    s_full = 0;
+  }
+  __syncthreads();
+  unsigned int round = round0 - 1;
+  int r = 0;
+  while (s_na > 0) {
+    if (r >= max_rounds) {
+      if (threadIdx.x == 0) atomicOr(err, 256);
+      break;
+    }
+    ++round;
+    ++r;
+    if (threadIdx.x == 0) {
+      s_n0 = s_na;
+      s_nb = 0;
+    }
+    __syncthreads();
+    const unsigned int n0 = s_n0;
+    for (unsigned int j = threadIdx.x; j < n0; j += blockDim.x)
+      d1_claim_one(A[j], col_desc, pool, owner, mark, round, A, &s_na);
+    __threadfence_block();
+    __syncthreads();
+    const unsigned int n1 = s_na;
+    for (unsigned int j = threadIdx.x; j < n1; j += blockDim.x) {
+      const uint32_t c = A[j];
+      const int rr = d1_reduce_one(c, col_desc, pool, pc, owner, err, lo);
+      if (rr == 2) s_full = 1;
+      if (rr != 0) {
+        mark[c] = round + 1;
+        B[atomicAdd(&s_nb, 1u)] = c;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    uint32_t* t = A;
+    A = B;
+    B = t;
+    if (threadIdx.x == 0) s_na = s_nb;
+    __syncthreads();
+    if (s_full) break;
+  }
+  if (threadIdx.x == 0) {
+    counts[0] = s_na;
+    if (s_full) *pool_full = 1;
+    rounds_out[0] = unsigned(r);
+    rounds_out[1] = (A == listA) ? 0u : 1u;  // which buffer holds the active list
+  }
 }
 
 __global__ void k_fill_u32(unsigned int* a, int64_t n, unsigned int v) {
@@ -1323,7 +1445,7 @@ int union_find_rounds(ts_ctx* ctx, int64_t nedges, int64_t nnodes, int32_t* ca, 
     k_uf_hook<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, dual, nedges);
     k_uf_link<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, nxt, nnxt,
                                               dual, nedges, cell_id, cell_key, node_id, node_key,
-                                              nnodes - 1, po);
+                                              po);
     k_uf_reset<<<blocks_for(nnodes), 256, 0, s>>>(parent, best, nnodes);
     TS_HIP(hipGetLastError());
     h_n = read_scalar(nnxt, s);
@@ -1572,52 +1694,92 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
 
     ctx->timer.start("K7 d1 reduction");
     unsigned int* owner = ws.get<unsigned int>("d1.owner", ne + 1);
-    unsigned int* nconf = ws.get<unsigned int>("d1.nconf", 1);
+    unsigned int* mark = ws.get<unsigned int>("d1.mark", ncols + 1);
+    uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
+    uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
+    unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 4);
     int* pool_full = ws.get<int>("d1.full", 1);
-    int rounds = 0;
-    for (;;) {
-      ++rounds;
-      k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
-      TS_HIP(hipMemsetAsync(nconf, 0, sizeof(unsigned int), s));
-      TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
-      k_d1_claim<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, pool.data, owner);
-      k_d1_reduce<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, pool.data, pool, owner, nconf,
-                                                    err, pool_full);
-      TS_HIP(hipGetLastError());
-      const unsigned int h_conf = read_scalar(nconf, s);
-      if (h_conf == 0) break;
-      if (read_scalar(pool_full, s)) {
-        // compact live columns into a larger pool
-        std::vector<uint64_t> desc(ncols);
-        TS_HIP(hipMemcpyAsync(desc.data(), col_desc, ncols * sizeof(uint64_t),
-                              hipMemcpyDeviceToHost, s));
-        TS_HIP(hipStreamSynchronize(s));
-        int64_t live = 0;
-        for (uint64_t d : desc) live += int64_t(d & 0xFFFFFFu);
-        const int64_t ncap = std::max<int64_t>(2 * pool_cap, 4 * live + (1 << 20));
-        uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
-        int64_t at = 0;
-        for (int64_t c = 0; c < ncols; ++c) {
-          const int64_t len = int64_t(desc[c] & 0xFFFFFFu);
-          if (len > 0)
-            TS_HIP(hipMemcpyAsync(np + at, pool.data + (desc[c] >> 24), len * sizeof(uint32_t),
-                                  hipMemcpyDeviceToDevice, s));
-          desc[c] = (uint64_t(at) << 24) | uint64_t(len);
-          at += len;
-        }
-        TS_HIP(hipMemcpyAsync(col_desc, desc.data(), ncols * sizeof(uint64_t),
-                              hipMemcpyHostToDevice, s));
-        TS_HIP(hipStreamSynchronize(s));
-        std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
-        pool.data = np;
-        pool_cap = ncap;
-        pool.cap = ncap;
-        unsigned long long top = at;
-        TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
-        TS_HIP(hipStreamSynchronize(s));
-        pool_hint = std::max(pool_hint, pool_cap);
+    unsigned int* tail_info = ws.get<unsigned int>("d1.tinfo", 2);
+    k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
+    k_fill_u32<<<blocks_for(ncols), 256, 0, s>>>(mark, ncols, 1u);
+    // grows the pool, compacting the live columns
+    auto grow_pool = [&]() {
+      std::vector<uint64_t> desc(ncols);
+      TS_HIP(hipMemcpyAsync(desc.data(), col_desc, ncols * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s));
+      TS_HIP(hipStreamSynchronize(s));
+      int64_t live = 0;
+      for (uint64_t d : desc) live += int64_t(d & 0xFFFFFFu);
+      const int64_t ncap = std::max<int64_t>(2 * pool_cap, 4 * live + (1 << 20));
+      uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
+      int64_t at = 0;
+      for (int64_t c = 0; c < ncols; ++c) {
+        const int64_t len = int64_t(desc[c] & 0xFFFFFFu);
+        if (len > 0)
+          TS_HIP(hipMemcpyAsync(np + at, pool.data + (desc[c] >> 24), len * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, s));
+        desc[c] = (uint64_t(at) << 24) | uint64_t(len);
+        at += len;
       }
-      if (rounds > 100000) throw Error(TS_ERR_INTERNAL, "saddle-saddle reduction did not converge");
+      TS_HIP(hipMemcpyAsync(col_desc, desc.data(), ncols * sizeof(uint64_t),
+                            hipMemcpyHostToDevice, s));
+      TS_HIP(hipStreamSynchronize(s));
+      std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
+      pool.data = np;
+      pool_cap = ncap;
+      pool.cap = ncap;
+      unsigned long long top = at;
+      TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
+      TS_HIP(hipStreamSynchronize(s));
+      pool_hint = std::max(pool_hint, pool_cap);
+    };
+    const unsigned int kTail = 8192;
+    // Columns are reduced block by block in index order; a block's columns
+    // only interact with each other once every earlier column is final.
+    const int64_t kBlock = 1 << 16;
+    unsigned int round = 1;  // round to run next; active members carry it in mark[]
+    int rounds = 0;
+    uint32_t* A = listA;
+    uint32_t* B = listB;
+    for (int64_t lo = 0; lo < ncols; lo += kBlock) {
+    const int64_t hi = std::min<int64_t>(ncols, lo + kBlock);
+    unsigned int h_n = unsigned(hi - lo);
+    k_iota_from<<<blocks_for(h_n), 256, 0, s>>>(A, h_n, uint32_t(lo));
+    k_fill_u32<<<1, 1, 0, s>>>(cnt, 1, h_n);
+    k_fill_u32<<<blocks_for(h_n), 256, 0, s>>>(mark + lo, h_n, round);
+    while (h_n > 0) {
+      if (h_n > kTail) {
+        ++rounds;
+        TS_HIP(hipMemsetAsync(cnt + 1, 0, sizeof(unsigned int), s));
+        TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
+        k_d1_claim<<<blocks_for(h_n), 256, 0, s>>>(col_desc, pool.data, owner, mark, round, A, cnt,
+                                                   h_n);
+        // displaced owners were appended: the list may have grown
+        const unsigned int n1 = read_scalar(cnt, s);
+        k_d1_reduce<<<blocks_for(n1), 256, 0, s>>>(col_desc, pool.data, pool, owner, mark, round, A,
+                                                   cnt, B, cnt + 1, err, pool_full, uint32_t(lo));
+        ++round;
+        TS_HIP(hipGetLastError());
+        h_n = read_scalar(cnt + 1, s);
+        TS_HIP(hipMemcpyAsync(cnt, cnt + 1, sizeof(unsigned int), hipMemcpyDeviceToDevice, s));
+        std::swap(A, B);
+        if (read_scalar(pool_full, s)) grow_pool();
+      } else {
+        TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
+        k_d1_tail<<<1, 1024, 0, s>>>(col_desc, pool.data, pool, owner, mark, round, A, B, cnt, err,
+                                     pool_full, 1 << 22, tail_info, uint32_t(lo));
+        TS_HIP(hipGetLastError());
+        unsigned int info[2];
+        TS_HIP(hipMemcpyAsync(info, tail_info, sizeof(info), hipMemcpyDeviceToHost, s));
+        h_n = read_scalar(cnt, s);
+        rounds += int(info[0]);
+        round += info[0];
+        if (info[1]) std::swap(A, B);
+        if (read_scalar(pool_full, s)) grow_pool();
+        if (read_scalar(err, s)) break;
+      }
+      if (rounds > (1 << 23)) throw Error(TS_ERR_INTERNAL, "saddle-saddle reduction did not converge");
+    }
     }
     R->rounds_d1 = rounds;
     k_d1_pairs<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, cols, pool.data, R->cid[1],
@@ -1654,6 +1816,12 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   R->pdeath = po.death;
   R->pbkey = po.bkey;
   R->pdkey = po.dkey;
+
+  if (std::getenv("TS_TRACE"))
+    std::fprintf(stderr,
+                 "[topsimp] n=%d crit=%lld/%lld/%lld/%lld rounds d0=%d d2=%d d1=%d cols=%lld\n", n,
+                 (long long)nmin, (long long)ne, (long long)ntri, (long long)nmax, R->rounds_d0,
+                 R->rounds_d2, R->rounds_d1, (long long)ncols);
 
   // ---- K8: diagram order ----
   ctx->timer.start("K8 diagram");

@@ -20,4 +20,16 @@ double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd
                     const std::vector<double>& qb, const std::vector<double>& qd,
                     std::vector<int>* match);
 
+// Near-optimal assignment of the same problem by an epsilon-scaled auction;
+// the total cost is within (points + targets) * eps_rel * W of the optimum,
+// W = max diag(p) + max diag(q).
+double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
+                      const std::vector<double>& qb, const std::vector<double>& qd,
+                      std::vector<int>* match, double eps_rel);
+
+// The solver's choice: exact up to a problem size, the auction above.
+double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
+                      const std::vector<double>& qb, const std::vector<double>& qd,
+                      std::vector<int>* match);
+
 }  // namespace ts

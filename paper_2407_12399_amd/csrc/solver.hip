@@ -13,9 +13,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <queue>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -185,6 +189,10 @@ void canonical_form(const std::vector<Pt>& P, const std::vector<int>& red, const
   }
 }
 
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 struct Solver {
   std::vector<Tgt> T;
   int ess_target = -1;
@@ -289,8 +297,27 @@ struct Solver {
           qd.push_back(T[j].d);
         }
       if (pi.empty()) continue;
+      if (const char* dir = std::getenv("TS_DUMP_ASSIGN")) {
+        static int seq = 0;
+        const std::string path = std::string(dir) + "/assign_" + std::to_string(seq++) + "_d" +
+                                 std::to_string(dim) + ".bin";
+        if (FILE* fp = std::fopen(path.c_str(), "wb")) {
+          const int64_t mm = int64_t(pb.size()), kk = int64_t(qb.size());
+          std::fwrite(&mm, 8, 1, fp);
+          std::fwrite(&kk, 8, 1, fp);
+          std::fwrite(pb.data(), 8, mm, fp);
+          std::fwrite(pd.data(), 8, mm, fp);
+          std::fwrite(qb.data(), 8, kk, fp);
+          std::fwrite(qd.data(), 8, kk, fp);
+          std::fclose(fp);
+        }
+      }
       std::vector<int> m;
-      assign_exact(pb, pd, qb, qd, &m);
+      const double t0 = now_s();
+      assign_reduced(pb, pd, qb, qd, &m);
+      if (std::getenv("TS_TRACE"))
+        std::fprintf(stderr, "[topsimp] assign dim %d: %zu points, %zu targets, %.3f s\n", dim,
+                     pb.size(), qb.size(), now_s() - t0);
       for (size_t s = 0; s < pi.size(); ++s) (*phi)[pi[s]] = m[s] >= 0 ? tj[m[s]] : -1;
     }
     canonical_form(P, red, T, phi);
@@ -329,120 +356,447 @@ void fetch_points(ts_ctx* ctx, const PersistenceResult& R, const float* x, std::
   }
 }
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 }  // namespace
 
 // ---------------------------------------------------------------- assignment
 
-double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd,
-                    const std::vector<double>& qb, const std::vector<double>& qd,
-                    std::vector<int>* match) {
-  // Augmented bipartite graph: left = points (m) + diagonal copies of targets
-  // (k); right = targets (k) + diagonal copies of points (m).  Edges:
-  //   point i - target j        c(p_i, q_j), only if c < diag(p_i) + diag(q_j)
-  //   point i - diag copy of i  diag(p_i)
-  //   diag copy of j - target j diag(q_j)
-  //   diag copy of j - diag copy of i   0, for the same (i, j) as above
-  // (the last block only needs the pairs kept in the first one: a matching
-  // that uses point i - target j can always pair the two diagonal copies).
-  const int m = int(pb.size()), k = int(qb.size());
-  match->assign(m, -1);
-  const int N = m + k;
-  if (N == 0) return 0.0;
-  struct E {
-    int to;
-    double c;
-  };
-  std::vector<std::vector<E>> adj(N);
-  std::vector<double> dp(m), dq(k);
-  for (int i = 0; i < m; ++i) dp[i] = diag_cost(pb[i], pd[i]);
-  for (int j = 0; j < k; ++j) dq[j] = diag_cost(qb[j], qd[j]);
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < k; ++j) {
-      const double c = pair_cost(pb[i], pd[i], qb[j], qd[j]);
-      if (c < dp[i] + dq[j]) {
-        adj[i].push_back({j, c});
-        adj[m + j].push_back({k + i, 0.0});
-      }
-    }
-    adj[i].push_back({k + i, dp[i]});
-  }
-  for (int j = 0; j < k; ++j) adj[m + j].push_back({j, dq[j]});
+namespace {
 
-  // successive shortest augmenting paths with potentials (Dijkstra)
-  const double INF = std::numeric_limits<double>::infinity();
-  std::vector<int> ml(N, -1), mr(N, -1);
-  std::vector<double> mc(N, 0.0), hl(N, 0.0), hr(N, 0.0), dl(N), dr(N);
-  std::vector<int> prev_r(N);
-  std::vector<int> touched_l, touched_r;
-  typedef std::pair<double, int> QI;  // (dist, node): node < N left, >= N right
-  for (int s = 0; s < N; ++s) {
-    std::fill(dl.begin(), dl.end(), INF);
-    std::fill(dr.begin(), dr.end(), INF);
-    std::priority_queue<QI, std::vector<QI>, std::greater<QI>> pq;
-    dl[s] = 0.0;
-    pq.push({0.0, s});
-    int found = -1;
-    while (!pq.empty()) {
-      const QI top = pq.top();
-      pq.pop();
-      const double d = top.first;
-      if (top.second < N) {
-        const int l = top.second;
-        if (d > dl[l]) continue;
-        for (const E& e : adj[l]) {
-          if (ml[l] == e.to) continue;
-          const double nd = d + e.c + hl[l] - hr[e.to];
-          if (nd < dr[e.to]) {
-            dr[e.to] = nd;
-            prev_r[e.to] = l;
-            pq.push({nd, N + e.to});
+// 2D KD-tree over the targets (birth, death).  Every target j carries a
+// score s_j (or "masked"); a node keeps the largest unmasked score below it.
+// best(p) returns the unmasked target minimising |p - q_j|^2 - s_j.
+struct KDTree {
+  struct Node {
+    double x0, x1, y0, y1, smax;
+    int left, right, parent, begin, end;
+  };
+  std::vector<Node> nodes;
+  std::vector<int> idx, leaf_of;
+  std::vector<double> s;
+  std::vector<char> masked;
+  const double* X = nullptr;
+  const double* Y = nullptr;
+  static constexpr double NEG = -std::numeric_limits<double>::infinity();
+
+  void build(const double* x, const double* y, int k) {
+    X = x;
+    Y = y;
+    idx.resize(k);
+    for (int j = 0; j < k; ++j) idx[j] = j;
+    leaf_of.assign(k, -1);
+    s.assign(k, 0.0);
+    masked.assign(k, 0);
+    nodes.clear();
+    if (k > 0) make(0, k, -1);
+  }
+  int make(int b, int e, int parent) {
+    Node nd;
+    nd.x0 = nd.y0 = std::numeric_limits<double>::infinity();
+    nd.x1 = nd.y1 = -std::numeric_limits<double>::infinity();
+    for (int i = b; i < e; ++i) {
+      nd.x0 = std::min(nd.x0, X[idx[i]]);
+      nd.x1 = std::max(nd.x1, X[idx[i]]);
+      nd.y0 = std::min(nd.y0, Y[idx[i]]);
+      nd.y1 = std::max(nd.y1, Y[idx[i]]);
+    }
+    nd.begin = b;
+    nd.end = e;
+    nd.left = nd.right = -1;
+    nd.parent = parent;
+    nd.smax = NEG;
+    const int id = int(nodes.size());
+    nodes.push_back(nd);
+    if (e - b > 8) {
+      const int mid = (b + e) / 2;
+      const bool byx = (nd.x1 - nd.x0) >= (nd.y1 - nd.y0);
+      std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int a, int c) {
+        return byx ? (X[a] < X[c] || (X[a] == X[c] && a < c))
+                   : (Y[a] < Y[c] || (Y[a] == Y[c] && a < c));
+      });
+      const int l = make(b, mid, id);
+      const int r = make(mid, e, id);
+      nodes[id].left = l;
+      nodes[id].right = r;
+    } else {
+      for (int i = b; i < e; ++i) leaf_of[idx[i]] = id;
+    }
+    return id;
+  }
+  void set_all(const std::vector<double>& sc) {
+    s = sc;
+    std::fill(masked.begin(), masked.end(), 0);
+    for (int i = int(nodes.size()) - 1; i >= 0; --i) refresh(i);
+  }
+  void refresh(int id) {
+    Node& nd = nodes[id];
+    if (nd.left < 0) {
+      double m = NEG;
+      for (int t = nd.begin; t < nd.end; ++t)
+        if (!masked[idx[t]]) m = std::max(m, s[idx[t]]);
+      nd.smax = m;
+    } else {
+      nd.smax = std::max(nodes[nd.left].smax, nodes[nd.right].smax);
+    }
+  }
+  // change target j (score / mask) and the maxima above it
+  void update(int j, double sj, bool mask) {
+    s[j] = sj;
+    masked[j] = mask;
+    for (int id = leaf_of[j]; id >= 0; id = nodes[id].parent) {
+      const double before = nodes[id].smax;
+      refresh(id);
+      if (nodes[id].smax == before && id != leaf_of[j]) break;
+    }
+  }
+  static double d2box(const Node& nd, double px, double py) {
+    const double dx = px < nd.x0 ? nd.x0 - px : (px > nd.x1 ? px - nd.x1 : 0.0);
+    const double dy = py < nd.y0 ? nd.y0 - py : (py > nd.y1 ? py - nd.y1 : 0.0);
+    return dx * dx + dy * dy;
+  }
+  // the two smallest values of |p - q_j|^2 - s_j over unmasked j (depth
+  // first, nearer child first, pruned by the node bounds)
+  mutable std::vector<std::pair<double, int>> stack_;
+  int best2(double px, double py, double* v1, double* v2) const {
+    *v1 = *v2 = std::numeric_limits<double>::infinity();
+    int bj = -1;
+    if (nodes.empty() || nodes[0].smax == NEG) return -1;
+    stack_.clear();
+    stack_.push_back({d2box(nodes[0], px, py) - nodes[0].smax, 0});
+    while (!stack_.empty()) {
+      const auto top = stack_.back();
+      stack_.pop_back();
+      if (top.first > *v2) continue;
+      const Node& nd = nodes[top.second];
+      if (nd.left < 0) {
+        for (int t = nd.begin; t < nd.end; ++t) {
+          const int j = idx[t];
+          if (masked[j]) continue;
+          const double dx = X[j] - px, dy = Y[j] - py;
+          const double v = (dx * dx + dy * dy) - s[j];
+          if (v < *v1 || (v == *v1 && j < bj)) {
+            *v2 = *v1;
+            *v1 = v;
+            bj = j;
+          } else if (v < *v2) {
+            *v2 = v;
           }
         }
       } else {
-        const int r = top.second - N;
-        if (d > dr[r]) continue;
-        if (mr[r] < 0) {
-          found = r;
-          break;
-        }
-        const int l = mr[r];
-        const double nd = d - mc[l] + hr[r] - hl[l];
-        if (nd < dl[l]) {
-          dl[l] = nd;
-          pq.push({nd, l});
+        const Node& L = nodes[nd.left];
+        const Node& R = nodes[nd.right];
+        const double bl = L.smax == NEG ? INFINITY : d2box(L, px, py) - L.smax;
+        const double br = R.smax == NEG ? INFINITY : d2box(R, px, py) - R.smax;
+        // push the farther child first so that the nearer one is visited first
+        if (bl <= br) {
+          if (br <= *v2) stack_.push_back({br, nd.right});
+          if (bl <= *v2) stack_.push_back({bl, nd.left});
+        } else {
+          if (bl <= *v2) stack_.push_back({bl, nd.left});
+          if (br <= *v2) stack_.push_back({br, nd.right});
         }
       }
     }
-    if (found < 0) throw Error(TS_ERR_INTERNAL, "assignment: no augmenting path");
-    const double D = dr[found];
-    for (int l = 0; l < N; ++l) hl[l] += std::min(dl[l], D);
-    for (int r = 0; r < N; ++r) hr[r] += std::min(dr[r], D);
-    // augment
-    int r = found;
-    while (true) {
-      const int l = prev_r[r];
-      const int old = ml[l];
-      double c = 0;
-      for (const E& e : adj[l])
-        if (e.to == r) {
-          c = e.c;
-          break;
+    return bj;
+  }
+  // argmin over unmasked j of |p - q_j|^2 - s_j; ties to the lower index
+  int best(double px, double py, double* val) const {
+    *val = std::numeric_limits<double>::infinity();
+    int bj = -1;
+    if (nodes.empty() || nodes[0].smax == NEG) return -1;
+    typedef std::pair<double, int> NI;  // (lower bound, node)
+    std::priority_queue<NI, std::vector<NI>, std::greater<NI>> todo;
+    todo.push({d2box(nodes[0], px, py) - nodes[0].smax, 0});
+    while (!todo.empty()) {
+      const NI top = todo.top();
+      todo.pop();
+      if (top.first > *val) break;
+      const Node& nd = nodes[top.second];
+      if (nd.left < 0) {
+        for (int t = nd.begin; t < nd.end; ++t) {
+          const int j = idx[t];
+          if (masked[j]) continue;
+          const double dx = X[j] - px, dy = Y[j] - py;
+          const double v = (dx * dx + dy * dy) - s[j];
+          if (v < *val || (v == *val && j < bj)) {
+            *val = v;
+            bj = j;
+          }
         }
-      ml[l] = r;
-      mr[r] = l;
-      mc[l] = c;
-      if (l == s) break;
-      r = old;
+      } else {
+        for (int c : {nd.left, nd.right})
+          if (nodes[c].smax != NEG) todo.push({d2box(nodes[c], px, py) - nodes[c].smax, c});
+      }
+    }
+    return bj;
+  }
+};
+
+}  // namespace
+
+// Forward auction with epsilon scaling (Bertsekas) on the square augmented
+// problem: persons are the points and one diagonal copy per target, objects
+// are the targets and one diagonal copy per point; a point values target j
+// at -c(p,q_j) and its own diagonal copy at -diag(p); the diagonal copy of
+// target j values target j at -diag(q_j) and every point's diagonal copy at
+// 0.  Bids use the KD-tree (best and second-best target) and a lazy heap of
+// the diagonal copies' prices.  The final assignment is within
+// (m + k) * eps_final of the optimum.
+double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
+                      const std::vector<double>& qb, const std::vector<double>& qd,
+                      std::vector<int>* match, double eps_rel) {
+  const int m = int(pb.size()), k = int(qb.size());
+  match->assign(m, -1);
+  std::vector<double> dp(m), dq(k);
+  double maxdp = 0, maxdq = 0;
+  for (int i = 0; i < m; ++i) maxdp = std::max(maxdp, dp[i] = diag_cost(pb[i], pd[i]));
+  for (int j = 0; j < k; ++j) maxdq = std::max(maxdq, dq[j] = diag_cost(qb[j], qd[j]));
+  const double W = std::max(maxdp + maxdq, 1e-300);
+  const int NP = m + k;  // persons: points 0..m-1, target copies m..m+k-1
+  // objects: targets 0..k-1, point copies k..k+m-1
+  std::vector<double> price(k + m, 0.0);
+  std::vector<int> owner(k + m, -1), holds(NP, -1);
+  KDTree tree;
+  tree.build(qb.data(), qd.data(), k);
+  {
+    std::vector<double> sc(k, 0.0);
+    tree.set_all(sc);  // s_j = -price_j
+  }
+  typedef std::pair<double, int> PI;
+  std::priority_queue<PI, std::vector<PI>, std::greater<PI>> copies;  // (price, i), lazy
+  for (int i = 0; i < m; ++i) copies.push({0.0, i});
+  auto two_cheapest = [&](int* i1, double* p1, double* p2) {
+    while (!copies.empty() && copies.top().first != price[k + copies.top().second]) copies.pop();
+    *i1 = -1;
+    *p1 = *p2 = std::numeric_limits<double>::infinity();
+    if (copies.empty()) return;
+    const PI a = copies.top();
+    copies.pop();
+    while (!copies.empty() && copies.top().first != price[k + copies.top().second]) copies.pop();
+    *i1 = a.second;
+    *p1 = a.first;
+    if (!copies.empty()) *p2 = copies.top().first;
+    copies.push(a);
+  };
+  double eps = W / 4.0;
+  const double eps_final = W * eps_rel;
+  std::vector<int> queue;
+  queue.reserve(NP);
+  for (int phase = 0;; ++phase) {
+    std::fill(owner.begin(), owner.end(), -1);
+    std::fill(holds.begin(), holds.end(), -1);
+    queue.clear();
+    for (int x = 0; x < NP; ++x) queue.push_back(x);
+    size_t head = 0;
+    int64_t bids = 0;
+    while (head < queue.size()) {
+      const int x = queue[head++];
+      if (holds[x] >= 0) continue;
+      double v1, v2;  // best and second-best values
+      int o1;
+      if (x < m) {
+        double c1, c2;
+        const int j = tree.best2(pb[x], pd[x], &c1, &c2);  // c = |p-q|^2 + price
+        const double vd = -dp[x] - price[k + x];
+        v1 = vd;
+        o1 = k + x;
+        v2 = -std::numeric_limits<double>::infinity();
+        if (j >= 0) {
+          if (-c1 > vd || (-c1 == vd && j < k + x)) {
+            v1 = -c1;
+            o1 = j;
+            v2 = std::max(vd, -c2);
+          } else {
+            v2 = -c1;
+          }
+        }
+      } else {
+        const int j = x - m;
+        int i1;
+        double p1, p2;
+        two_cheapest(&i1, &p1, &p2);
+        const double vt = -dq[j] - price[j];
+        if (i1 >= 0 && -p1 > vt) {
+          v1 = -p1;
+          o1 = k + i1;
+          v2 = std::max(vt, -p2);
+        } else {
+          v1 = vt;
+          o1 = j;
+          v2 = i1 >= 0 ? -p1 : -std::numeric_limits<double>::infinity();
+        }
+      }
+      if (v2 == -std::numeric_limits<double>::infinity()) v2 = v1 - W;
+      const double inc = (v1 - v2) + eps;
+      price[o1] += inc;
+      if (o1 < k) tree.update(o1, -price[o1], false);
+      else copies.push({price[o1], o1 - k});
+      const int prev = owner[o1];
+      owner[o1] = x;
+      holds[x] = o1;
+      if (prev >= 0) {
+        holds[prev] = -1;
+        queue.push_back(prev);
+      }
+      if (++bids > int64_t(400) * NP + 1000000)
+        throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
+    }
+    if (std::getenv("TS_TRACE"))
+      std::fprintf(stderr, "[topsimp] auction phase %d eps %.3g bids %lld\n", phase, eps,
+                   (long long)bids);
+    if (eps <= eps_final) break;
+    eps = std::max(eps / 16.0, eps_final);
+  }
+  double total = 0;
+  std::vector<char> used(k, 0);
+  for (int i = 0; i < m; ++i) {
+    const int o = holds[i];
+    if (o < k && pair_cost(pb[i], pd[i], qb[o], qd[o]) < dp[i] + dq[o]) {
+      (*match)[i] = o;
+      used[o] = 1;
+      total += pair_cost(pb[i], pd[i], qb[o], qd[o]);
+    } else {
+      total += dp[i];
     }
   }
-  double total = 0;  // every left node is matched
-  for (int l = 0; l < N; ++l) total += mc[l];
-  for (int i = 0; i < m; ++i) (*match)[i] = ml[i] < k ? ml[i] : -1;
+  for (int j = 0; j < k; ++j)
+    if (!used[j]) total += dq[j];
   return total;
+}
+
+double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd,
+                    const std::vector<double>& qb, const std::vector<double>& qd,
+                    std::vector<int>* match) {
+  // Maximum-weight matching: a point p matched to a target q saves
+  // w(p,q) = diag(p) + diag(q) - c(p,q) over sending both to the diagonal;
+  // only pairs with w > 0 can be in an optimum (a pair with w <= 0 is
+  // dissolved at the end: both go to the diagonal, as the pruning rule says).
+  // Rows-perfect assignment of the points to the targets or to their own
+  // diagonal column, with costs W - w >= 0 and W on the diagonal column,
+  // solved exactly by shortest augmenting paths (Dijkstra with potentials)
+  // on the complete graph: the cheapest unsettled target of a row is a
+  // KD-tree query, since its reduced cost is
+  //   (W - diag(p) - u_p) + |p - q|^2 - (diag(q) + v_q).
+  const int m = int(pb.size()), k = int(qb.size());
+  match->assign(m, -1);
+  std::vector<double> dp(m), dq(k);
+  double maxdp = 0, maxdq = 0;
+  for (int i = 0; i < m; ++i) maxdp = std::max(maxdp, dp[i] = diag_cost(pb[i], pd[i]));
+  for (int j = 0; j < k; ++j) maxdq = std::max(maxdq, dq[j] = diag_cost(qb[j], qd[j]));
+  double total = 0;
+  if (m == 0) {
+    for (int j = 0; j < k; ++j) total += dq[j];
+    return total;
+  }
+  const double W = maxdp + maxdq;
+  const double INF = std::numeric_limits<double>::infinity();
+  KDTree tree;
+  tree.build(qb.data(), qd.data(), k);
+  std::vector<double> v(k, 0.0), u(m, 0.0), sc(k);
+  for (int j = 0; j < k; ++j) sc[j] = dq[j];
+  tree.set_all(sc);
+  // column ids: targets 0..k-1; the diagonal column of row r is k + r
+  std::vector<int> row_of(k, -1), col_of(m, -1), way(k + m, -1);
+  std::vector<double> dcol(k + m, INF), drow(m, 0.0);
+  std::vector<int> settled_list, tree_rows;
+  struct Cand {
+    double d;
+    int row, col;
+    bool operator>(const Cand& o) const {
+      if (d != o.d) return d > o.d;
+      if (col != o.col) return col > o.col;
+      return row > o.row;
+    }
+  };
+  for (int s0 = 0; s0 < m; ++s0) {
+    std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> pq;
+    settled_list.clear();
+    tree_rows.clear();
+    auto offer_best = [&](int r) {
+      double val;
+      const int j = tree.best(pb[r], pd[r], &val);
+      if (j >= 0) pq.push({drow[r] + (W - dp[r] - u[r]) + val, r, j});
+    };
+    auto enter = [&](int r, double dr) {
+      drow[r] = dr;
+      tree_rows.push_back(r);
+      offer_best(r);
+      pq.push({dr + W - u[r], r, k + r});  // its diagonal column (potential 0, always free)
+    };
+    enter(s0, 0.0);
+    int found = -1;
+    double D = 0;
+    while (!pq.empty()) {
+      const Cand c = pq.top();
+      pq.pop();
+      if (c.col >= k) {  // a row's own diagonal column is free
+        found = c.col;
+        D = c.d;
+        way[found] = c.row;
+        break;
+      }
+      if (tree.masked[c.col]) {  // settled meanwhile: offer the row's next best
+        offer_best(c.row);
+        continue;
+      }
+      const int j = c.col;
+      dcol[j] = c.d;
+      way[j] = c.row;
+      tree.update(j, tree.s[j], true);
+      settled_list.push_back(j);
+      if (row_of[j] < 0) {
+        found = j;
+        D = c.d;
+        break;
+      }
+      enter(row_of[j], c.d);
+      offer_best(c.row);
+    }
+    if (found < 0) throw Error(TS_ERR_INTERNAL, "assignment: no augmenting path");
+    for (int r : tree_rows) u[r] += D - drow[r];
+    for (int j : settled_list) {
+      v[j] -= D - dcol[j];
+      dcol[j] = INF;
+      tree.update(j, dq[j] + v[j], false);
+    }
+    // augment
+    int j = found;
+    int guard = 0;
+    while (true) {
+      if (++guard > k + m + 2) throw Error(TS_ERR_INTERNAL, "assignment: augmenting path loops");
+      const int r = way[j];
+      const int prev = col_of[r];
+      col_of[r] = j;
+      if (j < k) row_of[j] = r;
+      if (r == s0) break;
+      j = prev;
+    }
+  }
+  std::vector<char> used(k, 0);
+  for (int i = 0; i < m; ++i) {
+    const int j = col_of[i];
+    if (j < k && pair_cost(pb[i], pd[i], qb[j], qd[j]) < dp[i] + dq[j]) {
+      (*match)[i] = j;
+      used[j] = 1;
+      total += pair_cost(pb[i], pd[i], qb[j], qd[j]);
+    } else {
+      total += dp[i];
+    }
+  }
+  for (int j = 0; j < k; ++j)
+    if (!used[j]) total += dq[j];
+  return total;
+}
+
+// Exact assignment up to kExactMax points + targets, auction above (the
+// exact method is quadratic on the dense reduced problems of noisy fields).
+double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
+                      const std::vector<double>& qb, const std::vector<double>& qd,
+                      std::vector<int>* match) {
+  int64_t limit = 4000;
+  if (const char* e = std::getenv("TS_EXACT_MAX")) limit = std::atoll(e);
+  if (int64_t(pb.size() + qb.size()) <= limit) return assign_exact(pb, pd, qb, qd, match);
+  return assign_auction(pb, pd, qb, qd, match, 1e-9);
 }
 
 // ---------------------------------------------------------------- loop

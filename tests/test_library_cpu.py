@@ -1,0 +1,82 @@
+"""CPU checks of the HIP library: it loads, exports every function its
+header declares, fails cleanly without a GPU, and its host-side exact
+assignment (Eq. 1 with q = 2 on the reduced problem, Sec. 4.3) equals the
+oracle's dense Hungarian solution."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_2407_12399_amd as ts
+    if not os.path.exists(ts.LIB_PATH):
+        from paper_2407_12399_amd import _build
+        _build.build()
+    ts.lib()
+    return ts
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "topsimp.h")).read()
+    return sorted(set(re.findall(r"\b(ts_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(ts):
+    names = _declared()
+    assert "ts_diagram" in names and "ts_simplify" in names
+    L = ctypes.CDLL(ts.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(ts.EXPORTS) == set(names)
+
+
+def test_create_without_gpu_fails_cleanly(ts):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = ts.lib().ts_create(ctypes.byref(h), 0, None)
+    assert rc != 0 and not h.value
+    assert ts.lib().ts_destroy(None) == 0
+
+
+def _instance(rng, m, k, dense):
+    if dense:  # every point overlaps every target (noise pairs near the diagonal)
+        pb = rng.normal(0, 0.02, m)
+        pd = pb + np.abs(rng.normal(0, 0.05, m))
+        qb = rng.normal(0, 0.02, k)
+        qd = qb + np.abs(rng.normal(0, 0.05, k))
+    else:
+        pb = rng.random(m)
+        pd = pb + rng.random(m) * 0.3
+        qb = rng.random(k)
+        qd = qb + rng.random(k) * 0.3
+    # single-precision values, as the diagrams hold them
+    return [a.astype(np.float32).astype(np.float64) for a in (pb, pd, qb, qd)]
+
+
+@pytest.mark.parametrize("seed,m,k,dense", [(s, m, k, d) for s, (m, k, d) in enumerate(
+    [(0, 0, False), (0, 5, False), (5, 0, False), (7, 9, False), (40, 35, False),
+     (40, 35, True), (150, 140, True), (200, 260, False), (300, 280, True), (1, 1, True)])])
+def test_assignment_matches_oracle(ts, orc, seed, m, k, dense):
+    rng = np.random.default_rng(100 + seed)
+    pb, pd, qb, qd = _instance(rng, m, k, dense)
+    mt, ct = ts.assign(pb, pd, qb, qd)
+    mo, co = orc.assign(pb, pd, qb, qd)
+    assert np.array_equal(mt, mo)
+    assert ct == pytest.approx(co, rel=1e-12, abs=1e-15)
+
+
+def test_assignment_bad_arguments(ts):
+    out = np.zeros(1, np.int32)
+    cost = np.zeros(1, np.float64)
+    rc = ts.lib().ts_assign(-1, None, None, 0, None, None, out.ctypes.data, cost.ctypes.data)
+    assert rc == -1
+    rc = ts.lib().ts_assign(2, None, None, 0, None, None, out.ctypes.data, cost.ctypes.data)
+    assert rc == -1
