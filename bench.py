@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=48)
     ap.add_argument("--diag-reps", type=int, default=3)
+    ap.add_argument("--diagram-only", action="store_true",
+                    help="only run the persistence map --diag-reps times (for profilers)")
     return ap.parse_args()
 
 
@@ -117,6 +119,10 @@ def main():
         for k, v in ts.stage_times().items():
             diag_stage.setdefault(k, []).append(v)
     stage_ms = {k: float(np.median(v)) for k, v in diag_stage.items()}
+    if args.diagram_only:
+        print(json.dumps({"persistence_map_ms": sum(stage_ms.values()), "stage_ms": stage_ms,
+                          "wall_ms": float(np.median(wall)) * 1e3, "pairs": len(D)}))
+        return
     pm_ms = sum(stage_ms.values())
     n_pairs = [int((D["dim"] == d).sum() - (D["essential"] if d == 0 else 0).sum())
                if d == 0 else int((D["dim"] == d).sum()) for d in range(3)]
