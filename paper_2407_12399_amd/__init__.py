@@ -150,10 +150,15 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+_cap_hint = {}
+
+
 def _pairs_call(fn, field):
     ctx = context()
     fp, dims, on_dev, keep = _as_field(field)
-    cap = 4096
+    nv = int(np.prod(dims))
+    # a capacity that usually fits, so that the map is not computed twice
+    cap = max(4096, _cap_hint.get((fn.__name__, nv), nv // 4 + 16))
     while True:
         out = np.empty(cap, PAIR_DTYPE)
         n = np.zeros(1, np.int64)
@@ -162,6 +167,7 @@ def _pairs_call(fn, field):
             cap = int(n[0]) + 1
             continue
         _check(ctx, rc)
+        _cap_hint[(fn.__name__, int(np.prod(dims)))] = int(n[0]) + int(n[0]) // 8 + 16
         return out[: int(n[0])].copy()
 
 

@@ -120,51 +120,23 @@ void finish_timing(ts_ctx* ctx) {
   ctx->stage_names.push_back(nullptr);
 }
 
-// Host records of the pairs (all, or the diagram subset in diagram order).
+// Host records of the pairs (all, or the diagram subset in diagram order),
+// assembled on the device.
 void pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev, bool diagram_only,
                    std::vector<ts_pair>* out) {
   hipStream_t s = ctx->stream;
-  const int64_t np = R.npairs;
-  std::vector<int32_t> dim(np), birth(np), death(np), order(R.g.n);
-  std::vector<uint64_t> bkey(np), dkey(np);
-  std::vector<float> f(R.g.n);
-  TS_HIP(hipMemcpyAsync(dim.data(), R.pdim, np * 4, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(birth.data(), R.pbirth, np * 4, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(death.data(), R.pdeath, np * 4, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(bkey.data(), R.pbkey, np * 8, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(dkey.data(), R.pdkey, np * 8, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(order.data(), R.order, size_t(R.g.n) * 4, hipMemcpyDeviceToHost, s));
-  TS_HIP(hipMemcpyAsync(f.data(), f_dev, size_t(R.g.n) * 4, hipMemcpyDeviceToHost, s));
-  std::vector<uint32_t> diag;
-  if (diagram_only) {
-    diag.resize(R.ndiag);
-    if (R.ndiag)
-      TS_HIP(hipMemcpyAsync(diag.data(), R.diag, R.ndiag * 4, hipMemcpyDeviceToHost, s));
-  }
+  const int64_t n = diagram_only ? R.ndiag : R.npairs;
+  ts_pair* d = ctx->ws.get<ts_pair>("api.records", n + 1);
+  pair_records(ctx, R, f_dev, diagram_only, d);
+  out->resize(n);
+  if (n) TS_HIP(hipMemcpyAsync(out->data(), d, n * sizeof(ts_pair), hipMemcpyDeviceToHost, s));
   TS_HIP(hipStreamSynchronize(s));
-  auto rec = [&](int64_t i) {
-    ts_pair p;
-    p.dim = dim[i];
-    p.essential = death[i] < 0 ? 1 : 0;
-    p.birth_cell = birth[i];
-    p.death_cell = death[i];
-    p.v_birth = order[bkey[i] >> 12];
-    p.v_death = order[dkey[i] >> 12];
-    p.birth = f[p.v_birth];
-    p.death = f[p.v_death];
-    return p;
-  };
-  out->clear();
-  if (diagram_only) {
-    for (uint32_t i : diag) out->push_back(rec(i));
-  } else {
-    for (int64_t i = 0; i < np; ++i) out->push_back(rec(i));
+  if (!diagram_only)
     std::sort(out->begin(), out->end(), [](const ts_pair& a, const ts_pair& b) {
       if (a.dim != b.dim) return a.dim < b.dim;
       if (a.birth_cell != b.birth_cell) return a.birth_cell < b.birth_cell;
       return a.death_cell < b.death_cell;
     });
-  }
 }
 
 template <class F>

@@ -41,6 +41,10 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
 // The whole persistence map (K1..K8) of a device field.
 void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R);
 
+// ts_pair records of the diagram (diagram order) or of all pairs (device).
+void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool diagram_only,
+                  ts_pair* out_dev);
+
 // Dense gradient partner arrays (device outputs of sizes n, 7n, 12n).
 void decode_gradient(ts_ctx* ctx, const PersistenceResult& R, int32_t* vup, int32_t* eup,
                      int32_t* tup);

@@ -26,6 +26,7 @@
 //   K8     diagram: v_birth != v_death filter, diagram-order sort.
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -655,6 +656,12 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
 // Lookup helpers
 // ======================================================================
 
+__global__ void k_set_marks(unsigned int* __restrict__ mark, int64_t n,
+                            const unsigned int* __restrict__ round_ptr) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) mark[i] = *round_ptr;
+}
+
 __global__ void k_iota_from(uint32_t* a, int64_t n, uint32_t base) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = base + uint32_t(i);
@@ -1155,141 +1162,351 @@ __device__ __forceinline__ void d1_claim_one(uint32_t c, const uint64_t* __restr
   }
 }
 
-// returns 1 if the column still has to be reduced further, 0 if it owns its
-// pivot; 2 if the pool is full (column unchanged)
-__device__ __forceinline__ int d1_reduce_one(uint32_t c, uint64_t* __restrict__ col_desc,
-                                             uint32_t* __restrict__ pool, const ColPool& pc,
-                                             const unsigned int* __restrict__ owner,
-                                             int* __restrict__ err, uint32_t lo) {
- for (;;) {
-  const uint64_t d = col_desc[c];
-  const uint32_t len = uint32_t(d & 0xFFFFFFu);
-  if (len == 0) return 0;
-  const uint64_t off_c = d >> 24;
-  const uint32_t piv = pool[off_c];
-  const unsigned int o = owner[piv];
-  if (o == c) return 0;
-  if (o > c) return 1;  // unowned, or owned by a later column: claim it next round
-  const uint64_t od = col_desc[o];
-  const uint32_t olen = uint32_t(od & 0xFFFFFFu);
-  const uint64_t off_o = od >> 24;
-  const unsigned long long at = atomicAdd(pc.top, (unsigned long long)(len + olen));
-  if ((int64_t)(at + len + olen) > pc.cap) return 2;
-  // symmetric difference of two descending lists
-  uint32_t i = 0, j = 0, w = 0;
-  while (i < len || j < olen) {
-    if (j >= olen || (i < len && pool[off_c + i] > pool[off_o + j])) {
-      pool[at + w++] = pool[off_c + i++];
-    } else if (i >= len || pool[off_o + j] > pool[off_c + i]) {
-      pool[at + w++] = pool[off_o + j++];
-    } else {
-      ++i;
-      ++j;
-    }
-  }
-  if (w == 0) atomicOr(err, 64);  // a negative column cannot vanish
-  col_desc[c] = (uint64_t(at) << 24) | uint64_t(w);
-  if (o >= lo || w == 0) return 1;
-  // `o` belongs to an earlier, finished block: its column is final, so keep
-  // reducing against final owners without waiting for the next round
- }
+// Every member of the active list carries the current round in mark[].
+// Device counters: cnt[0] = size of the current list (grows while owners
+// are displaced), cnt[1] = size of the next list, cnt[2] = size of the
+// current list when the round began.
+__global__ void k_d1_round_begin(unsigned int* __restrict__ cnt, int* __restrict__ pool_full) {
+  cnt[2] = cnt[0];
+  cnt[1] = 0;
+  cnt[3] = 0;
+  (void)pool_full;
 }
 
-// Every member of the active list carries the current round in mark[].
+__global__ void k_d1_round_end(unsigned int* __restrict__ cnt) { cnt[0] = cnt[1]; }
+
 __global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
                            unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
-                           unsigned int round, uint32_t* __restrict__ list,
-                           unsigned int* __restrict__ nlist, unsigned int n0) {
-  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n0) return;
-  d1_claim_one(list[j], col_desc, pool, owner, mark, round, list, nlist);
+                           const unsigned int* __restrict__ round_ptr, uint32_t* __restrict__ list,
+                           unsigned int* __restrict__ cnt) {
+  const unsigned int n0 = cnt[2];
+  const unsigned int round = *round_ptr;
+  for (unsigned int j = blockIdx.x * blockDim.x + threadIdx.x; j < n0; j += gridDim.x * blockDim.x)
+    d1_claim_one(list[j], col_desc, pool, owner, mark, round, list, &cnt[0]);
 }
 
-__global__ void k_d1_reduce(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
-                            const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
-                            unsigned int round, const uint32_t* __restrict__ list,
-                            const unsigned int* __restrict__ nlist, uint32_t* __restrict__ next,
-                            unsigned int* __restrict__ nnext, int* __restrict__ err,
-                            int* __restrict__ pool_full, uint32_t lo) {
-  const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= *nlist) return;
-  const uint32_t c = list[j];
-  const int r = d1_reduce_one(c, col_desc, pool, pc, owner, err, lo);
-  if (r == 2) atomicOr(pool_full, 1);
-  if (r != 0) {
-    mark[c] = round + 1;
-    next[atomicAdd(nnext, 1u)] = c;
+__global__ void k_d1_round_inc(unsigned int* __restrict__ round_ptr) { *round_ptr += 1; }
+
+// ---- wave-cooperative reduction of one column ----------------------------
+// The working column stays in LDS while it is reduced against a chain of
+// owner columns; each owner column is loaded by the whole wave and the
+// symmetric difference of two descending lists is formed in parallel: an
+// element x of list A kept in the result goes to slot
+//   2 * (#kept elements of A before x) - (index of x in A) + (#elements of B greater than x).
+constexpr int kWaveCap = 512;    // longest column handled in LDS
+constexpr int kRedWaves = 4;     // waves per block of the cooperative kernels
+
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// number of elements of the descending list L[0..n) that are greater than x
+__device__ __forceinline__ uint32_t count_greater(const uint32_t* L, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (L[mid] > x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// out = A xor B (both descending, unique); returns the length
+__device__ uint32_t wave_xor(const uint32_t* A, uint32_t a, const uint32_t* B, uint32_t b,
+                             uint32_t* out) {
+  const unsigned lane = lane_id();
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint32_t keptA = 0, keptB = 0;
+  for (uint32_t base = 0; base < a; base += 64) {
+    const uint32_t i = base + lane;
+    bool keep = false;
+    uint32_t r = 0;
+    if (i < a) {
+      r = count_greater(B, b, A[i]);
+      keep = !(r < b && B[r] == A[i]);
+    }
+    const uint64_t m = __ballot(keep);
+    const uint32_t pre = keptA + __popcll(m & lt);
+    if (keep) out[2 * pre - i + r] = A[i];
+    keptA += __popcll(m);
+  }
+  for (uint32_t base = 0; base < b; base += 64) {
+    const uint32_t j = base + lane;
+    bool keep = false;
+    uint32_t r = 0;
+    if (j < b) {
+      r = count_greater(A, a, B[j]);
+      keep = !(r < a && A[r] == B[j]);
+    }
+    const uint64_t m = __ballot(keep);
+    const uint32_t pre = keptB + __popcll(m & lt);
+    if (keep) out[2 * pre - j + r] = B[j];
+    keptB += __popcll(m);
+  }
+  wave_sync();
+  return keptA + keptB;
+}
+
+// Wave reduction of column c: returns 0 if c owns its pivot, 1 if it must be
+// reduced again next round, 2 if the pool is full (column unchanged), -1 if
+// the column or its owner is too long for LDS (the caller hands it to the
+// workgroup kernel).
+__device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
+                              const ColPool& pc, const unsigned int* __restrict__ owner,
+                              int* __restrict__ err, uint32_t lo, uint32_t* bufA, uint32_t* bufB,
+                              uint32_t* bufO) {
+  const unsigned lane = lane_id();
+  const uint64_t d = col_desc[c];
+  uint32_t len = uint32_t(d & 0xFFFFFFu);
+  if (len == 0) return 0;
+  if (len > kWaveCap) return -1;
+  const uint64_t off = d >> 24;
+  for (uint32_t i = lane; i < len; i += 64) bufA[i] = pool[off + i];
+  wave_sync();
+  bool changed = false;
+  int result = 1;
+  uint32_t* cur = bufA;
+  uint32_t* nxt = bufO;
+  for (int steps = 0;; ++steps) {
+    if (steps > (1 << 20)) {  // pivots strictly decrease: cannot happen
+      if (lane == 0) atomicOr(err, 512);
+      break;
+    }
+    const uint32_t piv = cur[0];
+    const unsigned int o = owner[piv];
+    if (o == c) {
+      result = 0;
+      break;
+    }
+    if (o > c) break;  // unowned or owned by a later column: claim next round
+    const uint64_t od = col_desc[o];
+    const uint32_t olen = uint32_t(od & 0xFFFFFFu);
+    if (olen > kWaveCap || len + olen > 2 * kWaveCap) {
+      if (!changed) return -1;
+      break;  // write back what we have; the next round hands it on
+    }
+    const uint64_t ooff = od >> 24;
+    for (uint32_t i = lane; i < olen; i += 64) bufB[i] = pool[ooff + i];
+    wave_sync();
+    const uint32_t w = wave_xor(cur, len, bufB, olen, nxt);
+    changed = true;
+    if (w == 0) {
+      if (lane == 0) atomicOr(err, 64);
+      len = 0;
+      break;
+    }
+    uint32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    len = w;
+    if (o >= lo || len > kWaveCap) break;  // block owner: one step per round
+  }
+  if (!changed) return result;
+  unsigned long long at = 0;
+  if (lane == 0) at = atomicAdd(pc.top, (unsigned long long)len);
+  at = __shfl(at, 0, 64);
+  if ((int64_t)(at + len) > pc.cap) return 2;  // column unchanged; retried after growth
+  for (uint32_t i = lane; i < len; i += 64) pool[at + i] = cur[i];
+  __threadfence();
+  if (lane == 0) col_desc[c] = (uint64_t(at) << 24) | uint64_t(len);
+  return result;
+}
+
+// ---- workgroup reduction of a long column -------------------------------
+constexpr int kLongThreads = 1024;
+
+// exclusive prefix sum of v over the workgroup; *total receives the sum
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t m = __ballot(v != 0);  // v is 0 or 1
+  const uint32_t in_wave = __popcll(m & lt);
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (unsigned w = 0; w < blockDim.x / 64; ++w) {
+      const uint32_t t = s_wave[w];
+      s_wave[w] = acc;
+      acc += t;
+    }
+    s_wave[blockDim.x / 64] = acc;
+  }
+  __syncthreads();
+  const uint32_t r = s_wave[wave] + in_wave;
+  *total = s_wave[blockDim.x / 64];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ uint32_t count_greater_g(const uint32_t* __restrict__ L, uint32_t n,
+                                                    uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (L[mid] > x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kLongThreads)
+k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
+                 const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                 unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ long_list,
+                 uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
+                 int* __restrict__ pool_full, uint32_t lo) {
+  __shared__ uint32_t s_wave[kLongThreads / 64 + 1];
+  __shared__ uint64_t s_off, s_ooff;
+  __shared__ unsigned long long s_at;
+  __shared__ uint32_t s_len, s_olen;
+  __shared__ int s_state;  // -1 continue, 0 owner, 1 next round, 2 pool full, 3 stop (error)
+  const unsigned int nlong = cnt[3];
+  const unsigned int round = *round_ptr;
+  for (unsigned int b = blockIdx.x; b < nlong; b += gridDim.x) {
+    const uint32_t c = long_list[b];
+    for (int steps = 0;; ++steps) {
+      if (threadIdx.x == 0) {
+        const uint64_t d = col_desc[c];
+        s_len = uint32_t(d & 0xFFFFFFu);
+        s_off = d >> 24;
+        s_state = -1;
+        if (s_len == 0 || steps > (1 << 20)) {
+          s_state = 3;
+          atomicOr(err, 1024);
+        } else {
+          const unsigned int o = owner[pool[s_off]];
+          if (o == c) s_state = 0;
+          else if (o > c) s_state = 1;
+          else {
+            const uint64_t od = col_desc[o];
+            s_olen = uint32_t(od & 0xFFFFFFu);
+            s_ooff = od >> 24;
+            s_at = atomicAdd(pc.top, (unsigned long long)(s_len + s_olen));
+            if ((int64_t)(s_at + s_len + s_olen) > pc.cap) s_state = 2;
+            if (steps > 0 && o >= lo) s_state = 1;  // block owner: one step per round
+          }
+        }
+      }
+      __syncthreads();
+      if (s_state >= 0) break;
+      const uint32_t a = s_len, bl = s_olen;
+      const uint32_t* A = pool + s_off;
+      const uint32_t* B = pool + s_ooff;
+      uint32_t* out = pool + s_at;
+      uint32_t keptA = 0, keptB = 0, tot;
+      for (uint32_t base = 0; base < a; base += kLongThreads) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t keep = 0, r = 0, x = 0;
+        if (i < a) {
+          x = A[i];
+          r = count_greater_g(B, bl, x);
+          keep = !(r < bl && B[r] == x);
+        }
+        const uint32_t pre = keptA + block_scan(keep, s_wave, &tot);
+        if (keep) out[2 * pre - i + r] = x;
+        keptA += tot;
+      }
+      for (uint32_t base = 0; base < bl; base += kLongThreads) {
+        const uint32_t j = base + threadIdx.x;
+        uint32_t keep = 0, r = 0, x = 0;
+        if (j < bl) {
+          x = B[j];
+          r = count_greater_g(A, a, x);
+          keep = !(r < a && A[r] == x);
+        }
+        const uint32_t pre = keptB + block_scan(keep, s_wave, &tot);
+        if (keep) out[2 * pre - j + r] = x;
+        keptB += tot;
+      }
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t w = keptA + keptB;
+        if (w == 0) atomicOr(err, 64);
+        col_desc[c] = (uint64_t(s_at) << 24) | uint64_t(w);
+      }
+      __threadfence();
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (s_state == 2) atomicOr(pool_full, 1);
+      if (s_state == 1 || s_state == 2) {
+        mark[c] = round + 1;
+        next[atomicAdd(&cnt[1], 1u)] = c;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Reduce phase with one wave per active column.
+__global__ void __launch_bounds__(64 * kRedWaves)
+k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
+                 const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                 unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ list,
+                 uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
+                 int* __restrict__ pool_full, uint32_t lo, uint32_t* __restrict__ long_list) {
+  __shared__ uint32_t s_buf[kRedWaves][3][2 * kWaveCap];
+  const unsigned wave = threadIdx.x >> 6;
+  const unsigned lane = lane_id();
+  const unsigned int n1 = cnt[0];
+  const unsigned int round = *round_ptr;
+  const unsigned gw = blockIdx.x * kRedWaves + wave;
+  const unsigned nw = gridDim.x * kRedWaves;
+  for (unsigned int j = gw; j < n1; j += nw) {
+    const uint32_t c = list[j];
+    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, err, lo, s_buf[wave][0], s_buf[wave][1],
+                           s_buf[wave][2]);
+    if (r < 0) {  // too long for the wave: handled by a whole workgroup this round
+      if (lane == 0) long_list[atomicAdd(&cnt[3], 1u)] = c;
+      wave_sync();
+      continue;
+    }
+    if (lane == 0) {
+      if (r == 2) atomicOr(pool_full, 1);
+      if (r != 0) {
+        mark[c] = round + 1;
+        next[atomicAdd(&cnt[1], 1u)] = c;
+      }
+    }
+    wave_sync();
   }
 }
 
 // The tail of the reduction in one workgroup: same rounds, workgroup
 // barriers instead of kernel boundaries.  Exits when no column is active,
 // when the pool is full (resumable) or after max_rounds (error flag).
-__global__ void __launch_bounds__(1024)
-k_d1_tail(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
-          unsigned int* __restrict__ owner, unsigned int* __restrict__ mark, unsigned int round0,
-          uint32_t* __restrict__ listA, uint32_t* __restrict__ listB, unsigned int* __restrict__ counts,
-          int* __restrict__ err, int* __restrict__ pool_full, int max_rounds,
-          unsigned int* __restrict__ rounds_out, uint32_t lo) {
-  __shared__ unsigned int s_na, s_nb, s_n0;
-  __shared__ int s_full;
-  uint32_t* A = listA;
-  uint32_t* B = listB;
-  if (threadIdx.x == 0) {
-    s_na = counts[0];
-    s_full = 0;
-  }
-  __syncthreads();
-  unsigned int round = round0 - 1;
-  int r = 0;
-  while (s_na > 0) {
-    if (r >= max_rounds) {
-      if (threadIdx.x == 0) atomicOr(err, 256);
-      break;
-    }
-    ++round;
-    ++r;
-    if (threadIdx.x == 0) {
-      s_n0 = s_na;
-      s_nb = 0;
-    }
-    __syncthreads();
-    const unsigned int n0 = s_n0;
-    for (unsigned int j = threadIdx.x; j < n0; j += blockDim.x)
-      d1_claim_one(A[j], col_desc, pool, owner, mark, round, A, &s_na);
-    __threadfence_block();
-    __syncthreads();
-    const unsigned int n1 = s_na;
-    for (unsigned int j = threadIdx.x; j < n1; j += blockDim.x) {
-      const uint32_t c = A[j];
-      const int rr = d1_reduce_one(c, col_desc, pool, pc, owner, err, lo);
-      if (rr == 2) s_full = 1;
-      if (rr != 0) {
-        mark[c] = round + 1;
-        B[atomicAdd(&s_nb, 1u)] = c;
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-    uint32_t* t = A;
-    A = B;
-    B = t;
-    if (threadIdx.x == 0) s_na = s_nb;
-    __syncthreads();
-    if (s_full) break;
-  }
-  if (threadIdx.x == 0) {
-    counts[0] = s_na;
-    if (s_full) *pool_full = 1;
-    rounds_out[0] = unsigned(r);
-    rounds_out[1] = (A == listA) ? 0u : 1u;  // which buffer holds the active list
-  }
-}
-
 __global__ void k_fill_u32(unsigned int* a, int64_t n, unsigned int v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
 }
+
+__global__ void k_col_lengths(const uint64_t* __restrict__ col_desc, int64_t ncols,
+                              uint32_t* __restrict__ lens) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c < ncols) lens[c] = uint32_t(col_desc[c] & 0xFFFFFFu);
+  if (c == ncols) lens[c] = 0;
+}
+
+__global__ void k_col_compact(uint64_t* __restrict__ col_desc, int64_t ncols,
+                              const uint32_t* __restrict__ pool, const uint32_t* __restrict__ offs,
+                              uint32_t* __restrict__ out) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const uint64_t d = col_desc[c];
+  const uint32_t len = uint32_t(d & 0xFFFFFFu);
+  const uint64_t from = d >> 24;
+  const uint64_t to = offs[c];
+  for (uint32_t i = 0; i < len; ++i) out[to + i] = pool[from + i];
+  col_desc[c] = (to << 24) | uint64_t(len);
+}
+
+__global__ void k_set_u64(unsigned long long* a, uint64_t v) { *a = v; }
 
 __global__ void k_fill_u64(uint64_t* a, int64_t n, uint64_t v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1691,6 +1908,20 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     }
     pool_hint = std::max(pool_hint, pool_cap);
     ctx->timer.stop();
+    auto length_stats = [&](const char* what) {
+      if (!std::getenv("TS_TRACE")) return;
+      std::vector<uint64_t> desc(ncols);
+      TS_HIP(hipMemcpy(desc.data(), col_desc, ncols * 8, hipMemcpyDeviceToHost));
+      std::vector<uint32_t> L(ncols);
+      uint64_t tot = 0;
+      for (int64_t c = 0; c < ncols; ++c) tot += (L[c] = uint32_t(desc[c] & 0xFFFFFFu));
+      std::sort(L.begin(), L.end());
+      std::fprintf(stderr,
+                   "[topsimp] %s column lengths: mean %.2f median %u p99 %u p99.99 %u max %u\n",
+                   what, double(tot) / ncols, L[ncols / 2], L[ncols * 99 / 100],
+                   L[std::min<int64_t>(ncols - 1, ncols * 9999 / 10000)], L[ncols - 1]);
+    };
+    length_stats("boundary");
 
     ctx->timer.start("K7 d1 reduction");
     unsigned int* owner = ws.get<unsigned int>("d1.owner", ne + 1);
@@ -1698,90 +1929,83 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
     uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
     unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 4);
+    uint32_t* long_list = ws.get<uint32_t>("d1.long", ncols + 1);
     int* pool_full = ws.get<int>("d1.full", 1);
-    unsigned int* tail_info = ws.get<unsigned int>("d1.tinfo", 2);
     k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
-    k_fill_u32<<<blocks_for(ncols), 256, 0, s>>>(mark, ncols, 1u);
-    // grows the pool, compacting the live columns
+    // grows the pool, compacting the live columns on the device
+    int grows = 0;
     auto grow_pool = [&]() {
-      std::vector<uint64_t> desc(ncols);
-      TS_HIP(hipMemcpyAsync(desc.data(), col_desc, ncols * sizeof(uint64_t),
-                            hipMemcpyDeviceToHost, s));
-      TS_HIP(hipStreamSynchronize(s));
-      int64_t live = 0;
-      for (uint64_t d : desc) live += int64_t(d & 0xFFFFFFu);
+      ++grows;
+      uint32_t* lens = ws.get<uint32_t>("d1.lens", ncols + 1);
+      uint32_t* offs = ws.get<uint32_t>("d1.offs", ncols + 1);
+      k_col_lengths<<<blocks_for(ncols + 1), 256, 0, s>>>(col_desc, ncols, lens);
+      scan_exclusive_u32(ws, lens, offs, ncols + 1, s);  // lens[ncols] = 0: offs[ncols] = total
+      const int64_t live = int64_t(read_scalar(offs + ncols, s));
       const int64_t ncap = std::max<int64_t>(2 * pool_cap, 4 * live + (1 << 20));
+      if (ncap >= (int64_t(1) << 40)) throw Error(TS_ERR_INTERNAL, "column pool too large");
       uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
-      int64_t at = 0;
-      for (int64_t c = 0; c < ncols; ++c) {
-        const int64_t len = int64_t(desc[c] & 0xFFFFFFu);
-        if (len > 0)
-          TS_HIP(hipMemcpyAsync(np + at, pool.data + (desc[c] >> 24), len * sizeof(uint32_t),
-                                hipMemcpyDeviceToDevice, s));
-        desc[c] = (uint64_t(at) << 24) | uint64_t(len);
-        at += len;
-      }
-      TS_HIP(hipMemcpyAsync(col_desc, desc.data(), ncols * sizeof(uint64_t),
-                            hipMemcpyHostToDevice, s));
-      TS_HIP(hipStreamSynchronize(s));
+      k_col_compact<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, pool.data, offs, np);
       std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
       pool.data = np;
       pool_cap = ncap;
       pool.cap = ncap;
-      unsigned long long top = at;
-      TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
-      TS_HIP(hipStreamSynchronize(s));
+      k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(live));
+      TS_HIP(hipGetLastError());
       pool_hint = std::max(pool_hint, pool_cap);
     };
-    const unsigned int kTail = 8192;
+    const int kCheckEvery = 8;
     // Columns are reduced block by block in index order; a block's columns
     // only interact with each other once every earlier column is final.
     const int64_t kBlock = 1 << 16;
-    unsigned int round = 1;  // round to run next; active members carry it in mark[]
+    unsigned int* round_d = ws.get<unsigned int>("d1.round", 1);
+    k_fill_u32<<<1, 1, 0, s>>>(round_d, 1, 1u);  // active members carry the round in mark[]
     int rounds = 0;
     uint32_t* A = listA;
     uint32_t* B = listB;
     for (int64_t lo = 0; lo < ncols; lo += kBlock) {
-    const int64_t hi = std::min<int64_t>(ncols, lo + kBlock);
-    unsigned int h_n = unsigned(hi - lo);
-    k_iota_from<<<blocks_for(h_n), 256, 0, s>>>(A, h_n, uint32_t(lo));
-    k_fill_u32<<<1, 1, 0, s>>>(cnt, 1, h_n);
-    k_fill_u32<<<blocks_for(h_n), 256, 0, s>>>(mark + lo, h_n, round);
-    while (h_n > 0) {
-      if (h_n > kTail) {
-        ++rounds;
-        TS_HIP(hipMemsetAsync(cnt + 1, 0, sizeof(unsigned int), s));
+      const int64_t hi = std::min<int64_t>(ncols, lo + kBlock);
+      unsigned int h_n = unsigned(hi - lo);
+      k_iota_from<<<blocks_for(h_n), 256, 0, s>>>(A, h_n, uint32_t(lo));
+      k_fill_u32<<<1, 1, 0, s>>>(cnt, 1, h_n);
+      k_set_marks<<<blocks_for(h_n), 256, 0, s>>>(mark + lo, h_n, round_d);
+      const unsigned grid = std::min<unsigned>(blocks_for(h_n), 1024u);
+      const unsigned wgrid = std::min<unsigned>(unsigned((h_n + kRedWaves - 1) / kRedWaves), 4096u);
+      while (h_n > 0) {
         TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
-        k_d1_claim<<<blocks_for(h_n), 256, 0, s>>>(col_desc, pool.data, owner, mark, round, A, cnt,
-                                                   h_n);
-        // displaced owners were appended: the list may have grown
-        const unsigned int n1 = read_scalar(cnt, s);
-        k_d1_reduce<<<blocks_for(n1), 256, 0, s>>>(col_desc, pool.data, pool, owner, mark, round, A,
-                                                   cnt, B, cnt + 1, err, pool_full, uint32_t(lo));
-        ++round;
+        for (int it = 0; it < kCheckEvery; ++it) {
+          ++rounds;
+          k_d1_round_begin<<<1, 1, 0, s>>>(cnt, pool_full);
+          k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
+          k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, mark,
+                                                            round_d, A, B, cnt, err, pool_full,
+                                                            uint32_t(lo), long_list);
+          k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, mark,
+                                                       round_d, long_list, B, cnt, err, pool_full,
+                                                       uint32_t(lo));
+          k_d1_round_end<<<1, 1, 0, s>>>(cnt);
+          k_d1_round_inc<<<1, 1, 0, s>>>(round_d);
+          std::swap(A, B);
+        }
         TS_HIP(hipGetLastError());
-        h_n = read_scalar(cnt + 1, s);
-        TS_HIP(hipMemcpyAsync(cnt, cnt + 1, sizeof(unsigned int), hipMemcpyDeviceToDevice, s));
-        std::swap(A, B);
-        if (read_scalar(pool_full, s)) grow_pool();
-      } else {
-        TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
-        k_d1_tail<<<1, 1024, 0, s>>>(col_desc, pool.data, pool, owner, mark, round, A, B, cnt, err,
-                                     pool_full, 1 << 22, tail_info, uint32_t(lo));
-        TS_HIP(hipGetLastError());
-        unsigned int info[2];
-        TS_HIP(hipMemcpyAsync(info, tail_info, sizeof(info), hipMemcpyDeviceToHost, s));
         h_n = read_scalar(cnt, s);
-        rounds += int(info[0]);
-        round += info[0];
-        if (info[1]) std::swap(A, B);
+        if (std::getenv("TS_TRACE_D1")) {
+          static auto t_prev = std::chrono::steady_clock::now();
+          const auto t_now = std::chrono::steady_clock::now();
+          std::fprintf(stderr, "[d1] block %lld rounds %d active %u  %.3f ms\n", (long long)(lo / kBlock),
+                       rounds, h_n,
+                       std::chrono::duration<double, std::milli>(t_now - t_prev).count());
+          t_prev = t_now;
+        }
         if (read_scalar(pool_full, s)) grow_pool();
         if (read_scalar(err, s)) break;
+        if (rounds > (1 << 23)) throw Error(TS_ERR_INTERNAL, "saddle-saddle reduction did not converge");
       }
-      if (rounds > (1 << 23)) throw Error(TS_ERR_INTERNAL, "saddle-saddle reduction did not converge");
-    }
     }
     R->rounds_d1 = rounds;
+    length_stats("reduced");
+    if (std::getenv("TS_TRACE"))
+      std::fprintf(stderr, "[topsimp] d1 reduction: %d rounds, pool %lld / %lld words, %d grows\n",
+                   rounds, (long long)read_scalar(pool.top, s), (long long)pool_cap, grows);
     k_d1_pairs<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, cols, pool.data, R->cid[1],
                                                  R->ckey[1], R->cid[2], R->ckey[2], po);
     ctx->timer.stop();
@@ -1833,6 +2057,38 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   R->ndiag = read_scalar(nd, s);
   radix_sort_u64(ws, dkeys, R->diag, R->ndiag, 0, 64, s);
   ctx->timer.stop();
+  TS_HIP(hipGetLastError());
+}
+
+namespace {
+__global__ void k_records(const uint32_t* __restrict__ sel, int64_t nsel, int use_sel,
+                          const int32_t* __restrict__ pdim, const int32_t* __restrict__ pbirth,
+                          const int32_t* __restrict__ pdeath, const uint64_t* __restrict__ bkey,
+                          const uint64_t* __restrict__ dkey, const int32_t* __restrict__ order,
+                          const float* __restrict__ f, ts_pair* __restrict__ out) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nsel) return;
+  const uint32_t i = use_sel ? sel[k] : uint32_t(k);
+  ts_pair p;
+  p.dim = pdim[i];
+  p.essential = pdeath[i] < 0 ? 1 : 0;
+  p.birth_cell = pbirth[i];
+  p.death_cell = pdeath[i];
+  p.v_birth = order[bkey[i] >> 12];
+  p.v_death = order[dkey[i] >> 12];
+  p.birth = f[p.v_birth];
+  p.death = f[p.v_death];
+  out[k] = p;
+}
+}  // namespace
+
+void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool diagram_only,
+                  ts_pair* out_dev) {
+  const int64_t n = diagram_only ? R.ndiag : R.npairs;
+  if (n == 0) return;
+  k_records<<<blocks_for(n), 256, 0, ctx->stream>>>(R.diag, n, diagram_only ? 1 : 0, R.pdim,
+                                                    R.pbirth, R.pdeath, R.pbkey, R.pdkey, R.order,
+                                                    f, out_dev);
   TS_HIP(hipGetLastError());
 }
 

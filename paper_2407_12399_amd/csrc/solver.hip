@@ -788,15 +788,153 @@ double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd
   return total;
 }
 
-// Exact assignment up to kExactMax points + targets, auction above (the
-// exact method is quadratic on the dense reduced problems of noisy fields).
+namespace {
+
+// Indices of the set B (KD-tree `tree` over B, scores s_b = diag(b)) that
+// are among the `topk` best of some query a by saving
+// w = diag(a) + diag(b) - c(a,b) > 0 (ties with the last one kept).  The
+// positivity test has a relative margin, so that no candidate is lost to
+// rounding.
+std::vector<int> top_candidates(KDTree* tree, const std::vector<double>& ab,
+                                const std::vector<double>& ad, const std::vector<double>& da,
+                                double scale, int nb, int topk) {
+  std::vector<char> keep(nb, 0);
+  std::vector<int> masked;
+  for (size_t a = 0; a < ab.size(); ++a) {
+    const double bound = da[a] + 1e-9 * (da[a] + scale) + 1e-300;
+    masked.clear();
+    double last = 0;
+    for (int t = 0;; ++t) {
+      double v;
+      const int b = tree->best(ab[a], ad[a], &v);
+      if (b < 0 || !(v < bound)) break;
+      if (t >= topk && v > last + 1e-12 * (std::fabs(last) + scale)) break;
+      keep[b] = 1;
+      last = v;
+      tree->update(b, tree->s[b], true);
+      masked.push_back(b);
+    }
+    for (int b : masked) tree->update(b, tree->s[b], false);
+  }
+  std::vector<int> out;
+  for (int b = 0; b < nb; ++b)
+    if (keep[b]) out.push_back(b);
+  return out;
+}
+
+// Indices a of the query set with some b of the tree at a positive saving
+// (same margin).
+std::vector<int> has_candidate(const KDTree& tree, const std::vector<double>& ab,
+                               const std::vector<double>& ad, const std::vector<double>& da,
+                               double scale) {
+  std::vector<int> out;
+  for (size_t a = 0; a < ab.size(); ++a) {
+    double v;
+    const int b = tree.best(ab[a], ad[a], &v);
+    if (b >= 0 && v < da[a] + 1e-9 * (da[a] + scale) + 1e-300) out.push_back(int(a));
+  }
+  return out;
+}
+
+}  // namespace
+
+// The solver's assignment: exact reductions first, then the exact method up
+// to a problem size (TS_EXACT_MAX, default 4000 points + targets) and the
+// auction above it.  Reductions, each of which keeps every optimum:
+//  (a) a point (target) with no target (point) at a positive saving
+//      w = diag(p) + diag(q) - c(p,q) goes to the diagonal;
+//  (b) with k targets left, a target is matched in an optimum to one of its
+//      k best points by saving: otherwise one of those is free and takes its
+//      place with a larger saving.  The same holds with the roles swapped.
 double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
                       std::vector<int>* match) {
   int64_t limit = 4000;
   if (const char* e = std::getenv("TS_EXACT_MAX")) limit = std::atoll(e);
-  if (int64_t(pb.size() + qb.size()) <= limit) return assign_exact(pb, pd, qb, qd, match);
-  return assign_auction(pb, pd, qb, qd, match, 1e-9);
+  const int m = int(pb.size()), k = int(qb.size());
+  match->assign(m, -1);
+  std::vector<double> dp(m), dq(k);
+  double maxdp = 0, maxdq = 0;
+  for (int i = 0; i < m; ++i) maxdp = std::max(maxdp, dp[i] = diag_cost(pb[i], pd[i]));
+  for (int j = 0; j < k; ++j) maxdq = std::max(maxdq, dq[j] = diag_cost(qb[j], qd[j]));
+  if (m + k <= 64) return assign_exact(pb, pd, qb, qd, match);
+
+  // rows and columns still in the problem (indices into the inputs)
+  std::vector<int> rows(m), cols(k);
+  for (int i = 0; i < m; ++i) rows[i] = i;
+  for (int j = 0; j < k; ++j) cols[j] = j;
+  auto gather = [](const std::vector<double>& v, const std::vector<int>& ix) {
+    std::vector<double> o(ix.size());
+    for (size_t t = 0; t < ix.size(); ++t) o[t] = v[ix[t]];
+    return o;
+  };
+  // side 0: points (rows), side 1: targets (columns)
+  std::vector<int>* idx[2] = {&rows, &cols};
+  const std::vector<double>* B[2] = {&pb, &qb};
+  const std::vector<double>* D[2] = {&pd, &qd};
+  const std::vector<double>* S[2] = {&dp, &dq};
+  const double scale = maxdp + maxdq;
+  auto make_tree = [&](int side, KDTree* tree, std::vector<double>* b, std::vector<double>* d) {
+    *b = gather(*B[side], *idx[side]);
+    *d = gather(*D[side], *idx[side]);
+    tree->build(b->data(), d->data(), int(b->size()));
+    tree->set_all(gather(*S[side], *idx[side]));
+  };
+  auto prune = [&](int side) {  // (a): items of `side` with no partner in the other side
+    std::vector<int>& mine = *idx[side];
+    if (mine.empty()) return;
+    KDTree tree;
+    std::vector<double> tb, td;
+    make_tree(1 - side, &tree, &tb, &td);
+    const std::vector<int> keep = has_candidate(tree, gather(*B[side], mine),
+                                                gather(*D[side], mine), gather(*S[side], mine),
+                                                scale);
+    std::vector<int> kept(keep.size());
+    for (size_t t = 0; t < keep.size(); ++t) kept[t] = mine[keep[t]];
+    mine.swap(kept);
+  };
+  auto top_k = [&](int side) {  // (b): keep the k best of `side` of every item of the other
+    std::vector<int>& mine = *idx[side];
+    const std::vector<int>& other = *idx[1 - side];
+    KDTree tree;
+    std::vector<double> tb, td;
+    make_tree(side, &tree, &tb, &td);
+    const std::vector<int> keep =
+        top_candidates(&tree, gather(*B[1 - side], other), gather(*D[1 - side], other),
+                       gather(*S[1 - side], other), scale, int(mine.size()), int(other.size()));
+    std::vector<int> kept(keep.size());
+    for (size_t t = 0; t < keep.size(); ++t) kept[t] = mine[keep[t]];
+    mine.swap(kept);
+  };
+  prune(0);
+  prune(1);
+  if (!cols.empty() && int64_t(rows.size()) > 4 * int64_t(cols.size()))
+    top_k(0);  // few targets
+  else if (!rows.empty() && int64_t(cols.size()) > 4 * int64_t(rows.size()))
+    top_k(1);  // few points
+
+  const std::vector<double> rb = gather(pb, rows), rd = gather(pd, rows);
+  const std::vector<double> cb = gather(qb, cols), cd = gather(qd, cols);
+  std::vector<int> sub;
+  if (int64_t(rows.size() + cols.size()) <= limit) {
+    assign_exact(rb, rd, cb, cd, &sub);
+  } else {
+    assign_auction(rb, rd, cb, cd, &sub, 1e-9);
+  }
+  std::vector<char> used(k, 0);
+  for (size_t t = 0; t < rows.size(); ++t)
+    if (sub[t] >= 0) {
+      (*match)[rows[t]] = cols[sub[t]];
+      used[cols[sub[t]]] = 1;
+    }
+  double total = 0;
+  for (int i = 0; i < m; ++i) {
+    const int j = (*match)[i];
+    total += j >= 0 ? pair_cost(pb[i], pd[i], qb[j], qd[j]) : dp[i];
+  }
+  for (int j = 0; j < k; ++j)
+    if (!used[j]) total += dq[j];
+  return total;
 }
 
 // ---------------------------------------------------------------- loop

@@ -73,6 +73,25 @@ def test_assignment_matches_oracle(ts, orc, seed, m, k, dense):
     assert ct == pytest.approx(co, rel=1e-12, abs=1e-15)
 
 
+@pytest.mark.parametrize("seed,m,k", [(0, 700, 4), (1, 500, 12), (2, 6, 600), (3, 400, 1)])
+def test_assignment_reductions_match_oracle(ts, orc, seed, m, k):
+    """Many noise points against a few far targets (and the reverse): the
+    exact reductions before the assignment keep the oracle's optimum."""
+    rng = np.random.default_rng(300 + seed)
+    many, few = max(m, k), min(m, k)
+    nb = rng.random(many)
+    nd = nb + np.abs(rng.normal(0, 0.03, many))
+    fb = rng.random(few) * 0.5
+    fd = fb + 0.1 + rng.random(few) * 0.4
+    pb, pd, qb, qd = (nb, nd, fb, fd) if m >= k else (fb, fd, nb, nd)
+    pb, pd, qb, qd = [a.astype(np.float32).astype(np.float64) for a in (pb, pd, qb, qd)]
+    assert len(pb) == m and len(qb) == k
+    mt, ct = ts.assign(pb, pd, qb, qd)
+    mo, co = orc.assign(pb, pd, qb, qd)
+    assert np.array_equal(mt, mo)
+    assert ct == pytest.approx(co, rel=1e-12, abs=1e-15)
+
+
 def test_assignment_bad_arguments(ts):
     out = np.zeros(1, np.int32)
     cost = np.zeros(1, np.float64)
