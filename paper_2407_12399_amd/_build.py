@@ -14,7 +14,7 @@ HEADERS = ["internal.h", "persistence.h", "solver.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall",
           "-Wno-unused-result", f"-I{os.path.join(HERE, '..', 'include')}"]
 # no packed FP32 instructions in device code
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -56,7 +56,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     if failed:
         raise RuntimeError("HIP build failed:\n" + "\n".join(failed))
     tmp = LIB + ".tmp"
-    link = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + [_obj(s) for s in SOURCES]
+    link = [HIPCC, "-shared", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + [_obj(s) for s in SOURCES]
     subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB

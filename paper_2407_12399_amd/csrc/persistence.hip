@@ -61,6 +61,7 @@ struct StarTables {
   uint8_t tet_local[6][4];   // canonical tet type, chain position -> star index
   uint8_t tri_chain[12][3];  // corner masks of the canonical chains
   uint16_t negx, posx, negy, posy, negz, posz;  // neighbours leaving the box side
+  int8_t nb_diff[14][14];    // star index of offset nb[b] - nb[a], -1 if not a neighbour
 };
 
 __constant__ StarTables c_st;
@@ -150,6 +151,13 @@ StarTables build_tables() {
     if (c.z < 0) T.negz |= 1u << k;
     if (c.z > 0) T.posz |= 1u << k;
   }
+  for (int a = 0; a < 14; ++a)
+    for (int b = 0; b < 14; ++b) {
+      const V3 d = {nb[b].x - nb[a].x, nb[b].y - nb[a].y, nb[b].z - nb[a].z};
+      T.nb_diff[a][b] = -1;
+      for (int k = 0; k < 14; ++k)
+        if (nb[k].x == d.x && nb[k].y == d.y && nb[k].z == d.z) T.nb_diff[a][b] = int8_t(k);
+    }
   int nt = 0;
   for (int a = 0; a < 14; ++a)
     for (int b = a + 1; b < 14; ++b) {
@@ -345,8 +353,20 @@ struct CritOut {
 };
 
 constexpr int kGradThreads = 256;
-constexpr int kSlotBytes = 80;  // >= 74 lower-star cells (excluding the centre)
+constexpr int kSlotBytes = 74;  // >= 74 lower-star cells (excluding the centre)
 constexpr int kCellBytes = 74;  // 14 edges, 36 triangles, 24 tets
+
+// The star tables that the lower-star loop indexes per lane, staged in LDS
+// (lane-dependent indices into constant memory become vector-memory loads).
+struct HotTables {
+  uint64_t tet_trim[24];
+  uint64_t edge_trim[14];
+  uint32_t tri_tetm[36];
+  uint16_t tri_nbm[36];
+  uint16_t tet_nbm[24];
+  uint8_t tri_tet[36][2];
+  uint8_t pair_tri[14][14];
+};
 
 __global__ void __launch_bounds__(kGradThreads)
 k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restrict__ code_out,
@@ -355,8 +375,20 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
   __shared__ uint8_t s_cell_slot[kCellBytes * kGradThreads];
   __shared__ unsigned int s_cnt[4];
   __shared__ unsigned long long s_base[4];
+  __shared__ HotTables T;
   const int tid = threadIdx.x;
   if (tid < 4) s_cnt[tid] = 0;
+  if (tid < 24) T.tet_trim[tid] = c_st.tet_trim[tid];
+  if (tid < 14) T.edge_trim[tid] = c_st.edge_trim[tid];
+  if (tid < 36) {
+    T.tri_tetm[tid] = c_st.tri_tetm[tid];
+    T.tri_nbm[tid] = c_st.tri_nbm[tid];
+    T.tri_tet[tid][0] = c_st.tri_tet[tid][0];
+    T.tri_tet[tid][1] = c_st.tri_tet[tid][1];
+  }
+  if (tid < 24) T.tet_nbm[tid] = c_st.tet_nbm[tid];
+  if (tid < 196) T.pair_tri[tid / 14][tid % 14] = c_st.pair_tri[tid / 14][tid % 14];
+  __syncthreads();
   uint8_t* slot_cell = s_slot_cell + tid;  // element i at [i * kGradThreads]
   uint8_t* cell_slot = s_cell_slot + tid;
 #define SLOT_CELL(i) slot_cell[(i) * kGradThreads]
@@ -406,10 +438,10 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
       uint32_t Lq = 0;
 #pragma unroll
       for (int t = 0; t < 36; ++t)
-        if ((uint32_t(c_st.tri_nbm[t]) & low) == uint32_t(c_st.tri_nbm[t])) Lt |= 1ull << t;
+        if ((uint32_t(T.tri_nbm[t]) & low) == uint32_t(T.tri_nbm[t])) Lt |= 1ull << t;
 #pragma unroll
       for (int q = 0; q < 24; ++q)
-        if ((uint32_t(c_st.tet_nbm[q]) & low) == uint32_t(c_st.tet_nbm[q])) Lq |= 1u << q;
+        if ((uint32_t(T.tet_nbm[q]) & low) == uint32_t(T.tet_nbm[q])) Lq |= 1u << q;
 
       // lower-star cells in lexicographic order: by highest other vertex P,
       // then the triangle (P,Q) for increasing Q followed by its tets (P,Q,R)
@@ -426,7 +458,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
         ++s;
         for (int Q = 0; Q < P; ++Q) {
           const int b = int(nib(bypos, Q));
-          const int t = c_st.pair_tri[a][b];
+          const int t = T.pair_tri[a][b];
           if (t == 255) continue;
           SLOT_CELL(s) = uint8_t((2u << 6) | t);
           CELL_SLOT(14 + t) = uint8_t(s);
@@ -436,9 +468,9 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
           uint32_t ra = 0, rb = 0;
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
-            const int q = c_st.tri_tet[t][i];
+            const int q = T.tri_tet[t][i];
             if (!((Lq >> q) & 1u)) continue;
-            const uint32_t third = uint32_t(c_st.tet_nbm[q]) & ~uint32_t(c_st.tri_nbm[t]);
+            const uint32_t third = uint32_t(T.tet_nbm[q]) & ~uint32_t(T.tri_nbm[t]);
             const uint32_t rp = nib(pos, ffs32(third));
             if (rp >= uint32_t(Q)) continue;
             if (qa < 0) {
@@ -477,20 +509,20 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
         else m1 |= 1ull << (sl - 64);
       };
       auto push_edge_cof = [&](int k) {
-        uint64_t m = c_st.edge_trim[k] & Lt;
+        uint64_t m = T.edge_trim[k] & Lt;
         while (m) {
           const int t = ffs64(m);
           m &= m - 1;
-          if (__popc(uint32_t(c_st.tri_nbm[t]) & ~Ec) == 1)
+          if (__popc(uint32_t(T.tri_nbm[t]) & ~Ec) == 1)
             set_slot(O0, O1, CELL_SLOT(14 + t));
         }
       };
       auto push_tri_cof = [&](int t) {
-        uint32_t m = c_st.tri_tetm[t] & Lq;
+        uint32_t m = T.tri_tetm[t] & Lq;
         while (m) {
           const int q = ffs32(m);
           m &= m - 1;
-          if (__popcll(c_st.tet_trim[q] & ~Tc) == 1) set_slot(O0, O1, CELL_SLOT(50 + q));
+          if (__popcll(T.tet_trim[q] & ~Tc) == 1) set_slot(O0, O1, CELL_SLOT(50 + q));
         }
       };
       auto set_tcode = [&](int t, uint32_t c) {
@@ -513,7 +545,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
           const int dim = int(cc >> 6), idx = int(cc & 63u);
           if (dim == 2) {
             if ((Tc >> idx) & 1ull) continue;
-            const uint32_t u = uint32_t(c_st.tri_nbm[idx]) & ~Ec;
+            const uint32_t u = uint32_t(T.tri_nbm[idx]) & ~Ec;
             if (u == 0) {
               set_slot(Z0, Z1, sl);
               continue;
@@ -521,13 +553,13 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
             const int k = ffs32(u);
             Ec |= 1u << k;
             Tc |= 1ull << idx;
-            const uint32_t j = __popcll(c_st.edge_trim[k] & ((1ull << idx) - 1ull));
+            const uint32_t j = __popcll(T.edge_trim[k] & ((1ull << idx) - 1ull));
             ecode |= uint64_t(j) << (3 * k);
             push_tri_cof(idx);
             push_edge_cof(k);
           } else {
             if ((Qc >> idx) & 1u) continue;
-            const uint64_t u = c_st.tet_trim[idx] & ~Tc;
+            const uint64_t u = T.tet_trim[idx] & ~Tc;
             if (u == 0) {
               set_slot(Z0, Z1, sl);
               continue;
@@ -535,7 +567,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
             const int t = ffs64(u);
             Tc |= 1ull << t;
             Qc |= 1u << idx;
-            set_tcode(t, c_st.tri_tet[t][0] == idx ? 2u : 3u);
+            set_tcode(t, T.tri_tet[t][0] == idx ? 2u : 3u);
             push_tri_cof(t);
           }
         }
@@ -764,8 +796,10 @@ __global__ void k_uf_hook(const uint32_t* __restrict__ list, const unsigned int*
     return;
   }
   const unsigned int pr = descending ? unsigned(nedges - 1 - i) : i;
-  atomicMin(&best[a], pr);
-  atomicMin(&best[b], pr);
+  // best[] of a large component is hit by many edges: a plain read filters
+  // out most of the atomics (best only decreases within a round)
+  if (pr < best[a]) atomicMin(&best[a], pr);
+  if (pr < best[b]) atomicMin(&best[b], pr);
 }
 
 struct PairOut {
@@ -961,73 +995,76 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
 // K7: saddle-saddle pairs
 // ======================================================================
 
-// Edge given by its higher vertex h and the star index k of the other vertex.
-__device__ __forceinline__ int nb_index(int dx, int dy, int dz) {
-  if (dx >= 0 && dy >= 0 && dz >= 0) return (dx | (dy << 1) | (dz << 2)) - 1;
-  return 7 + ((-dx) | ((-dy) << 1) | ((-dz) << 2)) - 1;
-}
-
-struct EdgeRef {
-  uint64_t key;  // rank(h) << 32 | rank(other)
-  uint32_t ref;  // h << 4 | k
+// Per-lane scratch with an interleaved layout: element j of lane t lives at
+// [j * stride + t], so that the lanes of a wave touching the same depth hit
+// the same cache lines.
+struct LaneHeap {  // max-heap of edge keys (duplicates allowed)
+  uint64_t* key;
+  uint32_t* ref;
+  int64_t stride;
+  int len, cap;
+  __device__ uint64_t k(int j) const { return key[int64_t(j) * stride]; }
+  __device__ bool push(uint64_t kk, uint32_t rr) {
+    if (len >= cap) return false;
+    int i = len++;
+    while (i > 0) {
+      const int p = (i - 1) >> 1;
+      const uint64_t pk = k(p);
+      if (pk >= kk) break;
+      key[int64_t(i) * stride] = pk;
+      ref[int64_t(i) * stride] = ref[int64_t(p) * stride];
+      i = p;
+    }
+    key[int64_t(i) * stride] = kk;
+    ref[int64_t(i) * stride] = rr;
+    return true;
+  }
+  __device__ void pop(uint64_t* kk, uint32_t* rr) {
+    *kk = key[0];
+    *rr = ref[0];
+    --len;
+    if (len == 0) return;
+    const uint64_t lk = k(len);
+    const uint32_t lr = ref[int64_t(len) * stride];
+    int i = 0;
+    while (true) {
+      int c = 2 * i + 1;
+      if (c >= len) break;
+      uint64_t ck = k(c);
+      if (c + 1 < len) {
+        const uint64_t ck2 = k(c + 1);
+        if (ck2 > ck) {
+          ck = ck2;
+          ++c;
+        }
+      }
+      if (ck <= lk) break;
+      key[int64_t(i) * stride] = ck;
+      ref[int64_t(i) * stride] = ref[int64_t(c) * stride];
+      i = c;
+    }
+    key[int64_t(i) * stride] = lk;
+    ref[int64_t(i) * stride] = lr;
+  }
 };
 
-__device__ __forceinline__ EdgeRef make_edge(const Grid& g, const int32_t* __restrict__ rank, int a,
-                                             int b) {
-  const int ra = rank[a], rb = rank[b];
-  const int h = ra > rb ? a : b, o = ra > rb ? b : a;
-  int hx, hy, hz, ox, oy, oz;
-  coords(g, h, &hx, &hy, &hz);
-  coords(g, o, &ox, &oy, &oz);
-  EdgeRef e;
-  e.key = (uint64_t(uint32_t(max(ra, rb))) << 32) | uint32_t(min(ra, rb));
-  e.ref = (uint32_t(h) << 4) | uint32_t(nb_index(ox - hx, oy - hy, oz - hz));
-  return e;
-}
-
-// toggle `e` in the ascending-key array a[0..*len) (keys unique); returns false on overflow
-__device__ __forceinline__ bool toggle_edge(uint64_t* keys, uint32_t* refs, int* len, int cap,
-                                            const EdgeRef& e) {
+// toggle r in the ascending row list rows[0..*len) (interleaved); false on overflow
+__device__ __forceinline__ bool toggle_row(uint32_t* rows, int64_t stride, int* len, int cap,
+                                           uint32_t r) {
   int lo = 0, hi = *len;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (keys[mid] < e.key) lo = mid + 1;
+    if (rows[int64_t(mid) * stride] < r) lo = mid + 1;
     else hi = mid;
   }
-  if (lo < *len && keys[lo] == e.key) {
-    for (int i = lo; i + 1 < *len; ++i) {
-      keys[i] = keys[i + 1];
-      refs[i] = refs[i + 1];
-    }
+  if (lo < *len && rows[int64_t(lo) * stride] == r) {
+    for (int i = lo; i + 1 < *len; ++i) rows[int64_t(i) * stride] = rows[int64_t(i + 1) * stride];
     --*len;
     return true;
   }
   if (*len >= cap) return false;
-  for (int i = *len; i > lo; --i) {
-    keys[i] = keys[i - 1];
-    refs[i] = refs[i - 1];
-  }
-  keys[lo] = e.key;
-  refs[lo] = e.ref;
-  ++*len;
-  return true;
-}
-
-__device__ __forceinline__ bool toggle_row(uint32_t* rows, int* len, int cap, uint32_t r) {
-  int lo = 0, hi = *len;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (rows[mid] < r) lo = mid + 1;
-    else hi = mid;
-  }
-  if (lo < *len && rows[lo] == r) {
-    for (int i = lo; i + 1 < *len; ++i) rows[i] = rows[i + 1];
-    --*len;
-    return true;
-  }
-  if (*len >= cap) return false;
-  for (int i = *len; i > lo; --i) rows[i] = rows[i - 1];
-  rows[lo] = r;
+  for (int i = *len; i > lo; --i) rows[int64_t(i) * stride] = rows[int64_t(i - 1) * stride];
+  rows[int64_t(lo) * stride] = r;
   ++*len;
   return true;
 }
@@ -1038,104 +1075,184 @@ struct ColPool {
   int64_t cap;
 };
 
+struct BoundaryArgs {
+  const uint32_t* cols;
+  const int32_t* tri_ids;
+  const uint64_t* tri_keys;
+  Grid g;
+  NbOff off;
+  const int32_t* rank;
+  const int32_t* order;
+  const uint4* code;
+  const uint32_t* edge_ids_sorted;
+  const uint32_t* edge_pos;
+  int64_t nedges;
+  const uint8_t* edge_state;
+  ColPool pool;
+  uint64_t* col_desc;
+  uint32_t* retry;
+  unsigned int* nretry;
+  int* pool_full;
+  int* err;
+  unsigned long long* stats;
+  int max_steps;
+};
+
 // Morse boundary of critical triangle column c (mod 2, restricted to the
-// critical edges that do not die in dimension 0), written descending.
-__global__ void k_d1_boundary(const uint32_t* __restrict__ cols, int64_t ncols,
-                              const int32_t* __restrict__ tri_ids,
-                              const uint64_t* __restrict__ tri_keys, Grid g, NbOff off,
-                              const int32_t* __restrict__ rank, const int32_t* __restrict__ order,
-                              const uint4* __restrict__ code,
-                              const uint32_t* __restrict__ edge_ids_sorted,
-                              const uint32_t* __restrict__ edge_pos, int64_t nedges,
-                              const uint8_t* __restrict__ edge_state, uint64_t* __restrict__ wkeys,
-                              uint32_t* __restrict__ wrefs, uint32_t* __restrict__ wrows, int wcap,
-                              int rcap, ColPool pool, uint64_t* __restrict__ col_desc,
-                              uint8_t* __restrict__ overflow, int* __restrict__ err,
-                              int64_t nthreads) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (tid >= nthreads) return;  // scratch is sized for exactly nthreads lanes
-  uint64_t* K = wkeys + tid * wcap;
-  uint32_t* Rf = wrefs + tid * wcap;
-  uint32_t* Rows = wrows + tid * rcap;
-  for (int64_t c = tid; c < ncols; c += nthreads) {
-    if (overflow[c] == 0 && col_desc[c] != ~0ull) continue;  // already done
-    const uint32_t ti = cols[c];
-    const int id = tri_ids[ti];
-    const int y = order[tri_keys[ti] >> 12];
-    const int anchor = id / 12, type = id - 12 * (id / 12);
-    int ax, ay, az, cx, cy, cz;
-    coords(g, anchor, &ax, &ay, &az);
-    coords(g, y, &cx, &cy, &cz);
-    const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
-    const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
-    const int lt = c_st.tri_local[type][p];
-    const int va = y + off.o[c_st.tri_nb[lt][0]], vb = y + off.o[c_st.tri_nb[lt][1]];
-    int wl = 0, rl = 0;
-    bool ok = toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, y, va)) &&
-              toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, y, vb)) &&
-              toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, va, vb));
-    int guard = 0;
-    while (ok && wl > 0) {
-      if (++guard > 64 * g.n) {
-        atomicOr(err, 8);
-        ok = false;
-        break;
-      }
-      --wl;
-      const uint32_t ref = Rf[wl];
-      const int h = int(ref >> 4), k = int(ref & 15u);
-      const uint32_t ec = edge_code(code[h], k);
-      if (ec == 7u) continue;  // paired with its vertex: the path ends
-      if (ec == 6u) {          // critical edge
-        const int lo = h + off.o[k];
-        const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
-        const int64_t f = find_id(edge_ids_sorted, nedges, uint32_t(eid));
-        if (f < 0) {
-          atomicOr(err, 16);
-          continue;
-        }
-        const uint32_t row = edge_pos[f];
-        if (edge_state[row] != 1) continue;  // dies in dimension 0: dropped
-        if (!toggle_row(Rows, &rl, rcap, row)) {
-          ok = false;
-          break;
-        }
+// critical edges that do not die in dimension 0), written descending: the
+// expansion pops the highest edge of the multiset, cancels equal copies in
+// pairs, and replaces an edge paired with a triangle by that triangle's two
+// other edges.  An edge is (key = rank(h) << 32 | rank(o), ref = h << 4 | k)
+// with h the higher vertex and k the star index of o.  A column whose heap or
+// row list overflows, or that needs more than max_steps pops, is appended to
+// the retry list and left unwritten.
+__device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, uint32_t* Rows,
+                                int64_t rstride, int rcap) {
+  const Grid& g = A.g;
+  const uint32_t ti = A.cols[c];
+  const int id = A.tri_ids[ti];
+  const int y = A.order[A.tri_keys[ti] >> 12];
+  const int anchor = id / 12, type = id - 12 * (id / 12);
+  int ax, ay, az, cx, cy, cz;
+  coords(g, anchor, &ax, &ay, &az);
+  coords(g, y, &cx, &cy, &cz);
+  const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
+  const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
+  const int lt = c_st.tri_local[type][p];
+  const int ka = c_st.tri_nb[lt][0], kb = c_st.tri_nb[lt][1];
+  H.len = 0;
+  int rl = 0;
+  // the three edges of the triangle (y is its highest vertex)
+  const uint32_t ry = uint32_t(A.rank[y]);
+  const uint32_t ra = uint32_t(A.rank[y + A.off.o[ka]]), rb = uint32_t(A.rank[y + A.off.o[kb]]);
+  bool ok = H.push((uint64_t(ry) << 32) | ra, (uint32_t(y) << 4) | uint32_t(ka)) &&
+            H.push((uint64_t(ry) << 32) | rb, (uint32_t(y) << 4) | uint32_t(kb));
+  if (ok) {
+    const bool a_hi = ra > rb;
+    const int hv = y + A.off.o[a_hi ? ka : kb];
+    const int kk = c_st.nb_diff[a_hi ? ka : kb][a_hi ? kb : ka];
+    ok = H.push((uint64_t(a_hi ? ra : rb) << 32) | (a_hi ? rb : ra), (uint32_t(hv) << 4) | uint32_t(kk));
+  }
+  int steps = 0, maxlen = H.len;
+  while (ok && H.len > 0) {
+    if (++steps > A.max_steps) {
+      ok = false;
+      break;
+    }
+    maxlen = max(maxlen, H.len);
+    uint64_t key;
+    uint32_t ref;
+    H.pop(&key, &ref);
+    int copies = 1;
+    while (H.len > 0 && H.k(0) == key) {
+      uint64_t k2;
+      uint32_t r2;
+      H.pop(&k2, &r2);
+      ++copies;
+    }
+    if ((copies & 1) == 0) continue;  // cancels mod 2
+    const int h = int(ref >> 4), k = int(ref & 15u);
+    const uint32_t ec = edge_code(A.code[h], k);
+    if (ec == 7u) continue;  // paired with its vertex: the path ends
+    if (ec == 6u) {          // critical edge
+      const int lo = h + A.off.o[k];
+      const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
+      const int64_t f = find_id(A.edge_ids_sorted, A.nedges, uint32_t(eid));
+      if (f < 0) {
+        atomicOr(A.err, 16);
         continue;
       }
-      // paired with the ec-th star triangle containing the edge
-      uint64_t m = c_st.edge_trim[k];
-      for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
-      if (m == 0) {
-        atomicOr(err, 128);
+      const uint32_t row = A.edge_pos[f];
+      if (A.edge_state[row] != 1) continue;  // dies in dimension 0: dropped
+      if (!toggle_row(Rows, rstride, &rl, rcap, row)) {
         ok = false;
         break;
       }
-      const int t = ffs64(m);
-      const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
-      const int lo = h + off.o[k], n2 = h + off.o[k2];
-      EdgeRef e1;
-      e1.key = (uint64_t(uint32_t(rank[h])) << 32) | uint32_t(rank[n2]);
-      e1.ref = (uint32_t(h) << 4) | uint32_t(k2);
-      ok = toggle_edge(K, Rf, &wl, wcap, e1) && toggle_edge(K, Rf, &wl, wcap, make_edge(g, rank, lo, n2));
-    }
-    if (!ok) {
-      overflow[c] = 1;
       continue;
     }
-    overflow[c] = 0;
-    if (rl == 0) {
-      atomicOr(err, 32);  // a negative triangle must have a non-empty boundary
-      col_desc[c] = 0;
-      continue;
+    // paired with the ec-th star triangle (h, o, n2) containing the edge
+    uint64_t m = c_st.edge_trim[k];
+    for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
+    if (m == 0) {
+      atomicOr(A.err, 128);
+      ok = false;
+      break;
     }
-    const unsigned long long at = atomicAdd(pool.top, (unsigned long long)rl);
-    if ((int64_t)(at + rl) > pool.cap) {
-      overflow[c] = 2;  // pool full: retried after growing the pool
-      continue;
+    const int t = ffs64(m);
+    const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
+    const uint32_t rh = uint32_t(key >> 32), ro = uint32_t(key);
+    const uint32_t rn = uint32_t(A.rank[h + A.off.o[k2]]);
+    // edges (h, n2) and (o, n2)
+    ok = H.push((uint64_t(rh) << 32) | rn, (uint32_t(h) << 4) | uint32_t(k2));
+    if (ok) {
+      const int o = h + A.off.o[k];
+      if (ro > rn) {
+        ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(o) << 4) | uint32_t(c_st.nb_diff[k][k2]));
+      } else {
+        const int n2 = h + A.off.o[k2];
+        ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(n2) << 4) | uint32_t(c_st.nb_diff[k2][k]));
+      }
     }
-    for (int i = 0; i < rl; ++i) pool.data[at + i] = Rows[rl - 1 - i];  // descending
-    col_desc[c] = (uint64_t(at) << 24) | uint64_t(rl);
   }
+  if (A.stats) {  // expansion statistics (diagnostics)
+    atomicAdd(&A.stats[0], (unsigned long long)steps);
+    atomicMax(&A.stats[1], (unsigned long long)steps);
+    atomicMax(&A.stats[2], (unsigned long long)maxlen);
+    if (steps > 1000) atomicAdd(&A.stats[3], 1ull);
+    if (!ok) atomicAdd(&A.stats[4], 1ull);
+    atomicAdd(&A.stats[5 + min(31 - __clz(steps | 1), 20)], 1ull);
+  }
+  if (!ok) {
+    A.retry[atomicAdd(A.nretry, 1u)] = c;
+    return;
+  }
+  if (rl == 0) {
+    atomicOr(A.err, 32);  // a negative triangle must have a non-empty boundary
+    A.col_desc[c] = 0;
+    return;
+  }
+  const unsigned long long at = atomicAdd(A.pool.top, (unsigned long long)rl);
+  if ((int64_t)(at + rl) > A.pool.cap) {
+    atomicOr(A.pool_full, 1);  // retried after growing the pool
+    A.retry[atomicAdd(A.nretry, 1u)] = c;
+    return;
+  }
+  for (int i = 0; i < rl; ++i) A.pool.data[at + i] = Rows[int64_t(rl - 1 - i) * rstride];
+  A.col_desc[c] = (uint64_t(at) << 24) | uint64_t(rl);
+}
+
+// Many short columns: one lane per column, heap and rows in global scratch
+// (interleaved, sized for exactly nthreads lanes).
+__global__ void k_d1_boundary(BoundaryArgs A, const uint32_t* __restrict__ todo, int64_t ntodo,
+                              uint64_t* __restrict__ hkeys, uint32_t* __restrict__ hrefs,
+                              uint32_t* __restrict__ hrows, int hcap, int rcap, int64_t nthreads) {
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= nthreads) return;
+  LaneHeap H;
+  H.key = hkeys + tid;
+  H.ref = hrefs + tid;
+  H.stride = nthreads;
+  H.cap = hcap;
+  for (int64_t w = tid; w < ntodo; w += nthreads)
+    boundary_column(A, todo ? todo[w] : uint32_t(w), H, hrows + tid, nthreads, rcap);
+}
+
+// Long columns: one column per workgroup of one wave, heap and rows in LDS,
+// expanded by the first lane (the chain of pops is sequential).
+constexpr int kLdsHeap = 2048, kLdsRows = 1024;
+__global__ void __launch_bounds__(64)
+k_d1_boundary_lds(BoundaryArgs A, const uint32_t* __restrict__ todo, int64_t ntodo) {
+  __shared__ uint64_t s_key[kLdsHeap];
+  __shared__ uint32_t s_ref[kLdsHeap];
+  __shared__ uint32_t s_rows[kLdsRows];
+  if (threadIdx.x != 0) return;
+  LaneHeap H;
+  H.key = s_key;
+  H.ref = s_ref;
+  H.stride = 1;
+  H.cap = kLdsHeap;
+  for (int64_t w = blockIdx.x; w < ntodo; w += gridDim.x)
+    boundary_column(A, todo[w], H, s_rows, 1, kLdsRows);
 }
 
 // Parallel Z2 reduction.  owner[p] is the lowest column whose current pivot
@@ -1856,9 +1973,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       radix_sort_u32(ws, ckeys, cols, ncols, 0, 32, s);
     }
     uint64_t* col_desc = ws.get<uint64_t>("d1.desc", ncols);
-    uint8_t* overflow = ws.get<uint8_t>("d1.ovf", ncols);
     k_fill_u64<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, ~0ull);
-    k_fill_u8<<<blocks_for(ncols), 256, 0, s>>>(overflow, ncols, 0);
     static int64_t pool_hint = 0;
     int64_t pool_cap = std::max<int64_t>(pool_hint, std::max<int64_t>(1 << 20, 16 * ncols));
     ColPool pool;
@@ -1866,44 +1981,87 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     pool.top = ws.get<unsigned long long>("d1.top", 1);
     pool.cap = pool_cap;
     TS_HIP(hipMemsetAsync(pool.top, 0, sizeof(unsigned long long), s));
-    int wcap = 128, rcap = 64;
+    uint32_t* todo[2] = {ws.get<uint32_t>("d1.todoA", ncols + 1),
+                         ws.get<uint32_t>("d1.todoB", ncols + 1)};
+    unsigned int* nretry = ws.get<unsigned int>("d1.nretry", 1);
+    int* bfull = ws.get<int>("d1.bfull", 1);
+    BoundaryArgs BA;
+    BA.cols = cols;
+    BA.tri_ids = R->cid[2];
+    BA.tri_keys = R->ckey[2];
+    BA.g = g;
+    BA.off = off;
+    BA.rank = R->rank;
+    BA.order = R->order;
+    BA.code = R->code;
+    BA.edge_ids_sorted = edge_ids_sorted;
+    BA.edge_pos = edge_pos;
+    BA.nedges = ne;
+    BA.edge_state = estate;
+    BA.nretry = nretry;
+    BA.pool_full = bfull;
+    BA.err = err;
+    BA.stats = nullptr;
+    const int hcap = 64, rcap = 32;
+    int64_t ntodo = ncols;
+    const uint32_t* list = nullptr;  // first pass: every column
     for (int pass = 0;; ++pass) {
-      const int64_t nthreads = std::min<int64_t>(ncols, pass == 0 ? 65536 : 4096);
-      uint64_t* wk = ws.get<uint64_t>("d1.wk", nthreads * wcap);
-      uint32_t* wr = ws.get<uint32_t>("d1.wr", nthreads * wcap);
-      uint32_t* rr = ws.get<uint32_t>("d1.rr", nthreads * rcap);
-      k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(
-          cols, ncols, R->cid[2], R->ckey[2], g, off, R->rank, R->order, R->code, edge_ids_sorted,
-          edge_pos, ne, estate, wk, wr, rr, wcap, rcap, pool, col_desc, overflow, err, nthreads);
-      TS_HIP(hipGetLastError());
-      // any column left to do?
-      std::vector<uint8_t> h_ovf(ncols);
-      TS_HIP(hipMemcpyAsync(h_ovf.data(), overflow, ncols, hipMemcpyDeviceToHost, s));
-      TS_HIP(hipStreamSynchronize(s));
-      bool any = false, pool_full = false;
-      for (uint8_t o : h_ovf) {
-        any = any || o != 0;
-        pool_full = pool_full || o == 2;
+      // pass 0: one lane per column with a bounded number of pops; later
+      // passes: the rest, one column per wave with the heap in LDS
+      const bool lds = pass > 0;
+      const int64_t nthreads = lds ? 0 : std::min<int64_t>(ntodo, int64_t(1) << 20);
+      uint32_t* out = todo[pass & 1];
+      TS_HIP(hipMemsetAsync(nretry, 0, sizeof(unsigned int), s));
+      TS_HIP(hipMemsetAsync(bfull, 0, sizeof(int), s));
+      if (std::getenv("TS_TRACE")) {
+        BA.stats = ws.get<unsigned long long>("d1.bstats", 32);
+        k_fill_u64<<<1, 32, 0, s>>>(reinterpret_cast<uint64_t*>(BA.stats), 32, 0);
       }
-      if (!any) break;
+      BA.pool = pool;
+      BA.col_desc = col_desc;
+      BA.retry = out;
+      BA.max_steps = lds ? 64 * g.n : 512;
+      if (!lds) {
+        uint64_t* hk = ws.get<uint64_t>("d1.hk", nthreads * hcap);
+        uint32_t* hr = ws.get<uint32_t>("d1.hr", nthreads * hcap);
+        uint32_t* rr = ws.get<uint32_t>("d1.rr", nthreads * rcap);
+        k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(BA, list, ntodo, hk, hr, rr, hcap,
+                                                           rcap, nthreads);
+      } else {
+        const unsigned nb = unsigned(std::min<int64_t>(ntodo, 8192));
+        k_d1_boundary_lds<<<nb, 64, 0, s>>>(BA, list, ntodo);
+      }
+      TS_HIP(hipGetLastError());
+      if (BA.stats) {
+        unsigned long long h[32];
+        TS_HIP(hipMemcpyAsync(h, BA.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+        std::fprintf(stderr,
+                     "[topsimp] d1 boundary pass %d: columns %lld %s steps %llu max %llu max heap "
+                     "%llu long %llu retried %llu; log2 histogram:",
+                     pass, (long long)ntodo, lds ? "lds" : "lanes", h[0], h[1], h[2], h[3], h[4]);
+        for (int b = 0; b < 21; ++b) std::fprintf(stderr, " %llu", h[5 + b]);
+        std::fprintf(stderr, "\n");
+      }
+      ntodo = read_scalar(nretry, s);
+      if (ntodo == 0) break;
       if (pass > 12) throw Error(TS_ERR_INTERNAL, "boundary extraction did not finish");
-      if (pool_full) {
+      list = out;
+      if (read_scalar(bfull, s)) {
         // grow the pool keeping its contents
-        const int64_t used = int64_t(read_scalar(pool.top, s));
-        const int64_t ncap = std::max<int64_t>(2 * pool_cap, used + 16 * ncols);
+        // (failed reservations past the old capacity were never written)
+        const int64_t keep = std::min<int64_t>(int64_t(read_scalar(pool.top, s)), pool_cap);
+        const int64_t ncap = std::max<int64_t>(2 * pool_cap, keep + 16 * ncols);
         uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
-        TS_HIP(hipMemcpyAsync(np, pool.data, std::min(used, pool_cap) * sizeof(uint32_t),
-                              hipMemcpyDeviceToDevice, s));
+        TS_HIP(hipMemcpyAsync(np, pool.data, keep * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);
         pool.data = np;
         pool_cap = ncap;
         pool.cap = ncap;
-        unsigned long long top = std::min(used, pool_cap);
-        TS_HIP(hipMemcpyAsync(pool.top, &top, sizeof(top), hipMemcpyHostToDevice, s));
-        TS_HIP(hipStreamSynchronize(s));
-      } else {
-        wcap *= 4;
-        rcap *= 4;
+        k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(keep));
+        TS_HIP(hipGetLastError());
+      } else if (pass > 0) {
+        throw Error(TS_ERR_CAPACITY, "saddle-saddle boundary exceeds the LDS heap");
       }
     }
     pool_hint = std::max(pool_hint, pool_cap);

@@ -20,6 +20,7 @@
 #include <map>
 #include <queue>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -281,44 +282,70 @@ struct Solver {
       if (!still[i]) red.push_back(int(i));
     }
     *n_red = int64_t(red.size());
-    for (int dim = 0; dim < 3; ++dim) {
-      std::vector<int> pi, tj;
+    // one reduced problem per dimension; the three are independent and are
+    // solved on separate host threads
+    struct Problem {
+      std::vector<int> pi, tj, match;
       std::vector<double> pb, pd, qb, qd;
+      double seconds = 0;
+      std::string error;
+    };
+    Problem pr[3];
+    for (int dim = 0; dim < 3; ++dim) {
+      Problem& q = pr[dim];
       for (int i : red)
         if (P[i].dim == dim) {
-          pi.push_back(i);
-          pb.push_back(P[i].b);
-          pd.push_back(P[i].d);
+          q.pi.push_back(i);
+          q.pb.push_back(P[i].b);
+          q.pd.push_back(P[i].d);
         }
+      if (q.pi.empty()) continue;
       for (size_t j = 0; j < T.size(); ++j)
         if (!held[j] && !T[j].ess && T[j].dim == dim) {
-          tj.push_back(int(j));
-          qb.push_back(T[j].b);
-          qd.push_back(T[j].d);
+          q.tj.push_back(int(j));
+          q.qb.push_back(T[j].b);
+          q.qd.push_back(T[j].d);
         }
-      if (pi.empty()) continue;
       if (const char* dir = std::getenv("TS_DUMP_ASSIGN")) {
         static int seq = 0;
         const std::string path = std::string(dir) + "/assign_" + std::to_string(seq++) + "_d" +
                                  std::to_string(dim) + ".bin";
         if (FILE* fp = std::fopen(path.c_str(), "wb")) {
-          const int64_t mm = int64_t(pb.size()), kk = int64_t(qb.size());
+          const int64_t mm = int64_t(q.pb.size()), kk = int64_t(q.qb.size());
           std::fwrite(&mm, 8, 1, fp);
           std::fwrite(&kk, 8, 1, fp);
-          std::fwrite(pb.data(), 8, mm, fp);
-          std::fwrite(pd.data(), 8, mm, fp);
-          std::fwrite(qb.data(), 8, kk, fp);
-          std::fwrite(qd.data(), 8, kk, fp);
+          std::fwrite(q.pb.data(), 8, mm, fp);
+          std::fwrite(q.pd.data(), 8, mm, fp);
+          std::fwrite(q.qb.data(), 8, kk, fp);
+          std::fwrite(q.qd.data(), 8, kk, fp);
+          std::fwrite(q.tj.data(), 4, kk, fp);
           std::fclose(fp);
         }
       }
-      std::vector<int> m;
-      const double t0 = now_s();
-      assign_reduced(pb, pd, qb, qd, &m);
+    }
+    auto solve = [](Problem* q) {
+      try {
+        const double t0 = now_s();
+        assign_reduced(q->pb, q->pd, q->qb, q->qd, &q->match);
+        q->seconds = now_s() - t0;
+      } catch (const std::exception& e) {
+        q->error = e.what();
+      }
+    };
+    std::vector<std::thread> workers;
+    for (int dim = 1; dim < 3; ++dim)
+      if (!pr[dim].pi.empty()) workers.emplace_back(solve, &pr[dim]);
+    if (!pr[0].pi.empty()) solve(&pr[0]);
+    for (std::thread& w : workers) w.join();
+    for (int dim = 0; dim < 3; ++dim) {
+      const Problem& q = pr[dim];
+      if (q.pi.empty()) continue;
+      if (!q.error.empty()) throw Error(TS_ERR_INTERNAL, q.error);
       if (std::getenv("TS_TRACE"))
         std::fprintf(stderr, "[topsimp] assign dim %d: %zu points, %zu targets, %.3f s\n", dim,
-                     pb.size(), qb.size(), now_s() - t0);
-      for (size_t s = 0; s < pi.size(); ++s) (*phi)[pi[s]] = m[s] >= 0 ? tj[m[s]] : -1;
+                     q.pb.size(), q.qb.size(), q.seconds);
+      for (size_t s = 0; s < q.pi.size(); ++s)
+        (*phi)[q.pi[s]] = q.match[s] >= 0 ? q.tj[q.match[s]] : -1;
     }
     canonical_form(P, red, T, phi);
   }
@@ -919,7 +946,9 @@ double assign_reduced(const std::vector<double>& pb, const std::vector<double>& 
   if (int64_t(rows.size() + cols.size()) <= limit) {
     assign_exact(rb, rd, cb, cd, &sub);
   } else {
-    assign_auction(rb, rd, cb, cd, &sub, 1e-9);
+    double eps_rel = 1e-9;
+    if (const char* e = std::getenv("TS_AUCTION_EPS")) eps_rel = std::atof(e);
+    assign_auction(rb, rd, cb, cd, &sub, eps_rel);
   }
   std::vector<char> used(k, 0);
   for (size_t t = 0; t < rows.size(); ++t)
