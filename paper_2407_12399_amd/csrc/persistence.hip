@@ -1283,11 +1283,13 @@ __device__ __forceinline__ void d1_claim_one(uint32_t c, const uint64_t* __restr
 // Device counters: cnt[0] = size of the current list (grows while owners
 // are displaced), cnt[1] = size of the next list, cnt[2] = size of the
 // current list when the round began.
-__global__ void k_d1_round_begin(unsigned int* __restrict__ cnt, int* __restrict__ pool_full) {
+// cnt[3]: long columns deferred to the workgroup kernel this round;
+// cnt[4]: the lowest active column (every column below it is final).
+__global__ void k_d1_round_begin(unsigned int* __restrict__ cnt) {
   cnt[2] = cnt[0];
   cnt[1] = 0;
   cnt[3] = 0;
-  (void)pool_full;
+  cnt[4] = 0xFFFFFFFFu;
 }
 
 __global__ void k_d1_round_end(unsigned int* __restrict__ cnt) { cnt[0] = cnt[1]; }
@@ -1298,8 +1300,14 @@ __global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t
                            unsigned int* __restrict__ cnt) {
   const unsigned int n0 = cnt[2];
   const unsigned int round = *round_ptr;
-  for (unsigned int j = blockIdx.x * blockDim.x + threadIdx.x; j < n0; j += gridDim.x * blockDim.x)
-    d1_claim_one(list[j], col_desc, pool, owner, mark, round, list, &cnt[0]);
+  uint32_t lowest = 0xFFFFFFFFu;
+  for (unsigned int j = blockIdx.x * blockDim.x + threadIdx.x; j < n0; j += gridDim.x * blockDim.x) {
+    const uint32_t c = list[j];
+    lowest = min(lowest, c);
+    d1_claim_one(c, col_desc, pool, owner, mark, round, list, &cnt[0]);
+  }
+  for (int sh = 32; sh >= 1; sh >>= 1) lowest = min(lowest, uint32_t(__shfl_xor(int(lowest), sh, 64)));
+  if ((threadIdx.x & 63u) == 0 && lowest != 0xFFFFFFFFu) atomicMin(&cnt[4], lowest);
 }
 
 __global__ void k_d1_round_inc(unsigned int* __restrict__ round_ptr) { *round_ptr += 1; }
@@ -1374,7 +1382,7 @@ __device__ uint32_t wave_xor(const uint32_t* A, uint32_t a, const uint32_t* B, u
 // workgroup kernel).
 __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
                               const ColPool& pc, const unsigned int* __restrict__ owner,
-                              int* __restrict__ err, uint32_t lo, uint32_t* bufA, uint32_t* bufB,
+                              int* __restrict__ err, uint32_t fin, uint32_t* bufA, uint32_t* bufB,
                               uint32_t* bufO) {
   const unsigned lane = lane_id();
   const uint64_t d = col_desc[c];
@@ -1420,7 +1428,7 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     cur = nxt;
     nxt = t;
     len = w;
-    if (o >= lo || len > kWaveCap) break;  // block owner: one step per round
+    if (o >= fin || len > kWaveCap) break;  // owner not final: one step per round
   }
   if (!changed) return result;
   unsigned long long at = 0;
@@ -1471,88 +1479,172 @@ __device__ __forceinline__ uint32_t count_greater_g(const uint32_t* __restrict__
   return lo;
 }
 
+// Symmetric difference of the descending lists A (a) and B (b) into out,
+// by the whole workgroup; returns the result length.
+__device__ uint32_t block_xor(const uint32_t* A, uint32_t a, const uint32_t* B, uint32_t b,
+                              uint32_t* out, uint32_t* s_wave) {
+  uint32_t keptA = 0, keptB = 0, tot;
+  for (uint32_t base = 0; base < a; base += kLongThreads) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t keep = 0, r = 0, x = 0;
+    if (i < a) {
+      x = A[i];
+      r = count_greater_g(B, b, x);
+      keep = !(r < b && B[r] == x);
+    }
+    const uint32_t pre = keptA + block_scan(keep, s_wave, &tot);
+    if (keep) out[2 * pre - i + r] = x;
+    keptA += tot;
+  }
+  for (uint32_t base = 0; base < b; base += kLongThreads) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t keep = 0, r = 0, x = 0;
+    if (j < b) {
+      x = B[j];
+      r = count_greater_g(A, a, x);
+      keep = !(r < a && A[r] == x);
+    }
+    const uint32_t pre = keptB + block_scan(keep, s_wave, &tot);
+    if (keep) out[2 * pre - j + r] = x;
+    keptB += tot;
+  }
+  __syncthreads();
+  return keptA + keptB;
+}
+
+// Reduce phase for long columns, one workgroup per column.  The working
+// column stays in LDS across the additions of a round (chained through
+// final owners) and is written back once; a column or owner too long for
+// the LDS buffers is reduced in global memory instead.
+constexpr uint32_t kLongCap = 12288;
 __global__ void __launch_bounds__(kLongThreads)
 k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
                  const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ long_list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
-                 int* __restrict__ pool_full, uint32_t lo) {
+                 int* __restrict__ pool_full) {
+  __shared__ uint32_t s_col[2][kLongCap];
+  __shared__ uint32_t s_own[kLongCap];
   __shared__ uint32_t s_wave[kLongThreads / 64 + 1];
   __shared__ uint64_t s_off, s_ooff;
   __shared__ unsigned long long s_at;
   __shared__ uint32_t s_len, s_olen;
   __shared__ int s_state;  // -1 continue, 0 owner, 1 next round, 2 pool full, 3 stop (error)
+  __shared__ int s_lds;    // the working column lives in s_col[cur]
+  __shared__ int s_spill;  // it must move to global memory before the next addition
   const unsigned int nlong = cnt[3];
   const unsigned int round = *round_ptr;
+  const uint32_t fin = cnt[4];  // owners below it are final
   for (unsigned int b = blockIdx.x; b < nlong; b += gridDim.x) {
     const uint32_t c = long_list[b];
+    if (threadIdx.x == 0) {
+      const uint64_t d = col_desc[c];
+      s_len = uint32_t(d & 0xFFFFFFu);
+      s_off = d >> 24;
+      s_lds = s_len <= kLongCap ? 1 : 0;
+      s_state = -1;
+    }
+    __syncthreads();
+    int cur = 0;
+    bool dirty = false;  // the LDS column is newer than col_desc[c]
+    if (s_lds)
+      for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) s_col[0][i] = pool[s_off + i];
+    __syncthreads();
     for (int steps = 0;; ++steps) {
       if (threadIdx.x == 0) {
-        const uint64_t d = col_desc[c];
-        s_len = uint32_t(d & 0xFFFFFFu);
-        s_off = d >> 24;
         s_state = -1;
-        if (s_len == 0 || steps > (1 << 20)) {
+        s_spill = 0;
+        if (s_len == 0 || steps > (1 << 22)) {
           s_state = 3;
           atomicOr(err, 1024);
         } else {
-          const unsigned int o = owner[pool[s_off]];
-          if (o == c) s_state = 0;
-          else if (o > c) s_state = 1;
-          else {
+          const uint32_t piv = s_lds ? s_col[cur][0] : pool[s_off];
+          const unsigned int o = owner[piv];
+          if (o == c) {
+            s_state = 0;
+          } else if (o > c || (steps > 0 && o >= fin)) {
+            s_state = 1;  // unowned, owned later, or owner not final: next round
+          } else {
             const uint64_t od = col_desc[o];
             s_olen = uint32_t(od & 0xFFFFFFu);
             s_ooff = od >> 24;
-            s_at = atomicAdd(pc.top, (unsigned long long)(s_len + s_olen));
-            if ((int64_t)(s_at + s_len + s_olen) > pc.cap) s_state = 2;
-            if (steps > 0 && o >= lo) s_state = 1;  // block owner: one step per round
+            if (s_lds && (s_olen > kLongCap || s_len + s_olen > kLongCap)) s_spill = 1;
           }
         }
       }
       __syncthreads();
       if (s_state >= 0) break;
-      const uint32_t a = s_len, bl = s_olen;
-      const uint32_t* A = pool + s_off;
-      const uint32_t* B = pool + s_ooff;
-      uint32_t* out = pool + s_at;
-      uint32_t keptA = 0, keptB = 0, tot;
-      for (uint32_t base = 0; base < a; base += kLongThreads) {
-        const uint32_t i = base + threadIdx.x;
-        uint32_t keep = 0, r = 0, x = 0;
-        if (i < a) {
-          x = A[i];
-          r = count_greater_g(B, bl, x);
-          keep = !(r < bl && B[r] == x);
+      if (s_spill) {
+        if (dirty) {  // write the LDS column into the pool first
+          if (threadIdx.x == 0) {
+            s_at = atomicAdd(pc.top, (unsigned long long)s_len);
+            if ((int64_t)(s_at + s_len) > pc.cap) s_state = 2;  // this round's progress is dropped
+          }
+          __syncthreads();
+          if (s_state == 2) break;
+          for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) pool[s_at + i] = s_col[cur][i];
+          __threadfence();
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            col_desc[c] = (uint64_t(s_at) << 24) | uint64_t(s_len);
+            s_off = s_at;
+          }
+          dirty = false;
         }
-        const uint32_t pre = keptA + block_scan(keep, s_wave, &tot);
-        if (keep) out[2 * pre - i + r] = x;
-        keptA += tot;
+        if (threadIdx.x == 0) s_lds = 0;
+        __syncthreads();
       }
-      for (uint32_t base = 0; base < bl; base += kLongThreads) {
-        const uint32_t j = base + threadIdx.x;
-        uint32_t keep = 0, r = 0, x = 0;
-        if (j < bl) {
-          x = B[j];
-          r = count_greater_g(A, a, x);
-          keep = !(r < a && A[r] == x);
+      if (s_lds) {
+        for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
+        __syncthreads();
+        const uint32_t w = block_xor(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_wave);
+        cur ^= 1;
+        dirty = true;
+        if (threadIdx.x == 0) {
+          if (w == 0) atomicOr(err, 64);  // a negative column cannot vanish
+          s_len = w;
         }
-        const uint32_t pre = keptB + block_scan(keep, s_wave, &tot);
-        if (keep) out[2 * pre - j + r] = x;
-        keptB += tot;
+        __syncthreads();
+      } else {
+        if (threadIdx.x == 0) {
+          s_at = atomicAdd(pc.top, (unsigned long long)(s_len + s_olen));
+          if ((int64_t)(s_at + s_len + s_olen) > pc.cap) s_state = 2;
+        }
+        __syncthreads();
+        if (s_state == 2) break;
+        const uint32_t w = block_xor(pool + s_off, s_len, pool + s_ooff, s_olen, pool + s_at, s_wave);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          if (w == 0) atomicOr(err, 64);
+          col_desc[c] = (uint64_t(s_at) << 24) | uint64_t(w);
+          s_len = w;
+          s_off = s_at;
+        }
+        __threadfence();
+        __syncthreads();
       }
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const uint32_t w = keptA + keptB;
-        if (w == 0) atomicOr(err, 64);
-        col_desc[c] = (uint64_t(s_at) << 24) | uint64_t(w);
-      }
-      __threadfence();
-      __syncthreads();
     }
+    // write back the LDS column
+    if (dirty && (s_state == 0 || s_state == 1)) {
+      if (threadIdx.x == 0) {
+        s_at = atomicAdd(pc.top, (unsigned long long)s_len);
+        if ((int64_t)(s_at + s_len) > pc.cap) s_state = 2;  // progress dropped
+      }
+      __syncthreads();
+      if (s_state != 2) {
+        for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) pool[s_at + i] = s_col[cur][i];
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) col_desc[c] = (uint64_t(s_at) << 24) | uint64_t(s_len);
+      }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      if (s_state == 2) atomicOr(pool_full, 1);
-      if (s_state == 1 || s_state == 2) {
+      int st = s_state;
+      if (st == 0 && dirty) st = 1;  // the pivot changed this round: claim it next round
+      if (st == 2) atomicOr(pool_full, 1);
+      if (st == 1 || st == 2) {
         mark[c] = round + 1;
         next[atomicAdd(&cnt[1], 1u)] = c;
       }
@@ -1567,17 +1659,18 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
                  const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
-                 int* __restrict__ pool_full, uint32_t lo, uint32_t* __restrict__ long_list) {
+                 int* __restrict__ pool_full, uint32_t* __restrict__ long_list) {
   __shared__ uint32_t s_buf[kRedWaves][3][2 * kWaveCap];
   const unsigned wave = threadIdx.x >> 6;
   const unsigned lane = lane_id();
   const unsigned int n1 = cnt[0];
+  const uint32_t fin = cnt[4];  // owners below it are final
   const unsigned int round = *round_ptr;
   const unsigned gw = blockIdx.x * kRedWaves + wave;
   const unsigned nw = gridDim.x * kRedWaves;
   for (unsigned int j = gw; j < n1; j += nw) {
     const uint32_t c = list[j];
-    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, err, lo, s_buf[wave][0], s_buf[wave][1],
+    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, err, fin, s_buf[wave][0], s_buf[wave][1],
                            s_buf[wave][2]);
     if (r < 0) {  // too long for the wave: handled by a whole workgroup this round
       if (lane == 0) long_list[atomicAdd(&cnt[3], 1u)] = c;
@@ -1595,9 +1688,6 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   }
 }
 
-// The tail of the reduction in one workgroup: same rounds, workgroup
-// barriers instead of kernel boundaries.  Exits when no column is active,
-// when the pool is full (resumable) or after max_rounds (error flag).
 __global__ void k_fill_u32(unsigned int* a, int64_t n, unsigned int v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
@@ -2086,7 +2176,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     unsigned int* mark = ws.get<unsigned int>("d1.mark", ncols + 1);
     uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
     uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
-    unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 4);
+    unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 5);
     uint32_t* long_list = ws.get<uint32_t>("d1.long", ncols + 1);
     int* pool_full = ws.get<int>("d1.full", 1);
     k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
@@ -2132,14 +2222,13 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
         for (int it = 0; it < kCheckEvery; ++it) {
           ++rounds;
-          k_d1_round_begin<<<1, 1, 0, s>>>(cnt, pool_full);
+          k_d1_round_begin<<<1, 1, 0, s>>>(cnt);
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
           k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, mark,
                                                             round_d, A, B, cnt, err, pool_full,
-                                                            uint32_t(lo), long_list);
+                                                            long_list);
           k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, mark,
-                                                       round_d, long_list, B, cnt, err, pool_full,
-                                                       uint32_t(lo));
+                                                       round_d, long_list, B, cnt, err, pool_full);
           k_d1_round_end<<<1, 1, 0, s>>>(cnt);
           k_d1_round_inc<<<1, 1, 0, s>>>(round_d);
           std::swap(A, B);
