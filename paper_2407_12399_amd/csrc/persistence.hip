@@ -711,15 +711,20 @@ __global__ void k_gather_ids(const int32_t* __restrict__ ids, const uint32_t* __
 }
 
 // index of `id` in the id-sorted array, -1 if absent
-__device__ __forceinline__ int64_t find_id(const uint32_t* sorted_ids, int64_t n, uint32_t id) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (sorted_ids[mid] < id) lo = mid + 1;
-    else hi = mid;
-  }
-  return (lo < n && sorted_ids[lo] == id) ? lo : -1;
+// pos_of[id] = position of the critical cell with canonical id `id` in its
+// key-sorted list (entries of non-critical ids are never read)
+__global__ void k_pos_map(const int32_t* __restrict__ ids, int64_t m, int32_t* __restrict__ pos_of) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < m) pos_of[ids[i]] = int32_t(i);
 }
+
+// position of critical cell `id` (checked against the list), -1 if not critical
+__device__ __forceinline__ int64_t crit_pos(const int32_t* __restrict__ pos_of,
+                                            const int32_t* __restrict__ ids, int64_t m, int id) {
+  const int32_t p = pos_of[id];
+  return (p >= 0 && p < m && ids[p] == id) ? p : -1;
+}
+
 
 // ======================================================================
 // K5: min-saddle pairs
@@ -933,8 +938,8 @@ __device__ int ascend(const Grid& g, const NbOff& off, const int32_t* __restrict
 __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
                           int64_t nt, Grid g, NbOff off, const int32_t* __restrict__ rank,
                           const int32_t* __restrict__ order, const uint4* __restrict__ code,
-                          const uint32_t* __restrict__ max_ids_sorted,
-                          const uint32_t* __restrict__ max_pos, int64_t nmax,
+                          const int32_t* __restrict__ max_pos_of,
+                          const int32_t* __restrict__ max_ids, int64_t nmax,
                           int32_t* __restrict__ ca, int32_t* __restrict__ cb,
                           uint32_t* __restrict__ list, int* __restrict__ err) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -977,12 +982,12 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
     if (mid < 0) {
       comp[s] = int(nmax);
     } else {
-      const int64_t f = find_id(max_ids_sorted, nmax, uint32_t(mid));
+      const int64_t f = crit_pos(max_pos_of, max_ids, nmax, mid);
       if (f < 0) {
         atomicOr(err, 4);
         comp[s] = int(nmax);
       } else {
-        comp[s] = int(max_pos[f]);
+        comp[s] = int(f);
       }
     }
   }
@@ -1084,8 +1089,8 @@ struct BoundaryArgs {
   const int32_t* rank;
   const int32_t* order;
   const uint4* code;
-  const uint32_t* edge_ids_sorted;
-  const uint32_t* edge_pos;
+  const int32_t* edge_pos_of;  // canonical edge id -> position among critical edges
+  const int32_t* edge_ids;     // critical edge ids by position
   int64_t nedges;
   const uint8_t* edge_state;
   ColPool pool;
@@ -1157,12 +1162,12 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
     if (ec == 6u) {          // critical edge
       const int lo = h + A.off.o[k];
       const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
-      const int64_t f = find_id(A.edge_ids_sorted, A.nedges, uint32_t(eid));
+      const int64_t f = crit_pos(A.edge_pos_of, A.edge_ids, A.nedges, eid);
       if (f < 0) {
         atomicOr(A.err, 16);
         continue;
       }
-      const uint32_t row = A.edge_pos[f];
+      const uint32_t row = uint32_t(f);
       if (A.edge_state[row] != 1) continue;  // dies in dimension 0: dropped
       if (!toggle_row(Rows, rstride, &rl, rcap, row)) {
         ok = false;
@@ -1292,7 +1297,16 @@ __global__ void k_d1_round_begin(unsigned int* __restrict__ cnt) {
   cnt[4] = 0xFFFFFFFFu;
 }
 
-__global__ void k_d1_round_end(unsigned int* __restrict__ cnt) { cnt[0] = cnt[1]; }
+// end of a round: the next list becomes current, the round advances and the
+// next round begins
+__global__ void k_d1_round_next(unsigned int* __restrict__ cnt, unsigned int* __restrict__ round_ptr) {
+  cnt[0] = cnt[1];
+  *round_ptr += 1;
+  cnt[2] = cnt[0];
+  cnt[1] = 0;
+  cnt[3] = 0;
+  cnt[4] = 0xFFFFFFFFu;
+}
 
 __global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
                            unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
@@ -1310,7 +1324,6 @@ __global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t
   if ((threadIdx.x & 63u) == 0 && lowest != 0xFFFFFFFFu) atomicMin(&cnt[4], lowest);
 }
 
-__global__ void k_d1_round_inc(unsigned int* __restrict__ round_ptr) { *round_ptr += 1; }
 
 // ---- wave-cooperative reduction of one column ----------------------------
 // The working column stays in LDS while it is reduced against a chain of
@@ -1383,7 +1396,7 @@ __device__ uint32_t wave_xor(const uint32_t* A, uint32_t a, const uint32_t* B, u
 __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
                               const ColPool& pc, const unsigned int* __restrict__ owner,
                               int* __restrict__ err, uint32_t fin, uint32_t* bufA, uint32_t* bufB,
-                              uint32_t* bufO) {
+                              uint32_t* bufO, unsigned long long* __restrict__ stats) {
   const unsigned lane = lane_id();
   const uint64_t d = col_desc[c];
   uint32_t len = uint32_t(d & 0xFFFFFFu);
@@ -1394,6 +1407,7 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
   wave_sync();
   bool changed = false;
   int result = 1;
+  int steps_done = 0;
   uint32_t* cur = bufA;
   uint32_t* nxt = bufO;
   for (int steps = 0;; ++steps) {
@@ -1419,6 +1433,7 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     wave_sync();
     const uint32_t w = wave_xor(cur, len, bufB, olen, nxt);
     changed = true;
+    ++steps_done;
     if (w == 0) {
       if (lane == 0) atomicOr(err, 64);
       len = 0;
@@ -1429,6 +1444,11 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     nxt = t;
     len = w;
     if (o >= fin || len > kWaveCap) break;  // owner not final: one step per round
+  }
+  if (stats && lane == 0) {  // diagnostics: columns, additions, longest chain
+    atomicAdd(&stats[0], 1ull);
+    atomicAdd(&stats[1], (unsigned long long)steps_done);
+    atomicMax(&stats[2], (unsigned long long)steps_done);
   }
   if (!changed) return result;
   unsigned long long at = 0;
@@ -1522,7 +1542,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
                  const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ long_list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
-                 int* __restrict__ pool_full) {
+                 int* __restrict__ pool_full, unsigned long long* __restrict__ stats) {
   __shared__ uint32_t s_col[2][kLongCap];
   __shared__ uint32_t s_own[kLongCap];
   __shared__ uint32_t s_wave[kLongThreads / 64 + 1];
@@ -1545,7 +1565,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       s_state = -1;
     }
     __syncthreads();
-    int cur = 0;
+    int cur = 0, nsteps = 0;
     bool dirty = false;  // the LDS column is newer than col_desc[c]
     if (s_lds)
       for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) s_col[0][i] = pool[s_off + i];
@@ -1574,6 +1594,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       }
       __syncthreads();
       if (s_state >= 0) break;
+      ++nsteps;
       if (s_spill) {
         if (dirty) {  // write the LDS column into the pool first
           if (threadIdx.x == 0) {
@@ -1641,6 +1662,11 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+      if (stats) {
+        atomicAdd(&stats[3], 1ull);
+        atomicAdd(&stats[4], (unsigned long long)nsteps);
+        atomicMax(&stats[5], (unsigned long long)nsteps);
+      }
       int st = s_state;
       if (st == 0 && dirty) st = 1;  // the pivot changed this round: claim it next round
       if (st == 2) atomicOr(pool_full, 1);
@@ -1659,7 +1685,8 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
                  const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
-                 int* __restrict__ pool_full, uint32_t* __restrict__ long_list) {
+                 int* __restrict__ pool_full, uint32_t* __restrict__ long_list,
+                 unsigned long long* __restrict__ stats) {
   __shared__ uint32_t s_buf[kRedWaves][3][2 * kWaveCap];
   const unsigned wave = threadIdx.x >> 6;
   const unsigned lane = lane_id();
@@ -1671,7 +1698,7 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   for (unsigned int j = gw; j < n1; j += nw) {
     const uint32_t c = list[j];
     int r = d1_reduce_wave(c, col_desc, pool, pc, owner, err, fin, s_buf[wave][0], s_buf[wave][1],
-                           s_buf[wave][2]);
+                           s_buf[wave][2], stats);
     if (r < 0) {  // too long for the wave: handled by a whole workgroup this round
       if (lane == 0) long_list[atomicAdd(&cnt[3], 1u)] = c;
       wave_sync();
@@ -1976,19 +2003,13 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
                                                          reinterpret_cast<uint32_t*>(ids2));
     R->cid[d] = ids2;
   }
-  // id-sorted lookups for edges (rows) and tets (maxima)
-  auto id_index = [&](int d, uint32_t** ids_sorted, uint32_t** pos) {
-    const int64_t m = R->ncrit[d];
-    *ids_sorted = ws.get<uint32_t>("pm.idsort" + std::to_string(d), m);
-    *pos = ws.get<uint32_t>("pm.idpos" + std::to_string(d), m);
-    if (m == 0) return;
-    TS_HIP(hipMemcpyAsync(*ids_sorted, R->cid[d], m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    k_iota<<<blocks_for(m), 256, 0, s>>>(*pos, m);
-    radix_sort_u32(ws, *ids_sorted, *pos, m, 0, 32, s);
-  };
-  uint32_t *edge_ids_sorted, *edge_pos, *max_ids_sorted, *max_pos;
-  id_index(1, &edge_ids_sorted, &edge_pos);
-  id_index(3, &max_ids_sorted, &max_pos);
+  // id -> position maps for edges (rows) and tets (maxima)
+  int32_t* edge_pos_of = ws.get<int32_t>("pm.edge_pos_of", int64_t(7) * n);
+  int32_t* max_pos_of = ws.get<int32_t>("pm.max_pos_of", int64_t(6) * n);
+  if (R->ncrit[1] > 0)
+    k_pos_map<<<blocks_for(R->ncrit[1]), 256, 0, s>>>(R->cid[1], R->ncrit[1], edge_pos_of);
+  if (R->ncrit[3] > 0)
+    k_pos_map<<<blocks_for(R->ncrit[3]), 256, 0, s>>>(R->cid[3], R->ncrit[3], max_pos_of);
   ctx->timer.stop();
 
   // pair output
@@ -2032,7 +2053,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     uint32_t* listA = ws.get<uint32_t>("uf2.listA", ntri + 1);
     k_fill_u8<<<blocks_for(ntri), 256, 0, s>>>(tstate, ntri, 0);
     k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, g, off, R->rank,
-                                               R->order, R->code, max_ids_sorted, max_pos, nmax,
+                                               R->order, R->code, max_pos_of, R->cid[3], nmax,
                                                ca, cb, listA, err);
     ctx->timer.stop();
     ctx->timer.start("K6 d2 union-find");
@@ -2084,8 +2105,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     BA.rank = R->rank;
     BA.order = R->order;
     BA.code = R->code;
-    BA.edge_ids_sorted = edge_ids_sorted;
-    BA.edge_pos = edge_pos;
+    BA.edge_pos_of = edge_pos_of;
+    BA.edge_ids = R->cid[1];
     BA.nedges = ne;
     BA.edge_state = estate;
     BA.nretry = nretry;
@@ -2210,27 +2231,35 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     int rounds = 0;
     uint32_t* A = listA;
     uint32_t* B = listB;
+    unsigned long long* rstats = nullptr;
+    if (std::getenv("TS_TRACE")) {
+      rstats = ws.get<unsigned long long>("d1.rstats", 8);
+      k_fill_u64<<<1, 8, 0, s>>>(reinterpret_cast<uint64_t*>(rstats), 8, 0);
+    }
     for (int64_t lo = 0; lo < ncols; lo += kBlock) {
       const int64_t hi = std::min<int64_t>(ncols, lo + kBlock);
       unsigned int h_n = unsigned(hi - lo);
       k_iota_from<<<blocks_for(h_n), 256, 0, s>>>(A, h_n, uint32_t(lo));
       k_fill_u32<<<1, 1, 0, s>>>(cnt, 1, h_n);
       k_set_marks<<<blocks_for(h_n), 256, 0, s>>>(mark + lo, h_n, round_d);
-      const unsigned grid = std::min<unsigned>(blocks_for(h_n), 1024u);
-      const unsigned wgrid = std::min<unsigned>(unsigned((h_n + kRedWaves - 1) / kRedWaves), 4096u);
+      k_d1_round_begin<<<1, 1, 0, s>>>(cnt);
       while (h_n > 0) {
+        // grids sized by the last known active count (the kernels stride over
+        // the device-side count, so a later, larger list is still covered)
+        const unsigned grid = std::min<unsigned>(std::max<unsigned>(blocks_for(h_n), 8u), 1024u);
+        const unsigned wgrid =
+            std::min<unsigned>(std::max<unsigned>((2 * h_n + kRedWaves - 1) / kRedWaves, 64u), 4096u);
         TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
         for (int it = 0; it < kCheckEvery; ++it) {
           ++rounds;
-          k_d1_round_begin<<<1, 1, 0, s>>>(cnt);
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
           k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, mark,
                                                             round_d, A, B, cnt, err, pool_full,
-                                                            long_list);
+                                                            long_list, rstats);
           k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, mark,
-                                                       round_d, long_list, B, cnt, err, pool_full);
-          k_d1_round_end<<<1, 1, 0, s>>>(cnt);
-          k_d1_round_inc<<<1, 1, 0, s>>>(round_d);
+                                                       round_d, long_list, B, cnt, err, pool_full,
+                                                       rstats);
+          k_d1_round_next<<<1, 1, 0, s>>>(cnt, round_d);
           std::swap(A, B);
         }
         TS_HIP(hipGetLastError());
@@ -2249,6 +2278,14 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       }
     }
     R->rounds_d1 = rounds;
+    if (rstats) {
+      unsigned long long h[8];
+      TS_HIP(hipMemcpy(h, rstats, sizeof(h), hipMemcpyDeviceToHost));
+      std::fprintf(stderr,
+                   "[topsimp] d1 reduction work: wave columns %llu additions %llu max chain %llu; "
+                   "long columns %llu additions %llu max chain %llu\n",
+                   h[0], h[1], h[2], h[3], h[4], h[5]);
+    }
     length_stats("reduced");
     if (std::getenv("TS_TRACE"))
       std::fprintf(stderr, "[topsimp] d1 reduction: %d rounds, pool %lld / %lld words, %d grows\n",
