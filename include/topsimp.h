@@ -9,8 +9,8 @@
  * Sec. 4.2, and runs the simplification solver of Alg. 1 with the direct
  * gradient step of Sec. 4.1 and the still-pair assignment reuse of Sec. 4.3.
  * Every step of the persistence map, the still-pair join and the update runs
- * in the library's HIP kernels on one GPU; the exact reduced assignment
- * (Eq. 1 with q = 2 on the pairs that are not still) runs on the host.
+ * in the library's HIP kernels on one GPU; the reduced W2 assignment (Eq. 1
+ * with q = 2 on the pairs that are not still) runs on the host.
  *
  * Conventions
  *  - Field: float32, layout [Lz][Ly][Lx] (x fastest), vertex id
@@ -171,12 +171,16 @@ int ts_critical(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_d
 int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
              ts_pair* out, int64_t capacity, int64_t* n_out);
 
-/* Exact W2^2 assignment of one dimension (Eq. 1 with q = 2 on the augmented
+/* W2^2 assignment of one dimension (Eq. 1 with q = 2 on the augmented
  * diagrams, Sec. 2.3 and 4.3), as used by ts_simplify for the pairs that are
  * not still.  Host arrays: points (pb[i], pd[i]), targets (qb[j], qd[j]);
- * match[i] receives the target index or -1 (diagonal); *cost the optimal
- * total (matched squared distances + diagonal costs of everything else).
+ * match[i] receives the target index or -1 (diagonal); *cost the total
+ * (matched squared distances + diagonal costs of everything else).
  * A point and a target with c(p,q) >= diag(p) + diag(q) are never matched.
+ * After exact reductions, a problem of at most 1000 points + targets is
+ * solved exactly (successive shortest paths); a larger one by an
+ * epsilon-scaled auction whose total is within (points + targets) * 1e-9 * W
+ * of the optimum, W = max diag(p) + max diag(q).
  * Needs no context and no GPU. */
 int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
               const double* qd, int32_t* match, double* cost);

@@ -92,6 +92,25 @@ def test_assignment_reductions_match_oracle(ts, orc, seed, m, k):
     assert ct == pytest.approx(co, rel=1e-12, abs=1e-15)
 
 
+@pytest.mark.parametrize("seed,dense", [(0, True), (1, False)])
+def test_large_assignment_within_auction_bound(ts, orc, seed, dense):
+    """Above 1000 points + targets the library runs the epsilon-scaled
+    auction: its total is within (m + k) * 1e-9 * W of the oracle's exact
+    optimum, and the returned matching realises the returned total."""
+    rng = np.random.default_rng(500 + seed)
+    pb, pd, qb, qd = _instance(rng, 700, 650, dense)
+    mt, ct = ts.assign(pb, pd, qb, qd)
+    mo, co = orc.assign(pb, pd, qb, qd)
+    W = ((pd - pb) ** 2 / 2).max() + ((qd - qb) ** 2 / 2).max()
+    assert abs(ct - co) <= (700 + 650) * 1e-9 * W
+    used = mt[mt >= 0]
+    assert len(set(used.tolist())) == len(used)
+    real = sum((pb[i] - qb[t]) ** 2 + (pd[i] - qd[t]) ** 2 if t >= 0 else (pd[i] - pb[i]) ** 2 / 2
+               for i, t in enumerate(mt))
+    real += sum((qd[j] - qb[j]) ** 2 / 2 for j in range(len(qb)) if j not in set(used.tolist()))
+    assert real == pytest.approx(ct, rel=1e-12)
+
+
 def test_assignment_bad_arguments(ts):
     out = np.zeros(1, np.int32)
     cost = np.zeros(1, np.float64)
