@@ -140,6 +140,32 @@ def test_simplify_loss_ratio_and_dim_mask(gpu, orc):
         assert np.array_equal(g.cpu().numpy(), go)
 
 
+def _torus_sdf(n, seed, noise=0.02):
+    """Signed distance to a torus (major radius 0.3, minor 0.1) in the unit
+    cube, plus uniform noise: one dominant saddle-saddle loop among noise."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n) / (n - 1) - 0.5
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    d = np.sqrt((np.sqrt(x * x + y * y) - 0.3) ** 2 + z * z) - 0.1
+    return (d + rng.uniform(-noise, noise, d.shape)).astype(np.float32)
+
+
+@pytest.mark.parametrize("alpha_b,alpha_d", [(0.0, 0.5), (0.5, 0.0)])
+def test_cut_and_fill_parity(gpu, orc, alpha_b, alpha_d):
+    """One-sided steps (only deaths or only births move, Sec. 5.3) on a
+    noisy torus distance field: same iterations and bit-identical g."""
+    f = _torus_sdf(18, 3)
+    kw = dict(threshold=0.1, alpha_b=alpha_b, alpha_d=alpha_d, j_max=30)
+    g, rep = gpu.simplify(_t(f), **kw)
+    go, ro = orc.simplify(f, **kw)
+    assert rep.iterations == ro.iterations and rep.cancelled == ro.cancelled
+    assert np.array_equal(g.cpu().numpy(), go)
+    # the torus loop is signal: it survives
+    D = gpu.diagram(g)
+    pers = D["death"] - D["birth"]
+    assert ((D["dim"] == 1) & (pers > 0.1 * ro.range)).sum() >= 1
+
+
 def test_errors(gpu):
     import torch
     f = np.zeros((3, 3, 3), np.float32)

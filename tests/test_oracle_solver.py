@@ -89,6 +89,37 @@ def test_halfway_step_closed_form(orc):
     assert rep.loss0 == pytest.approx(0.5 ** 2 / 2)
 
 
+@pytest.mark.parametrize("alpha_b,alpha_d", [(0.0, 0.5), (0.5, 0.0)])
+def test_one_sided_steps_closed_form(orc, alpha_b, alpha_d):
+    """Cut / fill variants (Sec. 5.3: only the death or only the birth
+    vertex moves).  On the single-dip field the moving vertex goes to the
+    current midpoint at every step, so the persistence halves per iteration
+    while the other vertex keeps its value; the solver stops at the first
+    iteration whose persistence is below 1e-6 of the range."""
+    dims = (6, 5, 4)
+    f = np.arange(120, dtype=np.float32).reshape(4, 5, 6) * np.float32(1.0)
+    v = 2 + 6 * (2 + 5 * 2)
+    w = v - (1 + 6 + 30)
+    f.ravel()[v] = f.ravel()[w] - np.float32(0.5)
+    g, rep = orc.simplify(f, threshold=0.5, nonsignal_dims=(0,), alpha_b=alpha_b,
+                          alpha_d=alpha_d)
+    b, d = np.float32(f.ravel()[v]), np.float32(f.ravel()[w])
+    tol = 1e-6 * rep.range
+    steps = 0
+    while float(d) - float(b) >= tol:
+        mid = np.float32((b + d) * np.float32(0.5))
+        if alpha_b == 0.0:
+            d = mid
+        else:
+            b = mid
+        steps += 1
+    assert rep.cancelled == 1 and rep.iterations == steps
+    assert g.ravel()[v] == b and g.ravel()[w] == d
+    other = np.ones(f.size, bool)
+    other[[v, w]] = False
+    assert np.array_equal(g.ravel()[other], f.ravel()[other])
+
+
 def test_stability_of_diagrams(orc):
     """bottleneck(D(f), D(g)) <= ||f - g||_inf (stability theorem)."""
     rng = np.random.default_rng(0)
