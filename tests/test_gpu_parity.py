@@ -109,6 +109,60 @@ def test_diagram_filament_48(gpu, orc):
     _same_pairs(gpu.diagram(_t(f)), orc.diagram(f))
 
 
+def test_diagram_gaussian_128(gpu, orc):
+    """The 128^3 workload (64 Gaussians, U[-0.1, 0.1] noise) at full size:
+    the whole diagram, bit-exact."""
+    f = fields.workload("gauss64_128", 0)
+    _same_pairs(gpu.diagram(_t(f)), orc.diagram(f))
+
+
+def test_filament_256_full_size(gpu, orc):
+    """The benchmark's 256^3 workload in the benchmark's launch
+    configuration, where the oracle cannot run the whole map: the vertex
+    order in full, the lower-star gradient on sampled vertices (the oracle
+    processes one lower star at a time), and invariants of the critical cells
+    and pairs that hold at any size."""
+    dims = (256, 256, 256)
+    f = fields.workload("filament_256", 0)
+    order_o, rank_o = orc.order(f)
+    ft = _t(f)
+    order_g, rank_g = gpu.order(ft)
+    assert np.array_equal(order_g.cpu().numpy(), order_o)
+    assert np.array_equal(rank_g.cpu().numpy(), rank_o)
+    del order_g, rank_g
+    vup, eup, tup = gpu.gradient(ft)
+    rng = np.random.default_rng(1)
+    n = f.size
+    for v in rng.integers(0, n, 3000):
+        pairs, crit = orc.gradient_at(rank_o, dims, int(v))
+        for fd, face, cof in pairs:
+            arr = (vup, eup, tup)[fd]
+            assert arr[face] == cof, (v, fd, face, cof)
+        for cd, cid in crit:
+            if cd < 3:
+                assert (vup, eup, tup)[cd][cid] == -1, (v, cd, cid)
+    crit = gpu.critical(ft)
+    c = [len(a) for a in crit]
+    assert c[0] - c[1] + c[2] - c[3] == 1
+    P = gpu.pairs(ft)
+    ess = P["essential"] == 1
+    assert ess.sum() == 1
+    # every critical d-cell is in exactly one pair: the birth of a d-pair or
+    # the death of a (d-1)-pair (the global minimum in the essential one)
+    for d in range(4):
+        cells = []
+        if d < 3:
+            cells.append(P["birth_cell"][P["dim"] == d])
+        if d > 0:
+            cells.append(P["death_cell"][(P["dim"] == d - 1) & ~ess])
+        assert np.array_equal(np.sort(np.concatenate(cells)), np.sort(crit[d])), d
+    # birth before death in the filtration
+    assert np.all(rank_o[P["v_birth"][~ess]] <= rank_o[P["v_death"][~ess]])
+    D = gpu.diagram(ft)
+    assert len(D) == int((P["v_birth"] != P["v_death"]).sum())
+    assert np.all(D["death"] >= D["birth"])
+
+
 def test_host_pointer_path(gpu, orc):
     f = _rand((9, 8, 7), 11, "normal")
     _same_pairs(gpu.diagram(f), orc.diagram(f))
