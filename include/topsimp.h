@@ -94,6 +94,13 @@ typedef struct {
   float cancel_tol_rel;    /* 1e-6 */
   float loss_ratio_s;      /* 0.01 */
   int32_t inputs_on_device; /* f and g are device pointers */
+  float assign_precision;  /* 0: the reduced assignment is exact up to 1000 points +
+                              targets and an auction within (points + targets) *
+                              1e-9 * W above (the default).  > 0: an auction for
+                              every size, stopped once its W2^2 total is within
+                              (1 + assign_precision)^2 of a dual lower bound; the
+                              paper runs 0.01 (Sec. 5).  Results then can differ
+                              from the exact optimum. */
 } ts_options;
 
 typedef struct {
@@ -184,6 +191,16 @@ int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_devi
  * Needs no context and no GPU. */
 int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
               const double* qd, int32_t* match, double* cost);
+
+/* The same problem by the epsilon-scaled auction alone, as ts_simplify runs it
+ * with assign_precision = rel_precision (Sec. 5 uses 0.01): the returned total
+ * is at most (1 + rel_precision)^2 times the optimum.  rel_precision = 0 runs
+ * the auction to its final epsilon 1e-9 * W.  Host arrays as in ts_assign;
+ * TS_ERR_ARG for a negative or non-finite rel_precision.  Needs no context
+ * and no GPU. */
+int ts_assign_auction(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt,
+                      const double* qb, const double* qd, double rel_precision, int32_t* match,
+                      double* cost);
 
 /* Per-kernel device time (ms) of the last ts_diagram / ts_simplify call,
  * measured with HIP events on the context's stream: stage_ms[i] for the

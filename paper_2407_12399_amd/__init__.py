@@ -48,7 +48,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("alpha_b", ctypes.c_float), ("alpha_d", ctypes.c_float),
                 ("j_max", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("cancel_tol_rel", ctypes.c_float), ("loss_ratio_s", ctypes.c_float),
-                ("inputs_on_device", ctypes.c_int32)]
+                ("inputs_on_device", ctypes.c_int32), ("assign_precision", ctypes.c_float)]
 
 
 class _Report(ctypes.Structure):
@@ -67,7 +67,8 @@ _lib = None
 _ctx = {}
 
 EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_simplify",
-           "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_stage_times"]
+           "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
+           "ts_stage_times"]
 
 
 def lib():
@@ -89,6 +90,7 @@ def lib():
         L.ts_critical.argtypes = [P, P, P, i32, P, P, i64, P]
         L.ts_pairs.argtypes = [P, P, P, i32, P, i64, P]
         L.ts_assign.argtypes = [i64, P, P, i64, P, P, P, P]
+        L.ts_assign_auction.argtypes = [i64, P, P, i64, P, P, ctypes.c_double, P, P]
         L.ts_stage_times.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_char_p)),
                                      ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
         for fn in EXPORTS:
@@ -243,6 +245,19 @@ def assign(pb, pd, qb, qd):
     return match[: len(pb)].copy(), float(cost[0])
 
 
+def assign_auction(pb, pd, qb, qd, rel_precision=0.0):
+    """The auction alone (host only), stopped at the given relative precision
+    (0: final epsilon): (match, cost)."""
+    pb, pd, qb, qd = (np.ascontiguousarray(a, dtype=np.float64) for a in (pb, pd, qb, qd))
+    match = np.empty(max(len(pb), 1), np.int32)
+    cost = np.zeros(1, np.float64)
+    rc = lib().ts_assign_auction(len(pb), _ptr(pb), _ptr(pd), len(qb), _ptr(qb), _ptr(qd),
+                                 ctypes.c_double(rel_precision), _ptr(match), _ptr(cost))
+    if rc != 0:
+        raise TopsimpError(rc, "ts_assign_auction failed")
+    return match[: len(pb)].copy(), float(cost[0])
+
+
 def stage_times():
     """{stage name: device ms} of the last call on the current context."""
     ctx = context()
@@ -277,7 +292,7 @@ class Report:
 
 def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
              alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
-             signal_pairs=None, out=None):
+             signal_pairs=None, out=None, assign_precision=0.0):
     """Topological simplification; returns (g, Report).  g has the kind of
     the input (torch CUDA tensor in, torch CUDA tensor out)."""
     ctx = context()
@@ -291,7 +306,8 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
         sig.threshold_rel = threshold
         sig.nonsignal_dim_mask = sum(1 << d for d in nonsignal_dims)
         sig.ties_signal = ties_signal
-    opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev)
+    opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev,
+                   assign_precision)
     rep = _Report()
     torch = _torch()
     if on_dev:

@@ -1,5 +1,6 @@
 // api.cpp -- C ABI of the topsimp library (context, workspace, stage calls).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -323,6 +324,8 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
     const Grid grid = make_grid(dims);
     if (!sig || !opt || !g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
     if (f == g) throw Error(TS_ERR_ARG, "g must not alias f");
+    if (!(opt->assign_precision >= 0) || !std::isfinite(opt->assign_precision))
+      throw Error(TS_ERR_ARG, "assign_precision must be finite and >= 0");
     if (opt->j_max < 0 || opt->stop_mode < 0 || opt->stop_mode > 1)
       throw Error(TS_ERR_ARG, "bad options");
     if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
@@ -344,6 +347,26 @@ int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, 
         QD(qd, qd + n_tgt);
     std::vector<int> m;
     *cost = assign_reduced(PB, PD, QB, QD, &m);
+    for (int64_t i = 0; i < n_pts; ++i) match[i] = m[i];
+    return TS_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return TS_ERR_INTERNAL;
+  }
+}
+
+int ts_assign_auction(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt,
+                      const double* qb, const double* qd, double rel_precision, int32_t* match,
+                      double* cost) {
+  if (n_pts < 0 || n_tgt < 0 || !match || !cost) return TS_ERR_ARG;
+  if ((n_pts > 0 && (!pb || !pd)) || (n_tgt > 0 && (!qb || !qd))) return TS_ERR_ARG;
+  if (!(rel_precision >= 0) || !std::isfinite(rel_precision)) return TS_ERR_ARG;
+  try {
+    std::vector<double> PB(pb, pb + n_pts), PD(pd, pd + n_pts), QB(qb, qb + n_tgt),
+        QD(qd, qd + n_tgt);
+    std::vector<int> m;
+    *cost = assign_reduced(PB, PD, QB, QD, &m, rel_precision, true);
     for (int64_t i = 0; i < n_pts; ++i) match[i] = m[i];
     return TS_OK;
   } catch (const Error& e) {

@@ -22,14 +22,17 @@ double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd
 
 // Near-optimal assignment of the same problem by an epsilon-scaled auction;
 // the total cost is within (points + targets) * eps_rel * W of the optimum,
-// W = max diag(p) + max diag(q).
+// W = max diag(p) + max diag(q).  With gap_rel > 0 it stops after the first
+// phase whose total is within (1 + gap_rel)^2 of the dual lower bound.
 double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
-                      std::vector<int>* match, double eps_rel);
+                      std::vector<int>* match, double eps_rel, double gap_rel = 0.0);
 
-// The solver's choice: exact up to a problem size, the auction above.
+// The solver's choice: exact up to a problem size, the auction above; with
+// gap_rel > 0 the auction with that stopping gap for every size.
 double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
-                      std::vector<int>* match);
+                      std::vector<int>* match, double gap_rel = 0.0,
+                      bool auction_only = false);
 
 }  // namespace ts

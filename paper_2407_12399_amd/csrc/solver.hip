@@ -197,6 +197,7 @@ double now_s() {
 struct Solver {
   std::vector<Tgt> T;
   int ess_target = -1;
+  double gap = 0;  // assignment precision (0: exact / tight auction)
 
   // Signal selection (Sec. 3): D_T = D(f0) minus the non-signal pairs.
   void targets(const std::vector<Pt>& P0, const ts_signal& sig, double range,
@@ -287,12 +288,14 @@ struct Solver {
     struct Problem {
       std::vector<int> pi, tj, match;
       std::vector<double> pb, pd, qb, qd;
+      double gap = 0;
       double seconds = 0;
       std::string error;
     };
     Problem pr[3];
     for (int dim = 0; dim < 3; ++dim) {
       Problem& q = pr[dim];
+      q.gap = gap;
       for (int i : red)
         if (P[i].dim == dim) {
           q.pi.push_back(i);
@@ -326,7 +329,7 @@ struct Solver {
     auto solve = [](Problem* q) {
       try {
         const double t0 = now_s();
-        assign_reduced(q->pb, q->pd, q->qb, q->qd, &q->match);
+        assign_reduced(q->pb, q->pd, q->qb, q->qd, &q->match, q->gap);
         q->seconds = now_s() - t0;
       } catch (const std::exception& e) {
         q->error = e.what();
@@ -571,7 +574,7 @@ struct KDTree {
 // (m + k) * eps_final of the optimum.
 double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
-                      std::vector<int>* match, double eps_rel) {
+                      std::vector<int>* match, double eps_rel, double gap_rel) {
   const int m = int(pb.size()), k = int(qb.size());
   match->assign(m, -1);
   std::vector<double> dp(m), dq(k);
@@ -672,6 +675,31 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       std::fprintf(stderr, "[topsimp] auction phase %d eps %.3g bids %lld\n", phase, eps,
                    (long long)bids);
     if (eps <= eps_final) break;
+    if (gap_rel > 0) {
+      // Dual bound of the square problem (benefits a = -cost, prices p):
+      // optimum <= sum of profits + sum of prices, so cost >= -(that).
+      double dual = 0, primal = 0, dmin = std::numeric_limits<double>::infinity();
+      for (int i = 0; i < m; ++i) dmin = std::min(dmin, price[k + i]);
+      for (int o = 0; o < k + m; ++o) dual += price[o];
+      for (int i = 0; i < m; ++i) {
+        double val;
+        const int j = tree.best(pb[i], pd[i], &val);  // min_j c_ij + p_j
+        double prof = -dp[i] - price[k + i];
+        if (j >= 0) prof = std::max(prof, -val);
+        dual += prof;
+        const int o = holds[i];
+        primal += o < k ? pair_cost(pb[i], pd[i], qb[o], qd[o]) : dp[i];
+      }
+      for (int j = 0; j < k; ++j) {
+        dual += std::max(-dq[j] - price[j], m > 0 ? -dmin : -std::numeric_limits<double>::infinity());
+        if (holds[m + j] == j) primal += dq[j];
+      }
+      const double lower = -dual;
+      if (std::getenv("TS_TRACE"))
+        std::fprintf(stderr, "[topsimp] auction phase %d total %.9g lower bound %.9g\n", phase,
+                     primal, lower);
+      if (lower > 0 && primal <= (1 + gap_rel) * (1 + gap_rel) * lower) break;
+    }
     eps = std::max(eps / 4.0, eps_final);  // a factor of 4 needs the fewest bids on noisy diagrams
   }
   double total = 0;
@@ -875,16 +903,17 @@ std::vector<int> has_candidate(const KDTree& tree, const std::vector<double>& ab
 //      place with a larger saving.  The same holds with the roles swapped.
 double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
-                      std::vector<int>* match) {
-  int64_t limit = 1000;
-  if (const char* e = std::getenv("TS_EXACT_MAX")) limit = std::atoll(e);
+                      std::vector<int>* match, double gap_rel, bool auction_only) {
+  if (gap_rel > 0) auction_only = true;
+  int64_t limit = auction_only ? 0 : 1000;
+  if (const char* e = std::getenv("TS_EXACT_MAX"); e && !auction_only) limit = std::atoll(e);
   const int m = int(pb.size()), k = int(qb.size());
   match->assign(m, -1);
   std::vector<double> dp(m), dq(k);
   double maxdp = 0, maxdq = 0;
   for (int i = 0; i < m; ++i) maxdp = std::max(maxdp, dp[i] = diag_cost(pb[i], pd[i]));
   for (int j = 0; j < k; ++j) maxdq = std::max(maxdq, dq[j] = diag_cost(qb[j], qd[j]));
-  if (m + k <= 64) return assign_exact(pb, pd, qb, qd, match);
+  if (m + k <= 64 && !auction_only) return assign_exact(pb, pd, qb, qd, match);
 
   // rows and columns still in the problem (indices into the inputs)
   std::vector<int> rows(m), cols(k);
@@ -946,7 +975,7 @@ double assign_reduced(const std::vector<double>& pb, const std::vector<double>& 
   if (int64_t(rows.size() + cols.size()) <= limit) {
     assign_exact(rb, rd, cb, cd, &sub);
   } else {
-    assign_auction(rb, rd, cb, cd, &sub, 1e-9);
+    assign_auction(rb, rd, cb, cd, &sub, 1e-9, gap_rel);
   }
   std::vector<char> used(k, 0);
   for (size_t t = 0; t < rows.size(); ++t)
@@ -1007,6 +1036,7 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
   std::vector<Pt> P;
   fetch_points(ctx, R, x, &P);
   Solver S;
+  S.gap = double(opt.assign_precision);
   std::vector<int> phi;
   S.targets(P, sig, range, &phi);
   const double L0 = S.loss(P, phi);

@@ -220,6 +220,26 @@ def test_cut_and_fill_parity(gpu, orc, alpha_b, alpha_d):
     assert ((D["dim"] == 1) & (pers > 0.1 * ro.range)).sum() >= 1
 
 
+def test_paper_auction_precision(gpu, orc):
+    """The paper's assignment setting (auction at relative precision 0.01,
+    Sec. 5) is an option: on a 24^3 noisy field it still cancels every
+    non-signal pair and keeps the signal pairs, though its trajectory may
+    differ from the exact oracle's."""
+    f = fields.gaussian_mixture((24, 24, 24), 8, 0.05, 2)
+    g, rep = gpu.simplify(_t(f), threshold=0.1, assign_precision=0.01)
+    go, ro = orc.simplify(f, threshold=0.1)
+    assert rep.cancelled == 1 and ro.cancelled == 1
+    assert rep.max_nonsignal_pers < 1e-6 * rep.range
+    assert rep.n_targets == ro.n_targets
+    D = gpu.diagram(g)
+    Do = orc.diagram(go)
+    thr = 0.1 * ro.range
+    big = lambda X: sorted(zip(X["dim"][(X["death"] - X["birth"]) > thr].tolist()))
+    assert big(D) == big(Do)
+    with pytest.raises(gpu.TopsimpError):
+        gpu.simplify(_t(f), assign_precision=-1.0)
+
+
 def test_errors(gpu):
     import torch
     f = np.zeros((3, 3, 3), np.float32)

@@ -111,6 +111,30 @@ def test_large_assignment_within_auction_bound(ts, orc, seed, dense):
     assert real == pytest.approx(ct, rel=1e-12)
 
 
+@pytest.mark.parametrize("precision", [0.01, 0.1])
+def test_auction_relative_precision(ts, orc, precision):
+    """The paper's setting (Sec. 5): an auction stopped at a relative
+    precision; its total is within (1 + precision)^2 of the exact optimum
+    and its matching realises the total."""
+    rng = np.random.default_rng(700)
+    pb, pd, qb, qd = _instance(rng, 300, 280, True)
+    mt, ct = ts.assign_auction(pb, pd, qb, qd, precision)
+    _, co = orc.assign(pb, pd, qb, qd)
+    assert co * (1 - 1e-12) <= ct <= (1 + precision) ** 2 * co
+    used = mt[mt >= 0]
+    assert len(set(used.tolist())) == len(used)
+    real = sum((pb[i] - qb[t]) ** 2 + (pd[i] - qd[t]) ** 2 if t >= 0 else (pd[i] - pb[i]) ** 2 / 2
+               for i, t in enumerate(mt))
+    real += sum((qd[j] - qb[j]) ** 2 / 2 for j in range(len(qb)) if j not in set(used.tolist()))
+    assert real == pytest.approx(ct, rel=1e-12)
+    # precision 0 runs to the final epsilon
+    _, c0 = ts.assign_auction(pb, pd, qb, qd, 0.0)
+    W = ((pd - pb) ** 2 / 2).max() + ((qd - qb) ** 2 / 2).max()
+    assert abs(c0 - co) <= (300 + 280) * 1e-9 * W
+    with pytest.raises(ts.TopsimpError):
+        ts.assign_auction(pb, pd, qb, qd, -1.0)
+
+
 def test_assignment_bad_arguments(ts):
     out = np.zeros(1, np.int32)
     cost = np.zeros(1, np.float64)
