@@ -16,7 +16,7 @@ the persistence kernels per map), the per-stage device times (HIP events on
 the library's stream), the roofline of the dominant kernel, and the CPU
 oracle timed on a bounded crop of the same field.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cancel] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cancel] [--paper-stop] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--dims", type=int, nargs=3, default=None)
     ap.add_argument("--cancel", action="store_true",
                     help="also run the solver to full cancellation (or j_max)")
+    ap.add_argument("--paper-stop", action="store_true",
+                    help="also time the solve to the paper's stop rule L <= 0.01 L0")
     ap.add_argument("--j-max", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper-auction", action="store_true",
@@ -223,6 +225,16 @@ def main():
             "assign_s": rp.assign_s, "loss": rp.loss,
             "note": "assignment by an auction stopped at relative precision 0.01 (the paper's "
                     "setting); not parity with the exact oracle"}
+    if args.paper_stop:
+        print(f"[bench] solve to the paper's stop rule (j_max {args.j_max})", file=sys.stderr,
+              flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rs = ts.simplify(ft, j_max=args.j_max, stop_mode=1, loss_ratio_s=0.01, **sig)
+        torch.cuda.synchronize()
+        out["paper_stop_run"] = {"wall_s": time.perf_counter() - t0, "iterations": rs.iterations,
+                                 "stopped": rs.cancelled, "loss0": rs.loss0, "loss": rs.loss,
+                                 "persistence_s": rs.persistence_s, "assign_s": rs.assign_s}
     if args.cancel:
         print(f"[bench] full solve (j_max {args.j_max})", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
