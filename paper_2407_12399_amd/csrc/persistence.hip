@@ -1308,6 +1308,24 @@ __global__ void k_d1_round_next(unsigned int* __restrict__ cnt, unsigned int* __
   cnt[4] = 0xFFFFFFFFu;
 }
 
+// pdesc[p] = the column of p's owner (after the claims of a round, the owner
+// of every claimed pivot keeps its column for the rest of the round), so that
+// a reduction step loads the owner and its column at once.
+__global__ void k_d1_publish(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
+                             const unsigned int* __restrict__ owner, const uint32_t* __restrict__ list,
+                             const unsigned int* __restrict__ cnt, int64_t nall,
+                             uint64_t* __restrict__ pdesc) {
+  const int64_t n = list ? int64_t(cnt[2]) : nall;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t c = list ? list[j] : uint32_t(j);
+    const uint64_t d = col_desc[c];
+    if ((d & 0xFFFFFFu) == 0) continue;
+    const uint32_t piv = pool[d >> 24];
+    if (owner[piv] == c) pdesc[piv] = d;
+  }
+}
+
 __global__ void k_d1_claim(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
                            unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
                            const unsigned int* __restrict__ round_ptr, uint32_t* __restrict__ list,
@@ -1395,6 +1413,7 @@ __device__ uint32_t wave_xor(const uint32_t* A, uint32_t a, const uint32_t* B, u
 // workgroup kernel).
 __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
                               const ColPool& pc, const unsigned int* __restrict__ owner,
+                              const uint64_t* __restrict__ pdesc,
                               int* __restrict__ err, uint32_t fin, uint32_t* bufA, uint32_t* bufB,
                               uint32_t* bufO, unsigned long long* __restrict__ stats) {
   const unsigned lane = lane_id();
@@ -1417,12 +1436,12 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     }
     const uint32_t piv = cur[0];
     const unsigned int o = owner[piv];
+    const uint64_t od = pdesc[piv];  // the owner's column, loaded with the owner
     if (o == c) {
       result = 0;
       break;
     }
     if (o > c) break;  // unowned or owned by a later column: claim next round
-    const uint64_t od = col_desc[o];
     const uint32_t olen = uint32_t(od & 0xFFFFFFu);
     if (olen > kWaveCap || len + olen > 2 * kWaveCap) {
       if (!changed) return -1;
@@ -1539,7 +1558,8 @@ __device__ uint32_t block_xor(const uint32_t* A, uint32_t a, const uint32_t* B, 
 constexpr uint32_t kLongCap = 12288;
 __global__ void __launch_bounds__(kLongThreads)
 k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
-                 const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                 const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
+                 unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ long_list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
                  int* __restrict__ pool_full, unsigned long long* __restrict__ stats) {
@@ -1580,12 +1600,12 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         } else {
           const uint32_t piv = s_lds ? s_col[cur][0] : pool[s_off];
           const unsigned int o = owner[piv];
+          const uint64_t od = pdesc[piv];  // the owner's column, loaded with the owner
           if (o == c) {
             s_state = 0;
           } else if (o > c || (steps > 0 && o >= fin)) {
             s_state = 1;  // unowned, owned later, or owner not final: next round
           } else {
-            const uint64_t od = col_desc[o];
             s_olen = uint32_t(od & 0xFFFFFFu);
             s_ooff = od >> 24;
             if (s_lds && (s_olen > kLongCap || s_len + s_olen > kLongCap)) s_spill = 1;
@@ -1682,7 +1702,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
 // Reduce phase with one wave per active column.
 __global__ void __launch_bounds__(64 * kRedWaves)
 k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
-                 const unsigned int* __restrict__ owner, unsigned int* __restrict__ mark,
+                 const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
+                 unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
                  int* __restrict__ pool_full, uint32_t* __restrict__ long_list,
@@ -1697,7 +1718,7 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   const unsigned nw = gridDim.x * kRedWaves;
   for (unsigned int j = gw; j < n1; j += nw) {
     const uint32_t c = list[j];
-    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, err, fin, s_buf[wave][0], s_buf[wave][1],
+    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, pdesc, err, fin, s_buf[wave][0], s_buf[wave][1],
                            s_buf[wave][2], stats);
     if (r < 0) {  // too long for the wave: handled by a whole workgroup this round
       if (lane == 0) long_list[atomicAdd(&cnt[3], 1u)] = c;
@@ -1936,6 +1957,9 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
 void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R) {
   upload_tables(ctx->device);
   hipStream_t s = ctx->stream;
+  const bool trace = std::getenv("TS_TRACE") != nullptr;
+  if (trace) TS_HIP(hipStreamSynchronize(s));
+  const auto t_wall = std::chrono::steady_clock::now();
   Workspace& ws = ctx->ws;
   const int n = g.n;
   R->g = g;
@@ -2194,6 +2218,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
 
     ctx->timer.start("K7 d1 reduction");
     unsigned int* owner = ws.get<unsigned int>("d1.owner", ne + 1);
+    uint64_t* pdesc = ws.get<uint64_t>("d1.pdesc", ne + 1);
     unsigned int* mark = ws.get<unsigned int>("d1.mark", ncols + 1);
     uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
     uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
@@ -2219,6 +2244,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       pool_cap = ncap;
       pool.cap = ncap;
       k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(live));
+      // owners' columns moved: publish them again
+      k_d1_publish<<<blocks_for(ncols), 256, 0, s>>>(col_desc, pool.data, owner, nullptr, nullptr,
+                                                     ncols, pdesc);
       TS_HIP(hipGetLastError());
       pool_hint = std::max(pool_hint, pool_cap);
     };
@@ -2253,10 +2281,13 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         for (int it = 0; it < kCheckEvery; ++it) {
           ++rounds;
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
-          k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, mark,
+          k_d1_publish<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, A, cnt, 0, pdesc);
+          k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
+                                                            mark,
                                                             round_d, A, B, cnt, err, pool_full,
                                                             long_list, rstats);
-          k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, mark,
+          k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
+                                                       mark,
                                                        round_d, long_list, B, cnt, err, pool_full,
                                                        rstats);
           k_d1_round_next<<<1, 1, 0, s>>>(cnt, round_d);
@@ -2342,6 +2373,12 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   radix_sort_u64(ws, dkeys, R->diag, R->ndiag, 0, 64, s);
   ctx->timer.stop();
   TS_HIP(hipGetLastError());
+  if (trace) {
+    TS_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "[topsimp] persistence map wall %.3f ms\n",
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                           t_wall).count());
+  }
 }
 
 namespace {
