@@ -1139,6 +1139,10 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
     ok = H.push((uint64_t(a_hi ? ra : rb) << 32) | (a_hi ? rb : ra), (uint32_t(hv) << 4) | uint32_t(kk));
   }
   int steps = 0, maxlen = H.len;
+  // edges leave the heap grouped by their higher vertex (it is the high part
+  // of the key): the vertex's gradient code is loaded once per group
+  int code_v = -1;
+  uint4 code_h = make_uint4(0, 0, 0, 0);
   while (ok && H.len > 0) {
     if (++steps > A.max_steps) {
       ok = false;
@@ -1157,7 +1161,11 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
     }
     if ((copies & 1) == 0) continue;  // cancels mod 2
     const int h = int(ref >> 4), k = int(ref & 15u);
-    const uint32_t ec = edge_code(A.code[h], k);
+    if (h != code_v) {
+      code_v = h;
+      code_h = A.code[h];
+    }
+    const uint32_t ec = edge_code(code_h, k);
     if (ec == 7u) continue;  // paired with its vertex: the path ends
     if (ec == 6u) {          // critical edge
       const int lo = h + A.off.o[k];
