@@ -53,6 +53,40 @@ __global__ void k_points(const uint32_t* __restrict__ diag, int64_t nd,
   out_f[2 * k + 1] = x[vd];
 }
 
+// still-join keys (Sec. 4.3): dim << 50 | v_b << 25 | v_d, with the diagram
+// index as payload (a stable sort keeps equal keys in diagram order)
+__global__ void k_join_keys(const int32_t* __restrict__ pts, int64_t np, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ idx) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  keys[k] = (uint64_t(uint32_t(pts[6 * k])) << 50) | (uint64_t(uint32_t(pts[6 * k + 2])) << 25) |
+            uint64_t(uint32_t(pts[6 * k + 3]));
+  idx[k] = uint32_t(k);
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* a, int64_t n, uint64_t key) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// prev_of[i] = the previous diagram's point with the same key and the same
+// occurrence rank among equal keys (the multiset join), or -1
+__global__ void k_join(const uint64_t* __restrict__ ck, const uint32_t* __restrict__ ci, int64_t nc,
+                       const uint64_t* __restrict__ pk, const uint32_t* __restrict__ pi, int64_t np,
+                       int32_t* __restrict__ prev_of) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= nc) return;
+  const uint64_t key = ck[s];
+  const int64_t r = s - lower_bound_u64(ck, nc, key);
+  const int64_t t = lower_bound_u64(pk, np, key) + r;
+  prev_of[ci[s]] = (t < np && pk[t] == key) ? int32_t(pi[t]) : -1;
+}
+
 // contribution keys: vertex << 33 | kind << 32 | diagram index
 __global__ void k_step_keys(const int32_t* __restrict__ vb, const int32_t* __restrict__ vd,
                             int64_t np, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
@@ -138,8 +172,44 @@ uint64_t pkey(int dim, int vb, int vd) {
 // v_d0) targets) receive a canonical assignment: point classes in diagram
 // order take their target classes sorted by lowest member id (diagonal
 // last); a target class hands out its ids in increasing order.
+void canonical_classes(const std::vector<Pt>& P, const std::vector<int>& red,
+                       const std::vector<Tgt>& T, std::vector<int>* phi);
+
+// Only points in a class of two or more, or matched into a target class of
+// two or more, can change; the others are left out of the class bookkeeping.
 void canonical_form(const std::vector<Pt>& P, const std::vector<int>& red, const std::vector<Tgt>& T,
                     std::vector<int>* phi) {
+  auto multi = [](std::vector<std::pair<uint64_t, int>>& v) {  // members of classes of >= 2
+    std::sort(v.begin(), v.end());
+    std::vector<int> idx;
+    for (size_t a = 0; a < v.size();) {
+      size_t b = a + 1;
+      while (b < v.size() && v[b].first == v[a].first) ++b;
+      if (b - a >= 2)
+        for (size_t c = a; c < b; ++c) idx.push_back(v[c].second);
+      a = b;
+    }
+    return idx;
+  };
+  std::vector<std::pair<uint64_t, int>> pk, tk;
+  pk.reserve(red.size());
+  for (int i : red) pk.push_back({pkey(P[i].dim, P[i].vb, P[i].vd), i});
+  for (int i : red)
+    if ((*phi)[i] >= 0) {
+      const Tgt& t = T[(*phi)[i]];
+      tk.push_back({pkey(t.dim, t.vb0, t.vd0), i});
+    }
+  std::vector<char> involved(P.size(), 0);
+  for (int i : multi(pk)) involved[i] = 1;
+  for (int i : multi(tk)) involved[i] = 1;
+  std::vector<int> sub;
+  for (int i : red)
+    if (involved[i]) sub.push_back(i);
+  if (!sub.empty()) canonical_classes(P, sub, T, phi);
+}
+
+void canonical_classes(const std::vector<Pt>& P, const std::vector<int>& red,
+                       const std::vector<Tgt>& T, std::vector<int>* phi) {
   std::unordered_map<uint64_t, int> pcls_of;
   std::vector<std::vector<int>> pcls;
   for (int i : red) {
@@ -243,32 +313,17 @@ struct Solver {
     return m;
   }
 
-  void assign(const std::vector<Pt>& P, const std::vector<Pt>& Pp, const std::vector<int>& phip,
+  // prev_of[i]: the still partner of point i in the previous diagram (-1 if
+  // none), from the device-side join
+  void assign(const std::vector<Pt>& P, const std::vector<int>& prev_of, const std::vector<int>& phip,
               std::vector<int>* phi, int64_t* n_still, int64_t* n_red) {
+    const double t_join = now_s();
     phi->assign(P.size(), -1);
-    // previous points grouped by key, in diagram order
-    std::unordered_map<uint64_t, std::pair<int, int>> head;  // key -> (first, count)
-    std::vector<int> chain(Pp.size(), -1), tail;
-    std::unordered_map<uint64_t, int> last;
-    head.reserve(Pp.size() * 2);
-    for (size_t j = 0; j < Pp.size(); ++j) {
-      const uint64_t k = pkey(Pp[j].dim, Pp[j].vb, Pp[j].vd);
-      auto it = last.find(k);
-      if (it == last.end()) {
-        head[k] = {int(j), 1};
-        last[k] = int(j);
-      } else {
-        chain[it->second] = int(j);
-        it->second = int(j);
-      }
-    }
     std::vector<char> still(P.size(), 0), held(T.size(), 0);
     *n_still = 0;
     for (size_t i = 0; i < P.size(); ++i) {
-      auto it = head.find(pkey(P[i].dim, P[i].vb, P[i].vd));
-      if (it == head.end() || it->second.first < 0) continue;
-      const int j = it->second.first;
-      it->second.first = chain[j];
+      const int j = prev_of[i];
+      if (j < 0) continue;
       still[i] = 1;
       ++*n_still;
       (*phi)[i] = phip[j];
@@ -283,6 +338,7 @@ struct Solver {
       if (!still[i]) red.push_back(int(i));
     }
     *n_red = int64_t(red.size());
+    const double t_build = now_s();
     // one reduced problem per dimension; the three are independent and are
     // solved on separate host threads
     struct Problem {
@@ -326,6 +382,7 @@ struct Solver {
         }
       }
     }
+    const double t_solve = now_s();
     auto solve = [](Problem* q) {
       try {
         const double t0 = now_s();
@@ -350,7 +407,13 @@ struct Solver {
       for (size_t s = 0; s < q.pi.size(); ++s)
         (*phi)[q.pi[s]] = q.match[s] >= 0 ? q.tj[q.match[s]] : -1;
     }
+    const double t_canon = now_s();
     canonical_form(P, red, T, phi);
+    if (std::getenv("TS_TRACE"))
+      std::fprintf(stderr,
+                   "[topsimp] assign host: still join %.3f s, problems %.3f s, solve %.3f s, "
+                   "canonical form %.3f s\n",
+                   t_build - t_join, t_solve - t_build, t_canon - t_solve, now_s() - t_canon);
   }
 };
 
@@ -1035,6 +1098,21 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
 
   std::vector<Pt> P;
   fetch_points(ctx, R, x, &P);
+  // still join on the device: each diagram's keys sorted once, in diagram
+  // order within equal keys (slots alternate between iterations)
+  int slot = 0;
+  int64_t nkeys[2] = {0, 0};
+  auto sort_keys = [&](int sl, int64_t np) {
+    const std::string tag = std::to_string(sl);
+    uint64_t* k = dev<uint64_t>(ctx, ("sim.jk" + tag).c_str(), np + 1);
+    uint32_t* ix = dev<uint32_t>(ctx, ("sim.ji" + tag).c_str(), np + 1);
+    if (np > 0) {
+      k_join_keys<<<nblk(np), 256, 0, s>>>(dev<int32_t>(ctx, "sim.pi", 6 * np + 6), np, k, ix);
+      radix_sort_u64(ctx->ws, k, ix, size_t(np), 0, 52, s);
+    }
+    nkeys[sl] = np;
+  };
+  sort_keys(slot, int64_t(P.size()));
   Solver S;
   S.gap = double(opt.assign_precision);
   std::vector<int> phi;
@@ -1096,8 +1174,27 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
     rep->persistence_s += now_s() - tp;
     // ---- assignment ----
     const double ta = now_s();
+    const int64_t nc = int64_t(Pn.size());
+    std::vector<int> prev_of(nc, -1);
+    {
+      const int prev = slot;
+      slot ^= 1;
+      sort_keys(slot, nc);
+      const std::string c = std::to_string(slot), q = std::to_string(prev);
+      int32_t* po = dev<int32_t>(ctx, "sim.prev_of", nc + 1);
+      if (nc > 0) {
+        k_join<<<nblk(nc), 256, 0, s>>>(dev<uint64_t>(ctx, ("sim.jk" + c).c_str(), nc + 1),
+                                        dev<uint32_t>(ctx, ("sim.ji" + c).c_str(), nc + 1), nc,
+                                        dev<uint64_t>(ctx, ("sim.jk" + q).c_str(), nkeys[prev] + 1),
+                                        dev<uint32_t>(ctx, ("sim.ji" + q).c_str(), nkeys[prev] + 1),
+                                        nkeys[prev], po);
+        TS_HIP(hipGetLastError());
+        TS_HIP(hipMemcpyAsync(prev_of.data(), po, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      }
+      TS_HIP(hipStreamSynchronize(s));
+    }
     std::vector<int> phin;
-    S.assign(Pn, P, phi, &phin, &n_still, &n_red);
+    S.assign(Pn, prev_of, phi, &phin, &n_still, &n_red);
     P.swap(Pn);
     phi.swap(phin);
     L = S.loss(P, phi);
