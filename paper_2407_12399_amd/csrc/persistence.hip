@@ -2119,6 +2119,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     k_fill_u64<<<blocks_for(ncols), 256, 0, s>>>(col_desc, ncols, ~0ull);
     static int64_t pool_hint = 0;
     int64_t pool_cap = std::max<int64_t>(pool_hint, std::max<int64_t>(1 << 20, 16 * ncols));
+    // TS_D1_POOL_WORDS: start from a given pool size (exercises the growth paths)
+    if (const char* e = std::getenv("TS_D1_POOL_WORDS")) pool_cap = std::max<int64_t>(64, std::atoll(e));
     ColPool pool;
     pool.data = ws.get<uint32_t>("d1.pool", pool_cap);
     pool.top = ws.get<unsigned long long>("d1.top", 1);
@@ -2194,7 +2196,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         // grow the pool keeping its contents
         // (failed reservations past the old capacity were never written)
         const int64_t keep = std::min<int64_t>(int64_t(read_scalar(pool.top, s)), pool_cap);
-        const int64_t ncap = std::max<int64_t>(2 * pool_cap, keep + 16 * ncols);
+        const int64_t ncap = std::max<int64_t>(2 * pool_cap, keep + 8 * ntodo);
         uint32_t* np = ws.get<uint32_t>("d1.pool2", ncap);
         TS_HIP(hipMemcpyAsync(np, pool.data, keep * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         std::swap(ws.bufs["d1.pool"], ws.bufs["d1.pool2"]);

@@ -163,6 +163,19 @@ def test_filament_256_full_size(gpu, orc):
     assert np.all(D["death"] >= D["birth"])
 
 
+def test_column_pool_growth(gpu, orc, monkeypatch):
+    """The saddle-saddle column pool starts tiny, so that the boundary pass
+    and the reduction both run out of it and grow it (the reduction compacts
+    the live columns on the device): the diagram is unchanged."""
+    f = fields.gaussian_mixture((40, 36, 33), 64, 0.1, 4)
+    ref = orc.diagram(f)
+    for words in ("256", "6000", "7500", "9000", "20000"):
+        monkeypatch.setenv("TS_D1_POOL_WORDS", words)
+        _same_pairs(gpu.diagram(_t(f)), ref)
+    monkeypatch.delenv("TS_D1_POOL_WORDS")
+    _same_pairs(gpu.diagram(_t(f)), ref)
+
+
 def test_host_pointer_path(gpu, orc):
     f = _rand((9, 8, 7), 11, "normal")
     _same_pairs(gpu.diagram(f), orc.diagram(f))
