@@ -1983,6 +1983,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   static int64_t cap_hint[4] = {0, 0, 0, 0};
   int64_t cap[4];
   for (int d = 0; d < 4; ++d) cap[d] = std::max<int64_t>(cap_hint[d], std::max<int64_t>(1024, n / 4));
+  // TS_CRIT_CAP: start from a given list capacity (exercises the retry path)
+  if (const char* e = std::getenv("TS_CRIT_CAP"))
+    for (int d = 0; d < 4; ++d) cap[d] = std::max<int64_t>(1, std::atoll(e));
   for (int attempt = 0; attempt < 3; ++attempt) {
     CritOut co;
     for (int d = 0; d < 4; ++d) {

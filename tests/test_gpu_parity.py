@@ -176,6 +176,16 @@ def test_column_pool_growth(gpu, orc, monkeypatch):
     _same_pairs(gpu.diagram(_t(f)), ref)
 
 
+def test_critical_list_retry(gpu, orc, monkeypatch):
+    """Critical-cell lists that start too small are sized from the counts
+    and the gradient kernel is run again: same critical cells."""
+    f = _rand((23, 19, 17), 6, "normal")
+    monkeypatch.setenv("TS_CRIT_CAP", "8")
+    for a, b in zip(gpu.critical(_t(f)), orc.critical(f)):
+        assert np.array_equal(a, b)
+    _same_pairs(gpu.diagram(_t(f)), orc.diagram(f))
+
+
 def test_host_pointer_path(gpu, orc):
     f = _rand((9, 8, 7), 11, "normal")
     _same_pairs(gpu.diagram(f), orc.diagram(f))
