@@ -206,6 +206,7 @@ def main():
                    "max_nonsignal_pers_rel": rep.max_nonsignal_pers / rep.range,
                    "persistence_s": rep.persistence_s, "assign_s": rep.assign_s,
                    "update_s": rep.update_s, "n_reduced_last": rep.n_reduced,
+                   "regradient_frac": rep.n_regradient / (n * max(steps, 1)),
                    "n_still_last": rep.n_still, "n_targets": rep.n_targets,
                    "stage_ms_total": solver_stage},
         "roofline": roofline,
@@ -234,7 +235,9 @@ def main():
         torch.cuda.synchronize()
         out["paper_stop_run"] = {"wall_s": time.perf_counter() - t0, "iterations": rs.iterations,
                                  "stopped": rs.cancelled, "loss0": rs.loss0, "loss": rs.loss,
-                                 "persistence_s": rs.persistence_s, "assign_s": rs.assign_s}
+                                 "persistence_s": rs.persistence_s, "assign_s": rs.assign_s,
+                                 "regradient_frac":
+                                     rs.n_regradient / (n * max(rs.iterations, 1))}
     if args.cancel:
         print(f"[bench] full solve (j_max {args.j_max})", file=sys.stderr, flush=True)
         torch.cuda.synchronize()

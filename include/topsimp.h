@@ -101,6 +101,10 @@ typedef struct {
                               (1 + assign_precision)^2 of a dual lower bound; the
                               paper runs 0.01 (Sec. 5).  Results then can differ
                               from the exact optimum. */
+  int32_t full_gradient;   /* 0: after each update, the discrete gradient is recomputed only
+                              for vertices with a changed value in their closed star
+                              (the fast update of Sec. 4.2; same result).  1: the whole
+                              gradient is recomputed every iteration. */
 } ts_options;
 
 typedef struct {
@@ -120,6 +124,8 @@ typedef struct {
   double persistence_s;     /* time in the persistence map (all iterations) */
   double assign_s;          /* time in the still join + assignment */
   double update_s;          /* time in the gradient step */
+  int64_t n_regradient;     /* vertices whose lower star was processed, summed over the
+                               maps after the first (n per map with full_gradient) */
 } ts_report;
 
 typedef struct ts_ctx ts_ctx;

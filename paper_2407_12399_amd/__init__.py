@@ -48,7 +48,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("alpha_b", ctypes.c_float), ("alpha_d", ctypes.c_float),
                 ("j_max", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("cancel_tol_rel", ctypes.c_float), ("loss_ratio_s", ctypes.c_float),
-                ("inputs_on_device", ctypes.c_int32), ("assign_precision", ctypes.c_float)]
+                ("inputs_on_device", ctypes.c_int32), ("assign_precision", ctypes.c_float),
+                ("full_gradient", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -60,7 +61,8 @@ class _Report(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64 * 3), ("n_still", ctypes.c_int64),
                 ("n_reduced", ctypes.c_int64), ("n_targets", ctypes.c_int64),
                 ("total_s", ctypes.c_double), ("persistence_s", ctypes.c_double),
-                ("assign_s", ctypes.c_double), ("update_s", ctypes.c_double)]
+                ("assign_s", ctypes.c_double), ("update_s", ctypes.c_double),
+                ("n_regradient", ctypes.c_int64)]
 
 
 _lib = None
@@ -287,12 +289,13 @@ class Report:
     persistence_s: float
     assign_s: float
     update_s: float
+    n_regradient: int
     status: int
 
 
 def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
              alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
-             signal_pairs=None, out=None, assign_precision=0.0):
+             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False):
     """Topological simplification; returns (g, Report).  g has the kind of
     the input (torch CUDA tensor in, torch CUDA tensor out)."""
     ctx = context()
@@ -307,7 +310,7 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
         sig.nonsignal_dim_mask = sum(1 << d for d in nonsignal_dims)
         sig.ties_signal = ties_signal
     opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev,
-                   assign_precision)
+                   assign_precision, int(bool(full_gradient)))
     rep = _Report()
     torch = _torch()
     if on_dev:
@@ -322,5 +325,5 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
     r = Report(rep.iterations, rep.cancelled, rep.loss0, rep.loss, rep.energy, rep.linf, rep.l2,
                rep.max_nonsignal_pers, rep.max_signal_disp, rep.range, tuple(rep.n_pairs),
                rep.n_still, rep.n_reduced, rep.n_targets, rep.total_s, rep.persistence_s,
-               rep.assign_s, rep.update_s, rc)
+               rep.assign_s, rep.update_s, rep.n_regradient, rc)
     return g, r

@@ -33,13 +33,24 @@ struct PersistenceResult {
   uint32_t* diag = nullptr;
   // round counts of the iterative stages (diagnostics)
   int rounds_d0 = 0, rounds_d2 = 0, rounds_d1 = 0;
+  // vertices whose lower star was processed by the last call (n unless the
+  // fast update ran)
+  int64_t n_regrad = 0;
+  // set when the call finished; the fast update needs a complete previous map
+  bool complete = false;
 };
 
 // Vertex order only (K1 + K2).
 void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* rank);
 
-// The whole persistence map (K1..K8) of a device field.
-void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R);
+// The whole persistence map (K1..K8) of a device field.  With `changed`
+// (device, n bytes, nonzero where the value differs from the field of the
+// previous call on the same R and context), the gradient is updated instead of
+// recomputed (Sec. 4.2): only vertices with a changed value in their closed
+// star run the lower-star loop; the result is the same as a full map.  Nothing
+// else may use the context's workspace between the two calls.
+void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R,
+                         const uint8_t* changed = nullptr);
 
 // ts_pair records of the diagram (diagram order) or of all pairs (device).
 void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool diagram_only,

@@ -368,9 +368,12 @@ struct HotTables {
   uint8_t pair_tri[14][14];
 };
 
+// kList: lane i processes vertex vlist[i] (i < nlist) instead of vertex i.
+template <bool kList>
 __global__ void __launch_bounds__(kGradThreads)
 k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restrict__ code_out,
-           int32_t* __restrict__ down_out, CritOut co) {
+           int32_t* __restrict__ down_out, CritOut co, const uint32_t* __restrict__ vlist,
+           int64_t nlist) {
   __shared__ uint8_t s_slot_cell[kSlotBytes * kGradThreads];
   __shared__ uint8_t s_cell_slot[kCellBytes * kGradThreads];
   __shared__ unsigned int s_cnt[4];
@@ -394,8 +397,9 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
 #define SLOT_CELL(i) slot_cell[(i) * kGradThreads]
 #define CELL_SLOT(i) cell_slot[(i) * kGradThreads]
 
-  const int v = blockIdx.x * kGradThreads + tid;
-  const bool active = v < g.n;
+  const int64_t lane = int64_t(blockIdx.x) * kGradThreads + tid;
+  const bool active = kList ? lane < nlist : lane < g.n;
+  const int v = kList ? (active ? int(vlist[lane]) : 0) : int(lane);
   int rx = 0;
   uint32_t low = 0;
   uint64_t pos = 0;  // nibble k: position of neighbour k among lower neighbours
@@ -680,6 +684,81 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
         co.id[3][p] = 6 * anchor + c_st.tet_type[q];
       }
       ++p;
+    }
+  }
+}
+
+// ---- fast update of the gradient between solver iterations (Sec. 4.2) ----
+// The lower star of v, hence its gradient code, its descent step and its
+// critical cells (up to the rank prefix of their keys), depends only on the
+// relative order of v and its 14 neighbours.  Unchanged values keep their
+// relative order, so only vertices with a changed value in their closed star
+// (dirty vertices) need the lower-star loop again.
+
+// dirty[v] = v or a neighbour changed value; dirty vertices are appended to
+// list (in no particular order) and counted in *count.
+__global__ void k_dirty(const uint8_t* __restrict__ changed, Grid g, NbOff off,
+                        uint8_t* __restrict__ dirty, uint32_t* __restrict__ list,
+                        unsigned int* __restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool d = false;
+  if (i < g.n) {
+    const int v = int(i);
+    int x, y, z;
+    coords(g, v, &x, &y, &z);
+    const uint32_t valid = valid_nbs(g, x, y, z);
+    uint32_t c = changed[v];
+#pragma unroll
+    for (int k = 0; k < 14; ++k)
+      if ((valid >> k) & 1u) c |= changed[v + off.o[k]];
+    d = c != 0;
+    dirty[v] = d ? 1 : 0;
+  }
+  const uint64_t m = __ballot(d);
+  if (m == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(count, unsigned(__popcll(m)));
+  base = unsigned(__shfl(int(base), leader, 64));
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (d) list[base + __popcll(m & lt)] = uint32_t(i);
+}
+
+// Critical cells of the previous map whose highest vertex is clean, with the
+// key prefix replaced by that vertex's new rank.  prev_order maps the old
+// rank prefix back to the vertex.  Appends at count (bounded by cap).
+__global__ void k_keep_crit(const uint64_t* __restrict__ pkey, const int32_t* __restrict__ pid,
+                            int64_t np, const int32_t* __restrict__ prev_order,
+                            const int32_t* __restrict__ rank, const uint8_t* __restrict__ dirty,
+                            uint64_t* __restrict__ key, int32_t* __restrict__ id, int64_t cap,
+                            unsigned long long* __restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool keep = false;
+  uint64_t k = 0;
+  int32_t c = 0;
+  if (i < np) {
+    const uint64_t pk = pkey[i];
+    const int v = prev_order[pk >> 12];
+    keep = dirty[v] == 0;
+    if (keep) {
+      k = (uint64_t(uint32_t(rank[v])) << 12) | (pk & 0xFFFull);
+      c = pid[i];
+    }
+  }
+  const uint64_t m = __ballot(keep);
+  if (m == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  base = (unsigned long long)__shfl((long long)base, leader, 64);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (keep) {
+    const unsigned long long p = base + __popcll(m & lt);
+    if ((int64_t)p < cap) {
+      key[p] = k;
+      id[p] = c;
     }
   }
 }
@@ -1962,7 +2041,8 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
   if (read_scalar(bad, s)) throw Error(TS_ERR_NONFINITE, "field contains NaN or Inf");
 }
 
-void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R) {
+void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R,
+                         const uint8_t* changed) {
   upload_tables(ctx->device);
   hipStream_t s = ctx->stream;
   const bool trace = std::getenv("TS_TRACE") != nullptr;
@@ -1970,13 +2050,57 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   const auto t_wall = std::chrono::steady_clock::now();
   Workspace& ws = ctx->ws;
   const int n = g.n;
+  const bool update = changed != nullptr && R->complete && R->g.Lx == g.Lx && R->g.Ly == g.Ly &&
+                      R->g.Lz == g.Lz;
+  R->complete = false;
   R->g = g;
   R->order = ws.get<int32_t>("pm.order", n);
   R->rank = ws.get<int32_t>("pm.rank", n);
   R->code = ws.get<uint4>("pm.code", n);
   R->down = ws.get<int32_t>("pm.down", n);
+  // the previous order and critical lists, read by the fast update
+  int32_t* prev_order = nullptr;
+  uint64_t* prev_key[4] = {};
+  int32_t* prev_id[4] = {};
+  int64_t prev_n[4] = {0, 0, 0, 0};
+  if (update) {
+    prev_order = ws.get<int32_t>("pm.order_prev", n);
+    TS_HIP(hipMemcpyAsync(prev_order, R->order, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    for (int d = 0; d < 4; ++d) {
+      prev_n[d] = R->ncrit[d];
+      prev_key[d] = ws.get<uint64_t>("pm.ckey_prev" + std::to_string(d), prev_n[d] + 1);
+      prev_id[d] = ws.get<int32_t>("pm.cid_prev" + std::to_string(d), prev_n[d] + 1);
+      if (prev_n[d] > 0) {
+        TS_HIP(hipMemcpyAsync(prev_key[d], R->ckey[d], size_t(prev_n[d]) * 8,
+                              hipMemcpyDeviceToDevice, s));
+        TS_HIP(hipMemcpyAsync(prev_id[d], R->cid[d], size_t(prev_n[d]) * 4,
+                              hipMemcpyDeviceToDevice, s));
+      }
+    }
+  }
   compute_order(ctx, f, n, R->order, R->rank);
   const NbOff off = make_offsets(g);
+
+  // dirty vertices of the fast update
+  uint8_t* dirty = nullptr;
+  uint32_t* dlist = nullptr;
+  int64_t ndirty = n;
+  if (update) {
+    dirty = ws.get<uint8_t>("pm.dirty", n);
+    dlist = ws.get<uint32_t>("pm.dirty_list", n);
+    unsigned int* dcnt = ws.get<unsigned int>("pm.dirty_count", 1);
+    TS_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned int), s));
+    ctx->timer.start("K3 dirty");
+    k_dirty<<<blocks_for(n), 256, 0, s>>>(changed, g, off, dirty, dlist, dcnt);
+    ctx->timer.stop();
+    TS_HIP(hipGetLastError());
+    unsigned int h = 0;
+    TS_HIP(hipMemcpyAsync(&h, dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipStreamSynchronize(s));
+    ndirty = int64_t(h);
+    if (ndirty > n) throw Error(TS_ERR_INTERNAL, "dirty vertex count exceeds the grid");
+  }
+  R->n_regrad = ndirty;
 
   // ---- K3 + K4: gradient and critical cells ----
   unsigned long long* ccount = ws.get<unsigned long long>("pm.ccount", 4);
@@ -1995,10 +2119,27 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     }
     co.count = ccount;
     TS_HIP(hipMemsetAsync(ccount, 0, 4 * sizeof(unsigned long long), s));
-    ctx->timer.start("K3 gradient");
-    k_gradient<<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(R->rank, g, off, R->code,
-                                                                    R->down, co);
-    ctx->timer.stop();
+    if (update) {
+      ctx->timer.start("K3 keep");
+      for (int d = 0; d < 4; ++d)
+        if (prev_n[d] > 0)
+          k_keep_crit<<<blocks_for(prev_n[d]), 256, 0, s>>>(prev_key[d], prev_id[d], prev_n[d],
+                                                            prev_order, R->rank, dirty, co.key[d],
+                                                            co.id[d], co.cap[d], ccount + d);
+      ctx->timer.stop();
+      TS_HIP(hipGetLastError());
+      if (ndirty > 0) {
+        ctx->timer.start("K3 gradient (dirty)");
+        k_gradient<true><<<blocks_for(ndirty, kGradThreads), kGradThreads, 0, s>>>(
+            R->rank, g, off, R->code, R->down, co, dlist, ndirty);
+        ctx->timer.stop();
+      }
+    } else {
+      ctx->timer.start("K3 gradient");
+      k_gradient<false><<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(
+          R->rank, g, off, R->code, R->down, co, nullptr, 0);
+      ctx->timer.stop();
+    }
     TS_HIP(hipGetLastError());
     unsigned long long h[4];
     TS_HIP(hipMemcpyAsync(h, ccount, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -2386,6 +2527,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   radix_sort_u64(ws, dkeys, R->diag, R->ndiag, 0, 64, s);
   ctx->timer.stop();
   TS_HIP(hipGetLastError());
+  R->complete = true;
   if (trace) {
     TS_HIP(hipStreamSynchronize(s));
     std::fprintf(stderr, "[topsimp] persistence map wall %.3f ms\n",

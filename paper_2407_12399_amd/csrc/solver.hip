@@ -101,7 +101,8 @@ __global__ void k_step_keys(const int32_t* __restrict__ vb, const int32_t* __res
 // x[v] <- x[v] - (alpha_b * B(v) + alpha_d * D(v)), sums in diagram order
 __global__ void k_step_apply(const uint64_t* __restrict__ keys, int64_t ne,
                              const float* __restrict__ tb, const float* __restrict__ td,
-                             float* __restrict__ x, float alpha_b, float alpha_d) {
+                             float* __restrict__ x, float alpha_b, float alpha_d,
+                             uint8_t* __restrict__ changed) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const uint32_t v = uint32_t(keys[e] >> 33);
@@ -119,6 +120,8 @@ __global__ void k_step_apply(const uint64_t* __restrict__ keys, int64_t ne,
   float nx = __fsub_rn(xv, s);
   if (nx == 0.0f) nx = 0.0f;  // -0 -> +0
   x[v] = nx;
+  // a value that compares equal keeps its place in the vertex order
+  if (nx != xv) changed[v] = 1;
 }
 
 __global__ void k_minmax(const float* __restrict__ f, int64_t n, float* __restrict__ out) {
@@ -1066,6 +1069,7 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
   std::memset(rep, 0, sizeof(*rep));
   float* x = dev<float>(ctx, "sim.x", n);
   float* f0 = dev<float>(ctx, "sim.f0", n);
+  uint8_t* changed = dev<uint8_t>(ctx, "sim.changed", n);
   if (opt.inputs_on_device) {
     TS_HIP(hipMemcpyAsync(f0, f, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   } else {
@@ -1159,8 +1163,9 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
       k_step_keys<<<nblk(np), 256, 0, s>>>(dvb, dvd, np, keys, vals);
       const int vbits = 33 + 32 - __builtin_clz(uint32_t(std::max(n - 1, 1)));
       radix_sort_u64(ctx->ws, keys, vals, size_t(2 * np), 0, vbits, s);
+      TS_HIP(hipMemsetAsync(changed, 0, size_t(n), s));
       k_step_apply<<<nblk(2 * np), 256, 0, s>>>(keys, 2 * np, dtb, dtd, x, opt.alpha_b,
-                                                opt.alpha_d);
+                                                opt.alpha_d, changed);
       ctx->timer.stop();
       TS_HIP(hipGetLastError());
       TS_HIP(hipStreamSynchronize(s));
@@ -1168,7 +1173,8 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
     rep->update_s += now_s() - tu;
     // ---- persistence ----
     tp = now_s();
-    compute_persistence(ctx, x, G, &R);
+    compute_persistence(ctx, x, G, &R, opt.full_gradient ? nullptr : changed);
+    rep->n_regradient += R.n_regrad;
     std::vector<Pt> Pn;
     fetch_points(ctx, R, x, &Pn);
     rep->persistence_s += now_s() - tp;

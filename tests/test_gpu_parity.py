@@ -243,6 +243,36 @@ def test_cut_and_fill_parity(gpu, orc, alpha_b, alpha_d):
     assert ((D["dim"] == 1) & (pers > 0.1 * ro.range)).sum() >= 1
 
 
+@pytest.mark.parametrize("case", ["gauss32", "ties", "filament64", "gauss128"])
+def test_fast_update_same_as_full(gpu, case):
+    """The fast gradient update between iterations (Sec. 4.2) gives the solver
+    the same maps as recomputing the whole gradient: the same iterations and a
+    bit-identical g, with fewer lower stars processed."""
+    if case == "gauss32":
+        f, kw = fields.gaussian_mixture((32, 32, 32), 8, 0.05, 11), dict(threshold=0.1, j_max=80)
+    elif case == "ties":
+        # values on a coarse grid: many equal neighbours, ordered by index
+        f = np.round(fields.gaussian_mixture((21, 18, 15), 8, 0.05, 12) * 16).astype(np.float32)
+        kw = dict(threshold=0.1, j_max=40)
+    elif case == "filament64":
+        f = fields.workload("filament_256", seed=3, dims=(64, 64, 64))
+        kw = dict(threshold=0.1, nonsignal_dims=(1,), ties_signal=1, j_max=4)
+    else:
+        f = fields.workload("gauss64_128", seed=4)
+        kw = dict(threshold=0.1, j_max=3)
+    n = f.size
+    ga, ra = gpu.simplify(_t(f), full_gradient=True, **kw)
+    gb, rb = gpu.simplify(_t(f), **kw)
+    assert ra.iterations == rb.iterations and ra.iterations > 0
+    assert ra.cancelled == rb.cancelled
+    assert np.array_equal(ga.cpu().numpy(), gb.cpu().numpy())
+    assert ra.loss == rb.loss
+    assert ra.n_regradient == n * ra.iterations
+    assert 0 < rb.n_regradient <= n * rb.iterations
+    if case in ("gauss32", "ties"):  # long runs: late updates touch few vertices
+        assert rb.n_regradient < n * rb.iterations
+
+
 def test_paper_auction_precision(gpu, orc):
     """The paper's setting (auction at relative precision 0.01 with the
     loss-ratio stop L <= 0.01 L0, Sec. 5) is an option: on a 24^3 noisy field
