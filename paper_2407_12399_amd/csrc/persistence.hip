@@ -695,70 +695,110 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
 // relative order, so only vertices with a changed value in their closed star
 // (dirty vertices) need the lower-star loop again.
 
-// dirty[v] = v or a neighbour changed value; dirty vertices are appended to
-// list (in no particular order) and counted in *count.
-__global__ void k_dirty(const uint8_t* __restrict__ changed, Grid g, NbOff off,
-                        uint8_t* __restrict__ dirty, uint32_t* __restrict__ list,
-                        unsigned int* __restrict__ count) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  bool d = false;
-  if (i < g.n) {
-    const int v = int(i);
-    int x, y, z;
-    coords(g, v, &x, &y, &z);
-    const uint32_t valid = valid_nbs(g, x, y, z);
-    uint32_t c = changed[v];
-#pragma unroll
-    for (int k = 0; k < 14; ++k)
-      if ((valid >> k) & 1u) c |= changed[v + off.o[k]];
-    d = c != 0;
-    dirty[v] = d ? 1 : 0;
-  }
-  const uint64_t m = __ballot(d);
-  if (m == 0) return;
+// Stream compaction in a 256-lane block: each lane handles kAppendPer items
+// (round j covers items base + j * 256 + lane).  Lanes record per round their
+// wave's count in s_cnt[j * 4 + wave]; block_reserve turns the counts into
+// offsets and reserves the block's range with one atomic, so items land in
+// (round, wave, lane) order and the counter sees one atomic per block.
+constexpr int kAppendPer = 16;
+
+__device__ __forceinline__ uint64_t lanes_below() {
   const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned int base = 0;
-  if (lane == leader) base = atomicAdd(count, unsigned(__popcll(m)));
-  base = unsigned(__shfl(int(base), leader, 64));
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  if (d) list[base + __popcll(m & lt)] = uint32_t(i);
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ void block_reserve(unsigned int* s_cnt, unsigned long long* counter,
+                              unsigned long long* s_base) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const unsigned int c = s_cnt[lane];
+    unsigned int x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned int y = unsigned(__shfl_up(int(x), d, 64));
+      if (lane >= d) x += y;
+    }
+    s_cnt[lane] = x - c;
+    if (lane == 63) *s_base = x ? atomicAdd(counter, (unsigned long long)x) : 0ull;
+  }
+  __syncthreads();
+}
+
+// dirty[v] = v or a neighbour changed value; dirty vertices are appended to
+// list and counted in *count.
+__global__ void __launch_bounds__(256)
+k_dirty(const uint8_t* __restrict__ changed, Grid g, NbOff off, uint8_t* __restrict__ dirty,
+        uint32_t* __restrict__ list, unsigned long long* __restrict__ count) {
+  __shared__ unsigned int s_cnt[4 * kAppendPer];
+  __shared__ unsigned long long s_base;
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = int64_t(blockIdx.x) * 256 * kAppendPer + threadIdx.x;
+  uint32_t bits = 0;
+#pragma unroll 1
+  for (int j = 0; j < kAppendPer; ++j) {
+    const int64_t i = base + j * 256;
+    bool d = false;
+    if (i < g.n) {
+      const int v = int(i);
+      int x, y, z;
+      coords(g, v, &x, &y, &z);
+      const uint32_t valid = valid_nbs(g, x, y, z);
+      uint32_t c = changed[v];
+#pragma unroll
+      for (int k = 0; k < 14; ++k)
+        if ((valid >> k) & 1u) c |= changed[v + off.o[k]];
+      d = c != 0;
+      dirty[v] = d ? 1 : 0;
+    }
+    bits |= uint32_t(d) << j;
+    const uint64_t m = __ballot(d);
+    if (__lane_id() == 0) s_cnt[j * 4 + wave] = unsigned(__popcll(m));
+  }
+  block_reserve(s_cnt, count, &s_base);
+#pragma unroll 1
+  for (int j = 0; j < kAppendPer; ++j) {
+    const bool d = (bits >> j) & 1u;
+    const uint64_t m = __ballot(d);
+    if (d) list[s_base + s_cnt[j * 4 + wave] + __popcll(m & lanes_below())] = uint32_t(base + j * 256);
+  }
 }
 
 // Critical cells of the previous map whose highest vertex is clean, with the
 // key prefix replaced by that vertex's new rank.  prev_order maps the old
 // rank prefix back to the vertex.  Appends at count (bounded by cap).
-__global__ void k_keep_crit(const uint64_t* __restrict__ pkey, const int32_t* __restrict__ pid,
-                            int64_t np, const int32_t* __restrict__ prev_order,
-                            const int32_t* __restrict__ rank, const uint8_t* __restrict__ dirty,
-                            uint64_t* __restrict__ key, int32_t* __restrict__ id, int64_t cap,
-                            unsigned long long* __restrict__ count) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  bool keep = false;
-  uint64_t k = 0;
-  int32_t c = 0;
-  if (i < np) {
+__global__ void __launch_bounds__(256)
+k_keep_crit(const uint64_t* __restrict__ pkey, const int32_t* __restrict__ pid, int64_t np,
+            const int32_t* __restrict__ prev_order, const int32_t* __restrict__ rank,
+            const uint8_t* __restrict__ dirty, uint64_t* __restrict__ key,
+            int32_t* __restrict__ id, int64_t cap, unsigned long long* __restrict__ count) {
+  __shared__ unsigned int s_cnt[4 * kAppendPer];
+  __shared__ unsigned long long s_base;
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = int64_t(blockIdx.x) * 256 * kAppendPer + threadIdx.x;
+  uint32_t bits = 0;
+#pragma unroll 1
+  for (int j = 0; j < kAppendPer; ++j) {
+    const int64_t i = base + j * 256;
+    bool keep = false;
+    if (i < np) keep = dirty[prev_order[pkey[i] >> 12]] == 0;
+    bits |= uint32_t(keep) << j;
+    const uint64_t m = __ballot(keep);
+    if (__lane_id() == 0) s_cnt[j * 4 + wave] = unsigned(__popcll(m));
+  }
+  block_reserve(s_cnt, count, &s_base);
+#pragma unroll 1
+  for (int j = 0; j < kAppendPer; ++j) {
+    const bool keep = (bits >> j) & 1u;
+    const uint64_t m = __ballot(keep);
+    if (!keep) continue;
+    const int64_t i = base + j * 256;
     const uint64_t pk = pkey[i];
     const int v = prev_order[pk >> 12];
-    keep = dirty[v] == 0;
-    if (keep) {
-      k = (uint64_t(uint32_t(rank[v])) << 12) | (pk & 0xFFFull);
-      c = pid[i];
-    }
-  }
-  const uint64_t m = __ballot(keep);
-  if (m == 0) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
-  base = (unsigned long long)__shfl((long long)base, leader, 64);
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  if (keep) {
-    const unsigned long long p = base + __popcll(m & lt);
+    const unsigned long long p = s_base + s_cnt[j * 4 + wave] + __popcll(m & lanes_below());
     if ((int64_t)p < cap) {
-      key[p] = k;
-      id[p] = c;
+      key[p] = (uint64_t(uint32_t(rank[v])) << 12) | (pk & 0xFFFull);
+      id[p] = pid[i];
     }
   }
 }
@@ -2088,13 +2128,13 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   if (update) {
     dirty = ws.get<uint8_t>("pm.dirty", n);
     dlist = ws.get<uint32_t>("pm.dirty_list", n);
-    unsigned int* dcnt = ws.get<unsigned int>("pm.dirty_count", 1);
-    TS_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned int), s));
+    unsigned long long* dcnt = ws.get<unsigned long long>("pm.dirty_count", 1);
+    TS_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long), s));
     ctx->timer.start("K3 dirty");
-    k_dirty<<<blocks_for(n), 256, 0, s>>>(changed, g, off, dirty, dlist, dcnt);
+    k_dirty<<<blocks_for(n, 256 * kAppendPer), 256, 0, s>>>(changed, g, off, dirty, dlist, dcnt);
     ctx->timer.stop();
     TS_HIP(hipGetLastError());
-    unsigned int h = 0;
+    unsigned long long h = 0;
     TS_HIP(hipMemcpyAsync(&h, dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
     TS_HIP(hipStreamSynchronize(s));
     ndirty = int64_t(h);
@@ -2123,9 +2163,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       ctx->timer.start("K3 keep");
       for (int d = 0; d < 4; ++d)
         if (prev_n[d] > 0)
-          k_keep_crit<<<blocks_for(prev_n[d]), 256, 0, s>>>(prev_key[d], prev_id[d], prev_n[d],
-                                                            prev_order, R->rank, dirty, co.key[d],
-                                                            co.id[d], co.cap[d], ccount + d);
+          k_keep_crit<<<blocks_for(prev_n[d], 256 * kAppendPer), 256, 0, s>>>(
+              prev_key[d], prev_id[d], prev_n[d], prev_order, R->rank, dirty, co.key[d],
+              co.id[d], co.cap[d], ccount + d);
       ctx->timer.stop();
       TS_HIP(hipGetLastError());
       if (ndirty > 0) {
