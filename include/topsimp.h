@@ -150,6 +150,20 @@ const char* ts_last_error(const ts_ctx* ctx);
 int ts_diagram(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_device,
                ts_pair* out, int64_t capacity, int64_t* n_out);
 
+/* Persistence diagrams of a batch of fields of different sizes (Sec. 2.2),
+ * computed together: the fields are copied one after another into one device
+ * buffer and every stage of the persistence map runs once over the whole
+ * batch.  Field i's diagram is exactly ts_diagram of field i alone (same
+ * records, same order, ids local to the field).
+ *   nf:       number of fields (>= 1); the batch holds at most 2^25 vertices
+ *   f:        host array of nf field pointers, each device or host (on_device)
+ *   dims:     host array of 3 * nf sizes (Lx, Ly, Lz of each field, each >= 2)
+ *   out:      host array of `capacity` records: field 0's diagram, then field 1's, ...
+ *   counts:   host array of nf entries, receives |D(f_i)| (also when the total
+ *             exceeds capacity, which returns TS_ERR_CAPACITY) */
+int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64_t* dims,
+                     int32_t on_device, ts_pair* out, int64_t capacity, int64_t* counts);
+
 /* Topological simplification (Alg. 1 with Sec. 4.1 and 4.3).
  *   f:  n floats (input, never modified), device or host (opt->inputs_on_device)
  *   g:  n floats (output), same memory kind as f, must not overlap f

@@ -68,7 +68,8 @@ class _Report(ctypes.Structure):
 _lib = None
 _ctx = {}
 
-EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_simplify",
+EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram_batch",
+           "ts_simplify",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
            "ts_stage_times"]
 
@@ -86,6 +87,7 @@ def lib():
         L.ts_last_error.argtypes = [P]
         L.ts_last_error.restype = ctypes.c_char_p
         L.ts_diagram.argtypes = [P, P, P, i32, P, i64, P]
+        L.ts_diagram_batch.argtypes = [P, i32, P, P, i32, P, i64, P]
         L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
         L.ts_order.argtypes = [P, P, i64, i32, P, P]
         L.ts_gradient.argtypes = [P, P, P, i32, P, P, P]
@@ -178,6 +180,40 @@ def _pairs_call(fn, field):
 def diagram(field) -> np.ndarray:
     """Persistence diagram D(f) in diagram order (structured array)."""
     return _pairs_call(lib().ts_diagram, field)
+
+
+def _batch_args(fields):
+    """(pointer array, dims array, on_device, keepalive) of a list of fields,
+    all device tensors or all host arrays."""
+    if len(fields) == 0:
+        raise ValueError("empty batch")
+    parts = [_as_field(f) for f in fields]
+    on_dev = {p[2] for p in parts}
+    if len(on_dev) != 1:
+        raise ValueError("a batch holds only device fields or only host fields")
+    ptrs = (ctypes.c_void_p * len(parts))(*[p[0] for p in parts])
+    dims = np.concatenate([p[1] for p in parts]).astype(np.int64)
+    return ptrs, dims, on_dev.pop(), parts
+
+
+def diagram_batch(fields) -> list:
+    """Diagrams of a list of fields of any sizes, computed together (every
+    stage runs once over the batch); one structured array per field."""
+    ctx = context()
+    ptrs, dims, on_dev, keep = _batch_args(fields)
+    nf = len(fields)
+    counts = np.zeros(nf, np.int64)
+    cap = max(4096, _cap_hint.get(("batch", int(dims.sum())), int(np.prod(dims.reshape(-1, 3), axis=1).sum()) // 4 + 16))
+    while True:
+        out = np.empty(cap, PAIR_DTYPE)
+        rc = lib().ts_diagram_batch(ctx, nf, ptrs, _ptr(dims), on_dev, _ptr(out), cap, _ptr(counts))
+        if rc == -5:
+            cap = int(counts.sum()) + 1
+            continue
+        _check(ctx, rc)
+        _cap_hint[("batch", int(dims.sum()))] = int(counts.sum()) * 9 // 8 + 16
+        ends = np.cumsum(counts)
+        return [out[e - c: e].copy() for c, e in zip(counts, ends)]
 
 
 def pairs(field) -> np.ndarray:

@@ -140,6 +140,52 @@ void pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev, 
     });
 }
 
+// Layout of a batch of fields stored one after another.
+Batch make_batch(int32_t nf, const int64_t* dims) {
+  if (nf < 1 || !dims) throw Error(TS_ERR_ARG, "a batch needs at least one field");
+  Batch B;
+  B.base.push_back(0);
+  for (int32_t i = 0; i < nf; ++i) {
+    B.grids.push_back(make_grid(dims + 3 * i));
+    B.base.push_back(B.base.back() + B.grids.back().n);
+    if (B.base.back() > (int64_t(1) << 25))
+      throw Error(TS_ERR_ARG, "batch larger than 2^25 vertices");
+  }
+  return B;
+}
+
+// The fields of a batch copied one after another into one device buffer.
+float* batch_field(ts_ctx* ctx, const Batch& B, const float* const* f, int on_device,
+                   const char* name) {
+  if (!f) throw Error(TS_ERR_ARG, "field list is NULL");
+  const int nf = int(B.grids.size());
+  float* d = ctx->ws.get<float>(name, B.base[nf]);
+  for (int i = 0; i < nf; ++i) {
+    if (!f[i]) throw Error(TS_ERR_ARG, "field pointer is NULL");
+    TS_HIP(hipMemcpyAsync(d + B.base[i], f[i], size_t(B.grids[i].n) * sizeof(float),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          ctx->stream));
+  }
+  return d;
+}
+
+// Field of batch vertex v.
+int field_of(const Batch& B, int64_t v) {
+  return int(std::upper_bound(B.base.begin(), B.base.end(), v) - B.base.begin()) - 1;
+}
+
+// Batch records to field-local ids: a cell id of dimension d is a multiple of
+// the vertex id space (1, 7, 12, 6 cells per anchor vertex for d = 0..3).
+ts_pair local_record(const ts_pair& r, int64_t base) {
+  static const int64_t per[4] = {1, 7, 12, 6};
+  ts_pair q = r;
+  q.v_birth -= base;
+  q.v_death -= base;
+  q.birth_cell -= per[r.dim] * base;
+  if (q.death_cell >= 0) q.death_cell -= per[r.dim + 1] * base;
+  return q;
+}
+
 template <class F>
 int guarded(ts_ctx* ctx, F&& fn) {
   if (!ctx) return TS_ERR_ARG;
@@ -314,6 +360,40 @@ int ts_diagram(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_de
     }
     if (!out && !P.empty()) throw Error(TS_ERR_ARG, "out is NULL");
     std::copy(P.begin(), P.end(), out);
+    return int(TS_OK);
+  });
+}
+
+int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64_t* dims,
+                     int32_t on_device, ts_pair* out, int64_t capacity, int64_t* counts) {
+  return guarded(ctx, [&]() {
+    const Batch B = make_batch(nf, dims);
+    if (!counts) throw Error(TS_ERR_ARG, "counts is NULL");
+    ctx->timer.reset();
+    const float* fd = batch_field(ctx, B, f, on_device, "api.batch_field");
+    Grid g{0, 0, 0, int(B.base[nf])};
+    PersistenceResult R;
+    compute_persistence(ctx, fd, g, &R, nullptr, &B);
+    std::vector<ts_pair> P;
+    pairs_to_host(ctx, R, fd, true, &P);
+    finish_timing(ctx);
+    // diagram order restricted to a field is that field's own diagram order
+    std::vector<std::vector<ts_pair>> per(nf);
+    for (const ts_pair& r : P) {
+      const int i = field_of(B, r.v_birth);
+      per[i].push_back(local_record(r, B.base[i]));
+    }
+    int64_t total = 0;
+    for (int i = 0; i < nf; ++i) {
+      counts[i] = int64_t(per[i].size());
+      total += counts[i];
+    }
+    if (total > capacity) {
+      ctx->err = "capacity too small";
+      return int(TS_ERR_CAPACITY);
+    }
+    if (!out && total > 0) throw Error(TS_ERR_ARG, "out is NULL");
+    for (int i = 0; i < nf; ++i) out = std::copy(per[i].begin(), per[i].end(), out);
     return int(TS_OK);
   });
 }

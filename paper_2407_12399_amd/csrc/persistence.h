@@ -2,9 +2,18 @@
 // Freudenthal triangulation (host-side interface of persistence.hip).
 #pragma once
 
+#include <vector>
+
 #include "internal.h"
 
 namespace ts {
+
+// Fields stored one after another in one device buffer: field i has grid
+// grids[i] and holds vertices [base[i], base[i + 1]) (base has nf + 1 entries).
+struct Batch {
+  std::vector<Grid> grids;
+  std::vector<int64_t> base;
+};
 
 // Everything the persistence map leaves on the device.  Pointers live in the
 // context workspace and stay valid until the next call that reuses it.
@@ -38,6 +47,9 @@ struct PersistenceResult {
   int64_t n_regrad = 0;
   // set when the call finished; the fast update needs a complete previous map
   bool complete = false;
+  // field dims (3 per field) of the last call, and the number of fields
+  std::vector<int64_t> layout;
+  int nfields = 1;
 };
 
 // Vertex order only (K1 + K2).
@@ -49,8 +61,11 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
 // recomputed (Sec. 4.2): only vertices with a changed value in their closed
 // star run the lower-star loop; the result is the same as a full map.  Nothing
 // else may use the context's workspace between the two calls.
+// With `batch`, f holds several fields one after another (g.n = their total,
+// g's dims unused) and the result is that of every field's own map, in the
+// batch's vertex and cell id spaces (ids offset by the field's base).
 void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R,
-                         const uint8_t* changed = nullptr);
+                         const uint8_t* changed = nullptr, const Batch* batch = nullptr);
 
 // ts_pair records of the diagram (diagram order) or of all pairs (device).
 void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool diagram_only,

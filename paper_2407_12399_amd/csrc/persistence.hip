@@ -292,6 +292,79 @@ __device__ __forceinline__ int lin(const Grid& g, int dx, int dy, int dz) {
   return dx + g.Lx * (dy + g.Ly * dz);
 }
 
+// ---- field geometry ----
+// Kernels that walk the grid see it through a geometry provider: site(v)
+// gives the grid of the field holding vertex v (local coordinates, validity of
+// the 14 neighbours, linear steps, neighbour offsets).  Vertex and cell ids
+// stay global, so arrays are indexed as for one grid.
+//   GeoOne:   one field; grid and offsets are kernel arguments.
+//   GeoBatch: fields stored one after another, field f at [base, base + n);
+//             a page map gives the field of each 2^kPageBits-vertex page's
+//             first vertex, and a short forward scan finds v's field.
+constexpr int kPageBits = 10;
+
+struct FieldDesc {
+  int base;  // first vertex of the field in the batch
+  int Lx, Ly, Lz;
+  int o[14];  // neighbour offsets
+};
+
+struct SiteOne {
+  const Grid& g;
+  const NbOff& off;
+  __device__ __forceinline__ void xyz(int v, int* x, int* y, int* z) const { coords(g, v, x, y, z); }
+  __device__ __forceinline__ uint32_t valid_at(int x, int y, int z) const {
+    return valid_nbs(g, x, y, z);
+  }
+  __device__ __forceinline__ int step(int dx, int dy, int dz) const { return lin(g, dx, dy, dz); }
+  __device__ __forceinline__ int nb(int k) const { return off.o[k]; }
+};
+
+struct SiteBatch {
+  Grid g;  // the field's grid (n unused)
+  int base;
+  const int* o;
+  __device__ __forceinline__ void xyz(int v, int* x, int* y, int* z) const {
+    coords(g, v - base, x, y, z);
+  }
+  __device__ __forceinline__ uint32_t valid_at(int x, int y, int z) const {
+    return valid_nbs(g, x, y, z);
+  }
+  __device__ __forceinline__ int step(int dx, int dy, int dz) const { return lin(g, dx, dy, dz); }
+  __device__ __forceinline__ int nb(int k) const { return o[k]; }
+};
+
+struct GeoOne {
+  Grid g;
+  NbOff off;
+  __device__ __forceinline__ int total() const { return g.n; }
+  __device__ __forceinline__ SiteOne site(int) const { return SiteOne{g, off}; }
+};
+
+struct GeoBatch {
+  const FieldDesc* fd;
+  const int32_t* page;
+  int nf;
+  int n;  // vertices of the whole batch
+  __device__ __forceinline__ int total() const { return n; }
+  __device__ __forceinline__ int field(int v) const {
+    int f = page[v >> kPageBits];
+    while (f + 1 < nf && v >= fd[f + 1].base) ++f;
+    return f;
+  }
+  __device__ __forceinline__ SiteBatch site(int v) const {
+    const FieldDesc* F = fd + field(v);
+    SiteBatch s;
+    s.g.Lx = F->Lx;
+    s.g.Ly = F->Ly;
+    s.g.Lz = F->Lz;
+    s.g.n = F->Lx * F->Ly * F->Lz;
+    s.base = F->base;
+    s.o = F->o;
+    return s;
+  }
+};
+
 __device__ __forceinline__ uint32_t nib(uint64_t packed, int i) {
   return uint32_t(packed >> (4 * i)) & 15u;
 }
@@ -369,9 +442,9 @@ struct HotTables {
 };
 
 // kList: lane i processes vertex vlist[i] (i < nlist) instead of vertex i.
-template <bool kList>
+template <bool kList, class Geo>
 __global__ void __launch_bounds__(kGradThreads)
-k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restrict__ code_out,
+k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
            int32_t* __restrict__ down_out, CritOut co, const uint32_t* __restrict__ vlist,
            int64_t nlist) {
   __shared__ uint8_t s_slot_cell[kSlotBytes * kGradThreads];
@@ -398,8 +471,9 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
 #define CELL_SLOT(i) cell_slot[(i) * kGradThreads]
 
   const int64_t lane = int64_t(blockIdx.x) * kGradThreads + tid;
-  const bool active = kList ? lane < nlist : lane < g.n;
+  const bool active = kList ? lane < nlist : lane < G.total();
   const int v = kList ? (active ? int(vlist[lane]) : 0) : int(lane);
+  const auto S = G.site(active ? v : 0);
   int rx = 0;
   uint32_t low = 0;
   uint64_t pos = 0;  // nibble k: position of neighbour k among lower neighbours
@@ -410,15 +484,15 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
   uint32_t tcode1 = 0;         // triangles 32..35
   if (active) {
     int x, y, z;
-    coords(g, v, &x, &y, &z);
-    const uint32_t valid = valid_nbs(g, x, y, z);
+    S.xyz(v, &x, &y, &z);
+    const uint32_t valid = S.valid_at(x, y, z);
     rx = rank[v];
     int r[14];
 #pragma unroll
     for (int k = 0; k < 14; ++k) {
       r[k] = INT_MAX;
       if ((valid >> k) & 1u) {
-        r[k] = rank[v + off.o[k]];
+        r[k] = rank[v + S.nb(k)];
         if (r[k] < rx) low |= 1u << k;
       }
     }
@@ -437,7 +511,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
       down_out[v] = v;
     } else {
       const int k0 = int(nib(bypos, 0));
-      down_out[v] = v + off.o[k0];
+      down_out[v] = v + S.nb(k0);
       uint64_t Lt = 0;
       uint32_t Lq = 0;
 #pragma unroll
@@ -643,7 +717,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
       const int k = ffs32(m);
       m &= m - 1;
       if ((int64_t)p < co.cap[1]) {
-        const int anchor = k < 7 ? v : v + off.o[k];
+        const int anchor = k < 7 ? v : v + S.nb(k);
         co.key[1][p] = rk | (uint64_t(nib(pos, k) + 1) << 8);
         co.id[1][p] = 7 * anchor + (k % 7);
       }
@@ -659,7 +733,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
       if ((int64_t)p < co.cap[2]) {
         const uint32_t pa = nib(pos, c_st.tri_nb[t][0]), pb = nib(pos, c_st.tri_nb[t][1]);
         const uint32_t hi = max(pa, pb), lo = min(pa, pb);
-        const int anchor = v + lin(g, c_st.tri_anc[t][0], c_st.tri_anc[t][1], c_st.tri_anc[t][2]);
+        const int anchor = v + S.step(c_st.tri_anc[t][0], c_st.tri_anc[t][1], c_st.tri_anc[t][2]);
         co.key[2][p] = rk | (uint64_t(hi + 1) << 8) | (uint64_t(lo + 1) << 4);
         co.id[2][p] = 12 * anchor + c_st.tri_type[t];
       }
@@ -679,7 +753,7 @@ k_gradient(const int32_t* __restrict__ rank, Grid g, NbOff off, uint4* __restric
         if (a < b) { const uint32_t t = a; a = b; b = t; }
         if (b < c) { const uint32_t t = b; b = c; c = t; }
         if (a < b) { const uint32_t t = a; a = b; b = t; }
-        const int anchor = v + lin(g, c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
+        const int anchor = v + S.step(c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
         co.key[3][p] = rk | (uint64_t(a + 1) << 8) | (uint64_t(b + 1) << 4) | uint64_t(c + 1);
         co.id[3][p] = 6 * anchor + c_st.tet_type[q];
       }
@@ -727,8 +801,9 @@ __device__ void block_reserve(unsigned int* s_cnt, unsigned long long* counter,
 
 // dirty[v] = v or a neighbour changed value; dirty vertices are appended to
 // list and counted in *count.
+template <class Geo>
 __global__ void __launch_bounds__(256)
-k_dirty(const uint8_t* __restrict__ changed, Grid g, NbOff off, uint8_t* __restrict__ dirty,
+k_dirty(const uint8_t* __restrict__ changed, Geo G, uint8_t* __restrict__ dirty,
         uint32_t* __restrict__ list, unsigned long long* __restrict__ count) {
   __shared__ unsigned int s_cnt[4 * kAppendPer];
   __shared__ unsigned long long s_base;
@@ -739,15 +814,16 @@ k_dirty(const uint8_t* __restrict__ changed, Grid g, NbOff off, uint8_t* __restr
   for (int j = 0; j < kAppendPer; ++j) {
     const int64_t i = base + j * 256;
     bool d = false;
-    if (i < g.n) {
+    if (i < G.total()) {
       const int v = int(i);
+      const auto S = G.site(v);
       int x, y, z;
-      coords(g, v, &x, &y, &z);
-      const uint32_t valid = valid_nbs(g, x, y, z);
+      S.xyz(v, &x, &y, &z);
+      const uint32_t valid = S.valid_at(x, y, z);
       uint32_t c = changed[v];
 #pragma unroll
       for (int k = 0; k < 14; ++k)
-        if ((valid >> k) & 1u) c |= changed[v + off.o[k]];
+        if ((valid >> k) & 1u) c |= changed[v + S.nb(k)];
       d = c != 0;
       dirty[v] = d ? 1 : 0;
     }
@@ -856,7 +932,8 @@ __global__ void k_min_index(const int32_t* __restrict__ min_ids, int64_t nmin,
 }
 
 // endpoints of critical edge i -> components (indices of the minima reached)
-__global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Grid g,
+template <class Geo>
+__global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Geo G,
                           const int32_t* __restrict__ down, const int32_t* __restrict__ min_idx,
                           int32_t* __restrict__ ca, int32_t* __restrict__ cb,
                           uint32_t* __restrict__ list, int* __restrict__ err) {
@@ -865,7 +942,7 @@ __global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Grid
   const int id = edge_ids[i];
   const int u = id / 7, t = id - 7 * (id / 7);
   const int m = t + 1;
-  const int w = u + lin(g, m & 1, (m >> 1) & 1, (m >> 2) & 1);
+  const int w = u + G.site(u).step(m & 1, (m >> 1) & 1, (m >> 2) & 1);
   int ends[2] = {u, w};
   int comp[2];
   for (int e = 0; e < 2; ++e) {
@@ -875,7 +952,7 @@ __global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Grid
       const int d = down[a];
       if (d == a) break;
       a = d;
-      if (++steps > g.n) {
+      if (++steps > G.total()) {
         atomicOr(err, 1);
         break;
       }
@@ -1005,11 +1082,12 @@ __global__ void k_uf_init(int32_t* __restrict__ parent, unsigned int* __restrict
 
 // Follows the ascending gradient path from star tet l of vertex y to a
 // maximum; returns the canonical id of the maximum, or -1 for the outside.
-__device__ int ascend(const Grid& g, const NbOff& off, const int32_t* __restrict__ rank,
+template <class Site>
+__device__ int ascend(const Site& S, int total, const int32_t* __restrict__ rank,
                       const uint4* __restrict__ code, int y, int l, int* err) {
   int steps = 0;
   while (true) {
-    if (++steps > 6 * g.n) {
+    if (++steps > 6 * total) {
       atomicOr(err, 2);
       return -1;
     }
@@ -1026,27 +1104,27 @@ __device__ int ascend(const Grid& g, const NbOff& off, const int32_t* __restrict
       }
     }
     if (paired_t < 0) {
-      const int anchor = y + lin(g, c_st.tet_anc[l][0], c_st.tet_anc[l][1], c_st.tet_anc[l][2]);
+      const int anchor = y + S.step(c_st.tet_anc[l][0], c_st.tet_anc[l][1], c_st.tet_anc[l][2]);
       return 6 * anchor + c_st.tet_type[l];
     }
     const int other = c_st.tri_tet[paired_t][1 - side];
     const uint32_t third = uint32_t(c_st.tet_nbm[other]) & ~uint32_t(c_st.tri_nbm[paired_t]);
     const int k = ffs32(third);
     int x, yy, z;
-    coords(g, y, &x, &yy, &z);
-    const uint32_t valid = valid_nbs(g, x, yy, z);
+    S.xyz(y, &x, &yy, &z);
+    const uint32_t valid = S.valid_at(x, yy, z);
     if (!((valid >> k) & 1u)) return -1;  // the facet lies on the box boundary
-    const int cv = y + off.o[k];
+    const int cv = y + S.nb(k);
     if (rank[cv] < rank[y]) {
       l = other;
     } else {
       // the next tet belongs to the lower star of its new apex cv
       const int anchor =
-          y + lin(g, c_st.tet_anc[other][0], c_st.tet_anc[other][1], c_st.tet_anc[other][2]);
+          y + S.step(c_st.tet_anc[other][0], c_st.tet_anc[other][1], c_st.tet_anc[other][2]);
       const int type = c_st.tet_type[other];
       int ax, ay, az, cx, cy, cz;
-      coords(g, anchor, &ax, &ay, &az);
-      coords(g, cv, &cx, &cy, &cz);
+      S.xyz(anchor, &ax, &ay, &az);
+      S.xyz(cv, &cx, &cy, &cz);
       const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
       l = c_st.tet_local[type][__popc(mask)];
       y = cv;
@@ -1054,8 +1132,9 @@ __device__ int ascend(const Grid& g, const NbOff& off, const int32_t* __restrict
   }
 }
 
+template <class Geo>
 __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
-                          int64_t nt, Grid g, NbOff off, const int32_t* __restrict__ rank,
+                          int64_t nt, Geo G, const int32_t* __restrict__ rank,
                           const int32_t* __restrict__ order, const uint4* __restrict__ code,
                           const int32_t* __restrict__ max_pos_of,
                           const int32_t* __restrict__ max_ids, int64_t nmax,
@@ -1065,16 +1144,17 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
   if (i >= nt) return;
   const int id = tri_ids[i];
   const int y = order[tri_keys[i] >> 12];  // highest vertex of the triangle
+  const auto S = G.site(y);
   const int anchor = id / 12, type = id - 12 * (id / 12);
   int ax, ay, az, cx, cy, cz;
-  coords(g, anchor, &ax, &ay, &az);
-  coords(g, y, &cx, &cy, &cz);
+  S.xyz(anchor, &ax, &ay, &az);
+  S.xyz(y, &cx, &cy, &cz);
   const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
   const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
   const int lt = c_st.tri_local[type][p];
   int x, yy, z;
-  coords(g, y, &x, &yy, &z);
-  const uint32_t valid = valid_nbs(g, x, yy, z);
+  S.xyz(y, &x, &yy, &z);
+  const uint32_t valid = S.valid_at(x, yy, z);
   int comp[2];
   for (int s = 0; s < 2; ++s) {
     const int q = c_st.tri_tet[lt][s];
@@ -1085,19 +1165,19 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
     // the tet is in the lower star of y unless its third vertex is higher
     const uint32_t third = uint32_t(c_st.tet_nbm[q]) & ~uint32_t(c_st.tri_nbm[lt]);
     const int k = ffs32(third);
-    const int cv = y + off.o[k];
+    const int cv = y + S.nb(k);
     int yv = y, l = q;
     if (rank[cv] > rank[y]) {
-      const int anc = y + lin(g, c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
+      const int anc = y + S.step(c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
       const int qt = c_st.tet_type[q];
       int bx, by, bz, vx, vy, vz;
-      coords(g, anc, &bx, &by, &bz);
-      coords(g, cv, &vx, &vy, &vz);
+      S.xyz(anc, &bx, &by, &bz);
+      S.xyz(cv, &vx, &vy, &vz);
       const int m2 = (vx - bx) | ((vy - by) << 1) | ((vz - bz) << 2);
       l = c_st.tet_local[qt][__popc(m2)];
       yv = cv;
     }
-    const int mid = ascend(g, off, rank, code, yv, l, err);
+    const int mid = ascend(S, G.total(), rank, code, yv, l, err);
     if (mid < 0) {
       comp[s] = int(nmax);
     } else {
@@ -1199,12 +1279,10 @@ struct ColPool {
   int64_t cap;
 };
 
-struct BoundaryArgs {
+struct BoundaryCommon {
   const uint32_t* cols;
   const int32_t* tri_ids;
   const uint64_t* tri_keys;
-  Grid g;
-  NbOff off;
   const int32_t* rank;
   const int32_t* order;
   const uint4* code;
@@ -1222,6 +1300,11 @@ struct BoundaryArgs {
   int max_steps;
 };
 
+template <class Geo>
+struct BoundaryArgs : BoundaryCommon {
+  Geo G;
+};
+
 // Morse boundary of critical triangle column c (mod 2, restricted to the
 // critical edges that do not die in dimension 0), written descending: the
 // expansion pops the highest edge of the multiset, cancels equal copies in
@@ -1230,16 +1313,17 @@ struct BoundaryArgs {
 // with h the higher vertex and k the star index of o.  A column whose heap or
 // row list overflows, or that needs more than max_steps pops, is appended to
 // the retry list and left unwritten.
-__device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, uint32_t* Rows,
+template <class Geo>
+__device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap& H, uint32_t* Rows,
                                 int64_t rstride, int rcap) {
-  const Grid& g = A.g;
   const uint32_t ti = A.cols[c];
   const int id = A.tri_ids[ti];
   const int y = A.order[A.tri_keys[ti] >> 12];
+  const auto S = A.G.site(y);  // the expansion stays in y's field
   const int anchor = id / 12, type = id - 12 * (id / 12);
   int ax, ay, az, cx, cy, cz;
-  coords(g, anchor, &ax, &ay, &az);
-  coords(g, y, &cx, &cy, &cz);
+  S.xyz(anchor, &ax, &ay, &az);
+  S.xyz(y, &cx, &cy, &cz);
   const int mask = (cx - ax) | ((cy - ay) << 1) | ((cz - az) << 2);
   const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
   const int lt = c_st.tri_local[type][p];
@@ -1248,12 +1332,12 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
   int rl = 0;
   // the three edges of the triangle (y is its highest vertex)
   const uint32_t ry = uint32_t(A.rank[y]);
-  const uint32_t ra = uint32_t(A.rank[y + A.off.o[ka]]), rb = uint32_t(A.rank[y + A.off.o[kb]]);
+  const uint32_t ra = uint32_t(A.rank[y + S.nb(ka)]), rb = uint32_t(A.rank[y + S.nb(kb)]);
   bool ok = H.push((uint64_t(ry) << 32) | ra, (uint32_t(y) << 4) | uint32_t(ka)) &&
             H.push((uint64_t(ry) << 32) | rb, (uint32_t(y) << 4) | uint32_t(kb));
   if (ok) {
     const bool a_hi = ra > rb;
-    const int hv = y + A.off.o[a_hi ? ka : kb];
+    const int hv = y + S.nb(a_hi ? ka : kb);
     const int kk = c_st.nb_diff[a_hi ? ka : kb][a_hi ? kb : ka];
     ok = H.push((uint64_t(a_hi ? ra : rb) << 32) | (a_hi ? rb : ra), (uint32_t(hv) << 4) | uint32_t(kk));
   }
@@ -1287,7 +1371,7 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
     const uint32_t ec = edge_code(code_h, k);
     if (ec == 7u) continue;  // paired with its vertex: the path ends
     if (ec == 6u) {          // critical edge
-      const int lo = h + A.off.o[k];
+      const int lo = h + S.nb(k);
       const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
       const int64_t f = crit_pos(A.edge_pos_of, A.edge_ids, A.nedges, eid);
       if (f < 0) {
@@ -1313,15 +1397,15 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
     const int t = ffs64(m);
     const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
     const uint32_t rh = uint32_t(key >> 32), ro = uint32_t(key);
-    const uint32_t rn = uint32_t(A.rank[h + A.off.o[k2]]);
+    const uint32_t rn = uint32_t(A.rank[h + S.nb(k2)]);
     // edges (h, n2) and (o, n2)
     ok = H.push((uint64_t(rh) << 32) | rn, (uint32_t(h) << 4) | uint32_t(k2));
     if (ok) {
-      const int o = h + A.off.o[k];
+      const int o = h + S.nb(k);
       if (ro > rn) {
         ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(o) << 4) | uint32_t(c_st.nb_diff[k][k2]));
       } else {
-        const int n2 = h + A.off.o[k2];
+        const int n2 = h + S.nb(k2);
         ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(n2) << 4) | uint32_t(c_st.nb_diff[k2][k]));
       }
     }
@@ -1355,7 +1439,8 @@ __device__ void boundary_column(const BoundaryArgs& A, uint32_t c, LaneHeap& H, 
 
 // Many short columns: one lane per column, heap and rows in global scratch
 // (interleaved, sized for exactly nthreads lanes).
-__global__ void k_d1_boundary(BoundaryArgs A, const uint32_t* __restrict__ todo, int64_t ntodo,
+template <class Geo>
+__global__ void k_d1_boundary(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo,
                               uint64_t* __restrict__ hkeys, uint32_t* __restrict__ hrefs,
                               uint32_t* __restrict__ hrows, int hcap, int rcap, int64_t nthreads) {
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1372,8 +1457,9 @@ __global__ void k_d1_boundary(BoundaryArgs A, const uint32_t* __restrict__ todo,
 // Long columns: one column per workgroup of one wave, heap and rows in LDS,
 // expanded by the first lane (the chain of pops is sequential).
 constexpr int kLdsHeap = 2048, kLdsRows = 1024;
+template <class Geo>
 __global__ void __launch_bounds__(64)
-k_d1_boundary_lds(BoundaryArgs A, const uint32_t* __restrict__ todo, int64_t ntodo) {
+k_d1_boundary_lds(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo) {
   __shared__ uint64_t s_key[kLdsHeap];
   __shared__ uint32_t s_ref[kLdsHeap];
   __shared__ uint32_t s_rows[kLdsRows];
@@ -1932,6 +2018,48 @@ __global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
 // K8: diagram
 // ======================================================================
 
+// Lowest and highest rank of every field of a batch (the essential class of
+// a field is born at its lowest vertex and paired with its highest).
+__global__ void k_field_extrema(const int32_t* __restrict__ rank, GeoBatch G,
+                                unsigned int* __restrict__ fmin, unsigned int* __restrict__ fmax) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int f = -1;
+  unsigned int r = 0;
+  if (v < G.n) {
+    f = G.field(int(v));
+    r = unsigned(rank[v]);
+  }
+  const int f0 = __shfl(f, 0, 64);
+  if (__all(f == f0) && f0 >= 0) {  // the whole wave lies in one field
+    unsigned int lo = r, hi = r;
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+      lo = min(lo, unsigned(__shfl_xor(int(lo), sh, 64)));
+      hi = max(hi, unsigned(__shfl_xor(int(hi), sh, 64)));
+    }
+    if (__lane_id() == 0) {
+      atomicMin(&fmin[f0], lo);
+      atomicMax(&fmax[f0], hi);
+    }
+  } else if (f >= 0) {
+    atomicMin(&fmin[f], r);
+    atomicMax(&fmax[f], r);
+  }
+}
+
+// One essential pair per field, appended at `at`.
+__global__ void k_essential(const unsigned int* __restrict__ fmin,
+                            const unsigned int* __restrict__ fmax,
+                            const int32_t* __restrict__ order, int nf, PairOut po, int64_t at) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t p = at + f;
+  po.dim[p] = 0;
+  po.birth[p] = order[fmin[f]];
+  po.death[p] = -1;
+  po.bkey[p] = uint64_t(fmin[f]) << 12;
+  po.dkey[p] = uint64_t(fmax[f]) << 12;
+}
+
 __global__ void k_diag_keys(const int32_t* __restrict__ pdim, const uint64_t* __restrict__ bkey,
                             const uint64_t* __restrict__ dkey, int64_t np, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ idx, unsigned int* __restrict__ nd) {
@@ -2082,7 +2210,7 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
 }
 
 void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, PersistenceResult* R,
-                         const uint8_t* changed) {
+                         const uint8_t* changed, const Batch* batch) {
   upload_tables(ctx->device);
   hipStream_t s = ctx->stream;
   const bool trace = std::getenv("TS_TRACE") != nullptr;
@@ -2090,10 +2218,25 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   const auto t_wall = std::chrono::steady_clock::now();
   Workspace& ws = ctx->ws;
   const int n = g.n;
-  const bool update = changed != nullptr && R->complete && R->g.Lx == g.Lx && R->g.Ly == g.Ly &&
-                      R->g.Lz == g.Lz;
+  const int nf = batch ? int(batch->grids.size()) : 1;
+  std::vector<int64_t> layout;
+  if (batch) {
+    if (nf < 1 || int64_t(batch->base.size()) != nf + 1 || batch->base[nf] != n)
+      throw Error(TS_ERR_ARG, "batch layout does not match the vertex count");
+    for (int i = 0; i < nf; ++i) {
+      const Grid& h = batch->grids[i];
+      if (batch->base[i + 1] - batch->base[i] != int64_t(h.n) || h.n < 1)
+        throw Error(TS_ERR_ARG, "batch field sizes do not match their grids");
+      layout.insert(layout.end(), {h.Lx, h.Ly, h.Lz});
+    }
+  } else {
+    layout = {g.Lx, g.Ly, g.Lz};
+  }
+  const bool update = changed != nullptr && R->complete && R->g.n == g.n && R->layout == layout;
   R->complete = false;
   R->g = g;
+  R->layout = layout;
+  R->nfields = nf;
   R->order = ws.get<int32_t>("pm.order", n);
   R->rank = ws.get<int32_t>("pm.rank", n);
   R->code = ws.get<uint4>("pm.code", n);
@@ -2119,7 +2262,40 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     }
   }
   compute_order(ctx, f, n, R->order, R->rank);
-  const NbOff off = make_offsets(g);
+
+  // geometry: one grid, or a batch resolved through a field table and a page map
+  GeoOne G1{g, batch ? NbOff{} : make_offsets(g)};
+  GeoBatch GB{nullptr, nullptr, nf, n};
+  if (batch) {
+    std::vector<FieldDesc> hfd(nf);
+    for (int i = 0; i < nf; ++i) {
+      const Grid& h = batch->grids[i];
+      const NbOff o = make_offsets(h);
+      hfd[i].base = int(batch->base[i]);
+      hfd[i].Lx = h.Lx;
+      hfd[i].Ly = h.Ly;
+      hfd[i].Lz = h.Lz;
+      for (int k = 0; k < 14; ++k) hfd[i].o[k] = o.o[k];
+    }
+    const int64_t npages = (int64_t(n) + (1 << kPageBits) - 1) >> kPageBits;
+    std::vector<int32_t> hpage(npages);
+    for (int i = 0, p = 0; p < npages; ++p) {
+      const int64_t first = int64_t(p) << kPageBits;
+      while (i + 1 < nf && first >= batch->base[i + 1]) ++i;
+      hpage[p] = i;
+    }
+    FieldDesc* dfd = ws.get<FieldDesc>("pm.fields", nf);
+    int32_t* dpage = ws.get<int32_t>("pm.pages", npages);
+    TS_HIP(hipMemcpyAsync(dfd, hfd.data(), nf * sizeof(FieldDesc), hipMemcpyHostToDevice, s));
+    TS_HIP(hipMemcpyAsync(dpage, hpage.data(), npages * 4, hipMemcpyHostToDevice, s));
+    TS_HIP(hipStreamSynchronize(s));
+    GB.fd = dfd;
+    GB.page = dpage;
+  }
+  auto with_geo = [&](auto&& fn) {
+    if (batch) fn(GB);
+    else fn(G1);
+  };
 
   // dirty vertices of the fast update
   uint8_t* dirty = nullptr;
@@ -2131,7 +2307,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     unsigned long long* dcnt = ws.get<unsigned long long>("pm.dirty_count", 1);
     TS_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long), s));
     ctx->timer.start("K3 dirty");
-    k_dirty<<<blocks_for(n, 256 * kAppendPer), 256, 0, s>>>(changed, g, off, dirty, dlist, dcnt);
+    with_geo([&](auto G) {
+      k_dirty<<<blocks_for(n, 256 * kAppendPer), 256, 0, s>>>(changed, G, dirty, dlist, dcnt);
+    });
     ctx->timer.stop();
     TS_HIP(hipGetLastError());
     unsigned long long h = 0;
@@ -2170,14 +2348,18 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       TS_HIP(hipGetLastError());
       if (ndirty > 0) {
         ctx->timer.start("K3 gradient (dirty)");
-        k_gradient<true><<<blocks_for(ndirty, kGradThreads), kGradThreads, 0, s>>>(
-            R->rank, g, off, R->code, R->down, co, dlist, ndirty);
+        with_geo([&](auto G) {
+          k_gradient<true><<<blocks_for(ndirty, kGradThreads), kGradThreads, 0, s>>>(
+              R->rank, G, R->code, R->down, co, dlist, ndirty);
+        });
         ctx->timer.stop();
       }
     } else {
       ctx->timer.start("K3 gradient");
-      k_gradient<false><<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(
-          R->rank, g, off, R->code, R->down, co, nullptr, 0);
+      with_geo([&](auto G) {
+        k_gradient<false><<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(
+            R->rank, G, R->code, R->down, co, nullptr, 0);
+      });
       ctx->timer.stop();
     }
     TS_HIP(hipGetLastError());
@@ -2202,7 +2384,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     }
     if (attempt == 2) throw Error(TS_ERR_INTERNAL, "critical-cell buffers did not fit");
   }
-  if (R->ncrit[0] - R->ncrit[1] + R->ncrit[2] - R->ncrit[3] != 1)
+  if (R->ncrit[0] - R->ncrit[1] + R->ncrit[2] - R->ncrit[3] != nf)
     throw Error(TS_ERR_INTERNAL, "Euler characteristic of the critical cells is not 1");
   const int64_t nmin = R->ncrit[0], ne = R->ncrit[1], ntri = R->ncrit[2], nmax = R->ncrit[3];
 
@@ -2229,7 +2411,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   ctx->timer.stop();
 
   // pair output
-  const int64_t pcap = nmin + nmax + ne + 16;
+  const int64_t pcap = nmin + nmax + ne + nf + 16;
   PairOut po;
   po.dim = ws.get<int32_t>("pm.pdim", pcap);
   po.birth = ws.get<int32_t>("pm.pbirth", pcap);
@@ -2252,7 +2434,10 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     uint32_t* listA = ws.get<uint32_t>("uf0.listA", ne + 1);
     k_min_index<<<blocks_for(nmin), 256, 0, s>>>(R->cid[0], nmin, min_idx);
     k_fill_u8<<<blocks_for(ne), 256, 0, s>>>(estate, ne, 0);
-    k_d0_init<<<blocks_for(ne), 256, 0, s>>>(R->cid[1], ne, g, R->down, min_idx, ca, cb, listA, err);
+    with_geo([&](auto G) {
+      k_d0_init<<<blocks_for(ne), 256, 0, s>>>(R->cid[1], ne, G, R->down, min_idx, ca, cb, listA,
+                                               err);
+    });
     ctx->timer.stop();
     ctx->timer.start("K5 d0 union-find");
     R->rounds_d0 = union_find_rounds(ctx, ne, nmin, ca, cb, estate, 0, R->cid[1], R->ckey[1],
@@ -2268,9 +2453,11 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     int32_t* cb = ws.get<int32_t>("pm.cb", std::max(ne, ntri));
     uint32_t* listA = ws.get<uint32_t>("uf2.listA", ntri + 1);
     k_fill_u8<<<blocks_for(ntri), 256, 0, s>>>(tstate, ntri, 0);
-    k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, g, off, R->rank,
-                                               R->order, R->code, max_pos_of, R->cid[3], nmax,
-                                               ca, cb, listA, err);
+    with_geo([&](auto G) {
+      k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, G, R->rank,
+                                                 R->order, R->code, max_pos_of, R->cid[3], nmax,
+                                                 ca, cb, listA, err);
+    });
     ctx->timer.stop();
     ctx->timer.start("K6 d2 union-find");
     // node ids/keys of maxima; the outside (index nmax) never dies
@@ -2314,12 +2501,10 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
                          ws.get<uint32_t>("d1.todoB", ncols + 1)};
     unsigned int* nretry = ws.get<unsigned int>("d1.nretry", 1);
     int* bfull = ws.get<int>("d1.bfull", 1);
-    BoundaryArgs BA;
+    BoundaryCommon BA;
     BA.cols = cols;
     BA.tri_ids = R->cid[2];
     BA.tri_keys = R->ckey[2];
-    BA.g = g;
-    BA.off = off;
     BA.rank = R->rank;
     BA.order = R->order;
     BA.code = R->code;
@@ -2354,11 +2539,21 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         uint64_t* hk = ws.get<uint64_t>("d1.hk", nthreads * hcap);
         uint32_t* hr = ws.get<uint32_t>("d1.hr", nthreads * hcap);
         uint32_t* rr = ws.get<uint32_t>("d1.rr", nthreads * rcap);
-        k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(BA, list, ntodo, hk, hr, rr, hcap,
-                                                           rcap, nthreads);
+        with_geo([&](auto G) {
+          BoundaryArgs<decltype(G)> A;
+          static_cast<BoundaryCommon&>(A) = BA;
+          A.G = G;
+          k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(A, list, ntodo, hk, hr, rr, hcap,
+                                                             rcap, nthreads);
+        });
       } else {
         const unsigned nb = unsigned(std::min<int64_t>(ntodo, 8192));
-        k_d1_boundary_lds<<<nb, 64, 0, s>>>(BA, list, ntodo);
+        with_geo([&](auto G) {
+          BoundaryArgs<decltype(G)> A;
+          static_cast<BoundaryCommon&>(A) = BA;
+          A.G = G;
+          k_d1_boundary_lds<<<nb, 64, 0, s>>>(A, list, ntodo);
+        });
       }
       TS_HIP(hipGetLastError());
       if (BA.stats) {
@@ -2526,8 +2721,17 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
 
   // ---- essential class and counts ----
   int64_t np = int64_t(read_scalar(po.count, s));
-  if (np + 1 > pcap) throw Error(TS_ERR_INTERNAL, "pair buffer overflow");
-  {
+  if (np + nf > pcap) throw Error(TS_ERR_INTERNAL, "pair buffer overflow");
+  if (batch) {
+    unsigned int* fmin = ws.get<unsigned int>("pm.fmin", nf);
+    unsigned int* fmax = ws.get<unsigned int>("pm.fmax", nf);
+    k_fill_u32<<<blocks_for(nf), 256, 0, s>>>(fmin, nf, 0xFFFFFFFFu);
+    k_fill_u32<<<blocks_for(nf), 256, 0, s>>>(fmax, nf, 0u);
+    k_field_extrema<<<blocks_for(n), 256, 0, s>>>(R->rank, GB, fmin, fmax);
+    k_essential<<<blocks_for(nf), 256, 0, s>>>(fmin, fmax, R->order, nf, po, np);
+    TS_HIP(hipGetLastError());
+    np += nf;
+  } else {
     const int32_t dim0 = 0, death = -1;
     int32_t gmin;
     TS_HIP(hipMemcpyAsync(&gmin, R->cid[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -2541,7 +2745,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     TS_HIP(hipStreamSynchronize(s));
     ++np;
   }
-  if (np - 1 != nmin - 1 + nmax + (ne - (nmin - 1)))
+  if (np - nf != nmin - nf + nmax + (ne - (nmin - nf)))
     throw Error(TS_ERR_INTERNAL, "pair count does not match the critical cells");
   R->npairs = np;
   R->pdim = po.dim;
