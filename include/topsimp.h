@@ -173,6 +173,26 @@ int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64
 int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
                 const ts_options* opt, float* g, ts_report* rep);
 
+/* Topological simplification of a batch of fields of different sizes
+ * (Alg. 1 per field).  The persistence maps of all fields run together, every
+ * stage one launch over the batch; the update step runs once for all fields
+ * still running.  Each field keeps its own targets (threshold relative to its
+ * own range), still join, assignment and stop rule, and a field stops being
+ * updated once its rule holds: g[i] and reps[i] (iterations, losses, sizes)
+ * are those of ts_simplify on field i alone.  The time fields and
+ * n_regradient of every report are those of the whole batch.
+ *   nf:   number of fields (>= 1); the batch holds at most 2^25 vertices
+ *   f, g: host arrays of nf pointers (device or host per opt->inputs_on_device);
+ *         no g[i] may alias an f[k]
+ *   dims: host array of 3 * nf sizes
+ *   sig:  mode 0 (persistence threshold) only
+ *   reps: host array of nf reports
+ * Returns TS_OK when every field's stop rule held, TS_WARN_NOT_CANCELLED
+ * otherwise, or an error. */
+int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64_t* dims,
+                      const ts_signal* sig, const ts_options* opt, float* const* g,
+                      ts_report* reps);
+
 /* ---- stage entry points (for per-stage checks and profiling) ----------- */
 
 /* Vertex order: order[i] = i-th lowest vertex, rank[order[i]] = i.

@@ -69,7 +69,7 @@ _lib = None
 _ctx = {}
 
 EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram_batch",
-           "ts_simplify",
+           "ts_simplify", "ts_simplify_batch",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
            "ts_stage_times"]
 
@@ -89,6 +89,7 @@ def lib():
         L.ts_diagram.argtypes = [P, P, P, i32, P, i64, P]
         L.ts_diagram_batch.argtypes = [P, i32, P, P, i32, P, i64, P]
         L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
+        L.ts_simplify_batch.argtypes = [P, i32, P, P, P, P, P, P]
         L.ts_order.argtypes = [P, P, i64, i32, P, P]
         L.ts_gradient.argtypes = [P, P, P, i32, P, P, P]
         L.ts_critical.argtypes = [P, P, P, i32, P, P, i64, P]
@@ -203,7 +204,8 @@ def diagram_batch(fields) -> list:
     ptrs, dims, on_dev, keep = _batch_args(fields)
     nf = len(fields)
     counts = np.zeros(nf, np.int64)
-    cap = max(4096, _cap_hint.get(("batch", int(dims.sum())), int(np.prod(dims.reshape(-1, 3), axis=1).sum()) // 4 + 16))
+    nv = int(np.prod(dims.reshape(-1, 3), axis=1).sum())
+    cap = max(4096, _cap_hint.get(("batch", nv), nv // 4 + 16))
     while True:
         out = np.empty(cap, PAIR_DTYPE)
         rc = lib().ts_diagram_batch(ctx, nf, ptrs, _ptr(dims), on_dev, _ptr(out), cap, _ptr(counts))
@@ -211,7 +213,7 @@ def diagram_batch(fields) -> list:
             cap = int(counts.sum()) + 1
             continue
         _check(ctx, rc)
-        _cap_hint[("batch", int(dims.sum()))] = int(counts.sum()) * 9 // 8 + 16
+        _cap_hint[("batch", nv)] = int(counts.sum()) * 9 // 8 + 16
         ends = np.cumsum(counts)
         return [out[e - c: e].copy() for c, e in zip(counts, ends)]
 
@@ -358,8 +360,39 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
     rc = lib().ts_simplify(ctx, fp, _ptr(dims), ctypes.byref(sig), ctypes.byref(opt), gp,
                            ctypes.byref(rep))
     _check(ctx, rc, allow=(0, 1))
-    r = Report(rep.iterations, rep.cancelled, rep.loss0, rep.loss, rep.energy, rep.linf, rep.l2,
-               rep.max_nonsignal_pers, rep.max_signal_disp, rep.range, tuple(rep.n_pairs),
-               rep.n_still, rep.n_reduced, rep.n_targets, rep.total_s, rep.persistence_s,
-               rep.assign_s, rep.update_s, rep.n_regradient, rc)
-    return g, r
+    return g, _report(rep, rc)
+
+
+def _report(rep, rc):
+    return Report(rep.iterations, rep.cancelled, rep.loss0, rep.loss, rep.energy, rep.linf,
+                  rep.l2, rep.max_nonsignal_pers, rep.max_signal_disp, rep.range,
+                  tuple(rep.n_pairs), rep.n_still, rep.n_reduced, rep.n_targets, rep.total_s,
+                  rep.persistence_s, rep.assign_s, rep.update_s, rep.n_regradient, rc)
+
+
+def simplify_batch(fields, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
+                   alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
+                   assign_precision=0.0, full_gradient=False):
+    """simplify() on a list of fields of any sizes, solved together (the
+    persistence maps of all fields run as one batch); returns (list of g,
+    list of Report).  Each field's result is that of simplify() on it alone;
+    report times are those of the whole batch."""
+    ctx = context()
+    ptrs, dims, on_dev, parts = _batch_args(fields)
+    nf = len(fields)
+    sig = _Signal()
+    sig.mode = 0
+    sig.threshold_rel = threshold
+    sig.nonsignal_dim_mask = sum(1 << d for d in nonsignal_dims)
+    sig.ties_signal = ties_signal
+    opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev,
+                   assign_precision, int(bool(full_gradient)))
+    reps = (_Report * nf)()
+    torch = _torch()
+    gs = [torch.empty_like(p[3]) if on_dev else np.empty_like(p[3]) for p in parts]
+    gptrs = (ctypes.c_void_p * nf)(*[ctypes.c_void_p(g.data_ptr()) if on_dev else _ptr(g)
+                                     for g in gs])
+    rc = lib().ts_simplify_batch(ctx, nf, ptrs, _ptr(dims), ctypes.byref(sig), ctypes.byref(opt),
+                                 gptrs, reps)
+    _check(ctx, rc, allow=(0, 1))
+    return gs, [_report(r, 1 - r.cancelled) for r in reps]

@@ -186,6 +186,17 @@ ts_pair local_record(const ts_pair& r, int64_t base) {
   return q;
 }
 
+void check_solver_args(const ts_signal* sig, const ts_options* opt) {
+  if (!sig || !opt) throw Error(TS_ERR_ARG, "null argument");
+  if (!(opt->assign_precision >= 0) || !std::isfinite(opt->assign_precision))
+    throw Error(TS_ERR_ARG, "assign_precision must be finite and >= 0");
+  if (opt->j_max < 0 || opt->stop_mode < 0 || opt->stop_mode > 1)
+    throw Error(TS_ERR_ARG, "bad options");
+  if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
+  if (sig->mode == 1 && sig->n_signal > 0 && !sig->signal)
+    throw Error(TS_ERR_ARG, "signal list is NULL");
+}
+
 template <class F>
 int guarded(ts_ctx* ctx, F&& fn) {
   if (!ctx) return TS_ERR_ARG;
@@ -398,19 +409,33 @@ int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64
   });
 }
 
+int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64_t* dims,
+                      const ts_signal* sig, const ts_options* opt, float* const* g,
+                      ts_report* reps) {
+  return guarded(ctx, [&]() {
+    const Batch B = make_batch(nf, dims);
+    check_solver_args(sig, opt);
+    if (sig->mode != 0) throw Error(TS_ERR_ARG, "a batch takes the threshold signal mode only");
+    if (!f || !g || !reps) throw Error(TS_ERR_ARG, "null argument");
+    for (int i = 0; i < nf; ++i) {
+      if (!f[i] || !g[i]) throw Error(TS_ERR_ARG, "null field pointer");
+      for (int k = 0; k < nf; ++k)
+        if (f[k] == g[i]) throw Error(TS_ERR_ARG, "an output must not alias an input");
+    }
+    ctx->timer.reset();
+    const int rc = simplify_batch(ctx, B, f, *sig, *opt, g, reps);
+    finish_timing(ctx);
+    return rc;
+  });
+}
+
 int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
                 const ts_options* opt, float* g, ts_report* rep) {
   return guarded(ctx, [&]() {
     const Grid grid = make_grid(dims);
-    if (!sig || !opt || !g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
+    check_solver_args(sig, opt);
+    if (!g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
     if (f == g) throw Error(TS_ERR_ARG, "g must not alias f");
-    if (!(opt->assign_precision >= 0) || !std::isfinite(opt->assign_precision))
-      throw Error(TS_ERR_ARG, "assign_precision must be finite and >= 0");
-    if (opt->j_max < 0 || opt->stop_mode < 0 || opt->stop_mode > 1)
-      throw Error(TS_ERR_ARG, "bad options");
-    if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
-    if (sig->mode == 1 && sig->n_signal > 0 && !sig->signal)
-      throw Error(TS_ERR_ARG, "signal list is NULL");
     ctx->timer.reset();
     const int rc = simplify(ctx, f, grid, *sig, *opt, g, rep);
     finish_timing(ctx);

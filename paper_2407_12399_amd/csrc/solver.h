@@ -13,6 +13,14 @@ Grid make_grid(const int64_t dims[3]);
 int simplify(ts_ctx* ctx, const float* f, const Grid& grid, const ts_signal& sig,
              const ts_options& opt, float* g, ts_report* rep);
 
+struct Batch;
+
+// The solver on a batch of fields (f[i], g[i], reps[i] per field): the
+// persistence maps of all fields run together, each field keeps its own
+// solve (the result of each field is that of simplify on it alone).
+int simplify_batch(ts_ctx* ctx, const Batch& B, const float* const* f, const ts_signal& sig,
+                   const ts_options& opt, float* const* g, ts_report* reps);
+
 // Exact W2^2 assignment of one dimension on the augmented diagrams
 // (Eq. 1, q = 2): match[i] = target index or -1 (diagonal).  Pairs with
 // c(p,q) >= diag(p) + diag(q) are excluded.  Returns the optimal cost.

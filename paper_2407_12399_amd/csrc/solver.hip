@@ -11,6 +11,7 @@
 //      assigned exactly, per dimension, to the targets no still point holds
 //      (host, sparse shortest augmenting paths).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1061,45 +1062,93 @@ double assign_reduced(const std::vector<double>& pb, const std::vector<double>& 
 
 // ---------------------------------------------------------------- loop
 
-int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
-             const ts_options& opt, float* g_out, ts_report* rep) {
+namespace {
+
+// One field of a solve and its solver state between iterations.
+struct FieldRun {
+  int64_t base = 0, n = 0;  // vertex range in the (batch) field buffer
+  Solver S;
+  std::vector<Pt> P;  // diagram points, batch vertex and cell ids
+  std::vector<int> phi;
+  double range = 0, tol = 0, L0 = 0, L = 0;
+  bool cancelled = false;
+  int iterations = 0;
+  int64_t n_still = 0, n_red = 0;
+};
+
+// The solve of one field (batch == nullptr) or of a batch of fields stored
+// one after another, whose persistence maps run together (every stage one
+// launch over the batch).  Each field follows its own Alg. 1: its own
+// targets, still join, assignment and stop rule; a field that stops is no
+// longer updated, so its result is that of a solve of the field alone.
+int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
+                    const Batch* batch, const ts_signal& sig, const ts_options& opt,
+                    float* const* g_out, ts_report* reps) {
   const double t0 = now_s();
   hipStream_t s = ctx->stream;
   const int n = G.n;
-  std::memset(rep, 0, sizeof(*rep));
+  std::vector<FieldRun> F(nf);
+  std::vector<int64_t> bases(nf + 1, 0);
+  for (int i = 0; i < nf; ++i) {
+    F[i].base = batch ? batch->base[i] : 0;
+    F[i].n = batch ? batch->grids[i].n : n;
+    bases[i + 1] = F[i].base + F[i].n;
+    std::memset(&reps[i], 0, sizeof(ts_report));
+  }
+  auto field_index = [&](int v) {
+    return nf == 1 ? 0
+                   : int(std::upper_bound(bases.begin(), bases.end(), int64_t(v)) - bases.begin()) - 1;
+  };
   float* x = dev<float>(ctx, "sim.x", n);
   float* f0 = dev<float>(ctx, "sim.f0", n);
   uint8_t* changed = dev<uint8_t>(ctx, "sim.changed", n);
-  if (opt.inputs_on_device) {
-    TS_HIP(hipMemcpyAsync(f0, f, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
-  } else {
-    TS_HIP(hipMemcpyAsync(f0, f, size_t(n) * 4, hipMemcpyHostToDevice, s));
-  }
+  for (int i = 0; i < nf; ++i)
+    TS_HIP(hipMemcpyAsync(f0 + F[i].base, f[i], size_t(F[i].n) * 4,
+                          opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
   TS_HIP(hipMemcpyAsync(x, f0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
 
+  double pers_s = 0, assign_s = 0, update_s = 0;
+  int64_t n_regrad = 0;
   PersistenceResult R;
   double tp = now_s();
-  compute_persistence(ctx, x, G, &R);  // also rejects non-finite values
-  rep->persistence_s += now_s() - tp;
+  compute_persistence(ctx, x, G, &R, nullptr, batch);  // also rejects non-finite values
+  pers_s += now_s() - tp;
 
-  // range of f0
-  double range;
+  // range of every field of f0
   {
     const int nb = 256;
-    float* mm = dev<float>(ctx, "sim.mm", 2 * nb);
-    k_minmax<<<nb, 256, 0, s>>>(f0, n, mm);
-    std::vector<float> h(2 * nb);
+    float* mm = dev<float>(ctx, "sim.mm", size_t(2) * nb * nf);
+    for (int i = 0; i < nf; ++i)
+      k_minmax<<<nb, 256, 0, s>>>(f0 + F[i].base, F[i].n, mm + size_t(2) * nb * i);
+    std::vector<float> h(size_t(2) * nb * nf);
     TS_HIP(hipMemcpyAsync(h.data(), mm, h.size() * 4, hipMemcpyDeviceToHost, s));
     TS_HIP(hipStreamSynchronize(s));
-    double mn = h[0], mx = h[1];
-    for (int b = 0; b < nb; ++b) {
-      mn = std::min(mn, double(h[2 * b]));
-      mx = std::max(mx, double(h[2 * b + 1]));
+    for (int i = 0; i < nf; ++i) {
+      const float* hb = h.data() + size_t(2) * nb * i;
+      double mn = hb[0], mx = hb[1];
+      for (int b = 0; b < nb; ++b) {
+        mn = std::min(mn, double(hb[2 * b]));
+        mx = std::max(mx, double(hb[2 * b + 1]));
+      }
+      F[i].range = mx - mn;
+      F[i].tol = double(opt.cancel_tol_rel) * F[i].range;
     }
-    range = mx - mn;
   }
-  const double tol = double(opt.cancel_tol_rel) * range;
 
+  // points of the batch diagram, split per field (each field's points stay in
+  // its own diagram order); local[k] = index of batch point k in its field
+  auto split = [&](const std::vector<Pt>& all, std::vector<std::vector<Pt>>* per,
+                   std::vector<std::vector<int64_t>>* gidx, std::vector<int32_t>* local) {
+    per->assign(nf, {});
+    gidx->assign(nf, {});
+    local->resize(all.size());
+    for (size_t k = 0; k < all.size(); ++k) {
+      const int i = field_index(all[k].vb);
+      (*local)[k] = int32_t((*per)[i].size());
+      (*per)[i].push_back(all[k]);
+      (*gidx)[i].push_back(int64_t(k));
+    }
+  };
   std::vector<Pt> P;
   fetch_points(ctx, R, x, &P);
   // still join on the device: each diagram's keys sorted once, in diagram
@@ -1117,38 +1166,49 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
     nkeys[sl] = np;
   };
   sort_keys(slot, int64_t(P.size()));
-  Solver S;
-  S.gap = double(opt.assign_precision);
-  std::vector<int> phi;
-  S.targets(P, sig, range, &phi);
-  const double L0 = S.loss(P, phi);
-  double L = L0;
-  auto done = [&](double Lc) {
-    if (opt.stop_mode == 1) return Lc <= double(opt.loss_ratio_s) * L0;
-    return S.max_diag_pers(P, phi) < tol;
+  std::vector<std::vector<Pt>> per;
+  std::vector<std::vector<int64_t>> gidx;
+  std::vector<int32_t> local_prev;
+  split(P, &per, &gidx, &local_prev);
+  auto done = [&](const FieldRun& r, double Lc) {
+    if (opt.stop_mode == 1) return Lc <= double(opt.loss_ratio_s) * r.L0;
+    return r.S.max_diag_pers(r.P, r.phi) < r.tol;
   };
+  int n_active = 0;
+  for (int i = 0; i < nf; ++i) {
+    FieldRun& r = F[i];
+    r.P.swap(per[i]);
+    r.S.gap = double(opt.assign_precision);
+    r.S.targets(r.P, sig, r.range, &r.phi);
+    r.L0 = r.L = r.S.loss(r.P, r.phi);
+    r.n_still = int64_t(r.P.size());
+    r.cancelled = opt.stop_mode == 0 && done(r, r.L);
+    n_active += r.cancelled ? 0 : 1;
+  }
   int j = 0;
-  int64_t n_still = int64_t(P.size()), n_red = 0;
-  bool cancelled = opt.stop_mode == 0 && done(L);
-  while (!cancelled && j < opt.j_max) {
+  while (n_active > 0 && j < opt.j_max) {
     ++j;
-    // ---- gradient step ----
+    // ---- gradient step of the fields still running ----
     const double tu = now_s();
     {
-      const int64_t np = int64_t(P.size());
-      std::vector<int32_t> hvb(np), hvd(np);
-      std::vector<float> htb(np), htd(np);
-      for (int64_t i = 0; i < np; ++i) {
-        hvb[i] = P[i].vb;
-        hvd[i] = P[i].vd;
-        if (phi[i] >= 0) {
-          htb[i] = S.T[phi[i]].b;
-          htd[i] = S.T[phi[i]].d;
-        } else {
-          const float mid = (P[i].b + P[i].d) * 0.5f;
-          htb[i] = htd[i] = mid;
+      std::vector<int32_t> hvb, hvd;
+      std::vector<float> htb, htd;
+      for (const FieldRun& r : F) {
+        if (r.cancelled) continue;
+        for (size_t k = 0; k < r.P.size(); ++k) {
+          hvb.push_back(r.P[k].vb);
+          hvd.push_back(r.P[k].vd);
+          if (r.phi[k] >= 0) {
+            htb.push_back(r.S.T[r.phi[k]].b);
+            htd.push_back(r.S.T[r.phi[k]].d);
+          } else {
+            const float mid = (r.P[k].b + r.P[k].d) * 0.5f;
+            htb.push_back(mid);
+            htd.push_back(mid);
+          }
         }
       }
+      const int64_t np = int64_t(hvb.size());
       int32_t* dvb = dev<int32_t>(ctx, "sim.vb", np);
       int32_t* dvd = dev<int32_t>(ctx, "sim.vd", np);
       float* dtb = dev<float>(ctx, "sim.tb", np);
@@ -1160,25 +1220,27 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
       TS_HIP(hipMemcpyAsync(dtb, htb.data(), np * 4, hipMemcpyHostToDevice, s));
       TS_HIP(hipMemcpyAsync(dtd, htd.data(), np * 4, hipMemcpyHostToDevice, s));
       ctx->timer.start("K10 update");
-      k_step_keys<<<nblk(np), 256, 0, s>>>(dvb, dvd, np, keys, vals);
-      const int vbits = 33 + 32 - __builtin_clz(uint32_t(std::max(n - 1, 1)));
-      radix_sort_u64(ctx->ws, keys, vals, size_t(2 * np), 0, vbits, s);
       TS_HIP(hipMemsetAsync(changed, 0, size_t(n), s));
-      k_step_apply<<<nblk(2 * np), 256, 0, s>>>(keys, 2 * np, dtb, dtd, x, opt.alpha_b,
-                                                opt.alpha_d, changed);
+      if (np > 0) {
+        k_step_keys<<<nblk(np), 256, 0, s>>>(dvb, dvd, np, keys, vals);
+        const int vbits = 33 + 32 - __builtin_clz(uint32_t(std::max(n - 1, 1)));
+        radix_sort_u64(ctx->ws, keys, vals, size_t(2 * np), 0, vbits, s);
+        k_step_apply<<<nblk(2 * np), 256, 0, s>>>(keys, 2 * np, dtb, dtd, x, opt.alpha_b,
+                                                  opt.alpha_d, changed);
+      }
       ctx->timer.stop();
       TS_HIP(hipGetLastError());
       TS_HIP(hipStreamSynchronize(s));
     }
-    rep->update_s += now_s() - tu;
+    update_s += now_s() - tu;
     // ---- persistence ----
     tp = now_s();
-    compute_persistence(ctx, x, G, &R, opt.full_gradient ? nullptr : changed);
-    rep->n_regradient += R.n_regrad;
+    compute_persistence(ctx, x, G, &R, opt.full_gradient ? nullptr : changed, batch);
+    n_regrad += R.n_regrad;
     std::vector<Pt> Pn;
     fetch_points(ctx, R, x, &Pn);
-    rep->persistence_s += now_s() - tp;
-    // ---- assignment ----
+    pers_s += now_s() - tp;
+    // ---- still join (whole batch) and assignment (per field) ----
     const double ta = now_s();
     const int64_t nc = int64_t(Pn.size());
     std::vector<int> prev_of(nc, -1);
@@ -1199,58 +1261,127 @@ int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
       }
       TS_HIP(hipStreamSynchronize(s));
     }
-    std::vector<int> phin;
-    S.assign(Pn, prev_of, phi, &phin, &n_still, &n_red);
-    P.swap(Pn);
-    phi.swap(phin);
-    L = S.loss(P, phi);
-    rep->assign_s += now_s() - ta;
-    cancelled = done(L);
+    std::vector<int32_t> local_n;
+    split(Pn, &per, &gidx, &local_n);
+    // a still partner is a point of the same field (the join key holds the
+    // batch vertex ids): its index in that field's previous points
+    std::vector<int> todo;
+    for (int i = 0; i < nf; ++i)
+      if (!F[i].cancelled) todo.push_back(i);
+    std::vector<std::string> errs(nf);
+    auto run_field = [&](int i) {
+      try {
+        FieldRun& r = F[i];
+        std::vector<int> pof(per[i].size(), -1);
+        for (size_t k = 0; k < per[i].size(); ++k) {
+          const int pg = prev_of[gidx[i][k]];
+          if (pg >= 0) pof[k] = local_prev[pg];
+        }
+        std::vector<int> phin;
+        r.S.assign(per[i], pof, r.phi, &phin, &r.n_still, &r.n_red);
+        r.P.swap(per[i]);
+        r.phi.swap(phin);
+        r.L = r.S.loss(r.P, r.phi);
+        r.iterations = j;
+        r.cancelled = done(r, r.L);
+      } catch (const std::exception& e) {
+        errs[i] = e.what();
+      }
+    };
+    if (todo.size() == 1) {
+      run_field(todo[0]);
+    } else {
+      // fields on a few host threads (each solves its dimensions on threads too)
+      const int nw = int(std::min<size_t>(todo.size(), 8));
+      std::atomic<size_t> next{0};
+      std::vector<std::thread> workers;
+      for (int w = 0; w < nw; ++w)
+        workers.emplace_back([&]() {
+          for (size_t t = next++; t < todo.size(); t = next++) run_field(todo[t]);
+        });
+      for (std::thread& w : workers) w.join();
+    }
+    for (int i = 0; i < nf; ++i)
+      if (!errs[i].empty()) throw Error(TS_ERR_INTERNAL, errs[i]);
+    n_active = 0;
+    for (const FieldRun& r : F) n_active += r.cancelled ? 0 : 1;
+    local_prev.swap(local_n);
+    assign_s += now_s() - ta;
   }
+  for (FieldRun& r : F)
+    if (!r.cancelled) r.iterations = j;
 
-  // ---- outputs and report ----
+  // ---- outputs and reports ----
   std::vector<float> hx(n), hf(n);
   TS_HIP(hipMemcpyAsync(hx.data(), x, size_t(n) * 4, hipMemcpyDeviceToHost, s));
   TS_HIP(hipMemcpyAsync(hf.data(), f0, size_t(n) * 4, hipMemcpyDeviceToHost, s));
   if (opt.inputs_on_device)
-    TS_HIP(hipMemcpyAsync(g_out, x, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    for (int i = 0; i < nf; ++i)
+      TS_HIP(hipMemcpyAsync(g_out[i], x + F[i].base, size_t(F[i].n) * 4,
+                            hipMemcpyDeviceToDevice, s));
   TS_HIP(hipStreamSynchronize(s));
-  if (!opt.inputs_on_device) std::memcpy(g_out, hx.data(), size_t(n) * 4);
-  rep->iterations = j;
-  rep->cancelled = cancelled ? 1 : 0;
-  rep->loss0 = L0;
-  rep->loss = L;
-  {
-    std::vector<char> used(S.T.size(), 0);
-    for (int t : phi)
-      if (t >= 0) used[t] = 1;
-    double un = 0;
-    for (size_t t = 0; t < S.T.size(); ++t)
-      if (!used[t]) un += diag_cost(S.T[t].b, S.T[t].d);
-    rep->energy = L + un;
+  bool all = true;
+  for (int i = 0; i < nf; ++i) {
+    const FieldRun& r = F[i];
+    ts_report* rep = &reps[i];
+    if (!opt.inputs_on_device) std::memcpy(g_out[i], hx.data() + r.base, size_t(r.n) * 4);
+    rep->iterations = r.iterations;
+    rep->cancelled = r.cancelled ? 1 : 0;
+    all = all && r.cancelled;
+    rep->loss0 = r.L0;
+    rep->loss = r.L;
+    {
+      std::vector<char> used(r.S.T.size(), 0);
+      for (int t : r.phi)
+        if (t >= 0) used[t] = 1;
+      double un = 0;
+      for (size_t t = 0; t < r.S.T.size(); ++t)
+        if (!used[t]) un += diag_cost(r.S.T[t].b, r.S.T[t].d);
+      rep->energy = r.L + un;
+    }
+    double linf = 0, l2 = 0;
+    for (int64_t v = r.base; v < r.base + r.n; ++v) {
+      const double d = double(hx[v]) - double(hf[v]);
+      linf = std::max(linf, std::fabs(d));
+      l2 += d * d;
+    }
+    rep->linf = linf;
+    rep->l2 = std::sqrt(l2);
+    rep->max_nonsignal_pers = r.S.max_diag_pers(r.P, r.phi);
+    double disp = 0;
+    for (size_t k = 0; k < r.P.size(); ++k)
+      if (r.phi[k] >= 0)
+        disp = std::max(disp, std::sqrt(pair_cost(r.P[k].b, r.P[k].d, r.S.T[r.phi[k]].b,
+                                                  r.S.T[r.phi[k]].d)));
+    rep->max_signal_disp = disp;
+    rep->range = r.range;
+    for (const Pt& p : r.P)
+      if (!p.ess) rep->n_pairs[p.dim]++;
+    rep->n_still = r.n_still;
+    rep->n_reduced = r.n_red;
+    rep->n_targets = int64_t(r.S.T.size());
+    // times and the gradient work are those of the whole (batch) solve
+    rep->persistence_s = pers_s;
+    rep->assign_s = assign_s;
+    rep->update_s = update_s;
+    rep->n_regradient = n_regrad;
+    rep->total_s = now_s() - t0;
   }
-  double linf = 0, l2 = 0;
-  for (int i = 0; i < n; ++i) {
-    const double d = double(hx[i]) - double(hf[i]);
-    linf = std::max(linf, std::fabs(d));
-    l2 += d * d;
-  }
-  rep->linf = linf;
-  rep->l2 = std::sqrt(l2);
-  rep->max_nonsignal_pers = S.max_diag_pers(P, phi);
-  double disp = 0;
-  for (size_t i = 0; i < P.size(); ++i)
-    if (phi[i] >= 0)
-      disp = std::max(disp, std::sqrt(pair_cost(P[i].b, P[i].d, S.T[phi[i]].b, S.T[phi[i]].d)));
-  rep->max_signal_disp = disp;
-  rep->range = range;
-  for (const Pt& p : P)
-    if (!p.ess) rep->n_pairs[p.dim]++;
-  rep->n_still = n_still;
-  rep->n_reduced = n_red;
-  rep->n_targets = int64_t(S.T.size());
-  rep->total_s = now_s() - t0;
-  return cancelled ? TS_OK : TS_WARN_NOT_CANCELLED;
+  return all ? TS_OK : TS_WARN_NOT_CANCELLED;
+}
+
+}  // namespace
+
+int simplify(ts_ctx* ctx, const float* f, const Grid& G, const ts_signal& sig,
+             const ts_options& opt, float* g_out, ts_report* rep) {
+  return simplify_fields(ctx, 1, &f, G, nullptr, sig, opt, &g_out, rep);
+}
+
+int simplify_batch(ts_ctx* ctx, const Batch& B, const float* const* f, const ts_signal& sig,
+                   const ts_options& opt, float* const* g_out, ts_report* reps) {
+  const int nf = int(B.grids.size());
+  const Grid G{0, 0, 0, int(B.base[nf])};
+  return simplify_fields(ctx, nf, f, G, &B, sig, opt, g_out, reps);
 }
 
 }  // namespace ts

@@ -221,6 +221,37 @@ def test_diagram_batch_uneven_64(gpu):
         _same_pairs(d, gpu.diagram(_t(f)))
 
 
+@pytest.mark.parametrize("kw", [dict(j_max=1000), dict(stop_mode=1, j_max=1000),
+                                dict(j_max=25, nonsignal_dims=(1,), ties_signal=1,
+                                     full_gradient=True)])
+def test_simplify_batch_matches_single(gpu, kw):
+    """Fields solved as a batch: every field's g, iterations, stop and loss
+    are those of solving it alone (fields stop at different iterations)."""
+    fs = _uneven_batch(7, 6, 22, 3) + [_rand((9, 8, 7), 5, "ties")]
+    gs, reps = gpu.simplify_batch([_t(f) for f in fs], threshold=0.1, **kw)
+    its = set()
+    for f, g, r in zip(fs, gs, reps):
+        g1, r1 = gpu.simplify(_t(f), threshold=0.1, **kw)
+        assert (r.iterations, r.cancelled) == (r1.iterations, r1.cancelled)
+        assert np.array_equal(g.cpu().numpy(), g1.cpu().numpy())
+        assert r.loss == r1.loss and r.loss0 == r1.loss0
+        assert r.n_pairs == r1.n_pairs and r.n_targets == r1.n_targets
+        its.add(r.iterations)
+    if kw.get("j_max") == 1000:
+        assert len(its) > 1  # the fields really stop at different iterations
+
+
+def test_simplify_batch_oracle(gpu, orc):
+    """A small batch against the oracle, field by field."""
+    fs = [fields.gaussian_mixture(d, 8, 0.05, 40 + i)
+          for i, d in enumerate([(12, 9, 7), (5, 11, 8), (10, 10, 10)])]
+    gs, reps = gpu.simplify_batch([np.ascontiguousarray(f) for f in fs], threshold=0.1, j_max=200)
+    for f, g, r in zip(fs, gs, reps):
+        go, ro = orc.simplify(f, threshold=0.1, j_max=200)
+        assert r.iterations == ro.iterations and r.cancelled == ro.cancelled
+        assert np.array_equal(g, go)
+
+
 def test_host_pointer_path(gpu, orc):
     f = _rand((9, 8, 7), 11, "normal")
     _same_pairs(gpu.diagram(f), orc.diagram(f))
