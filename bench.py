@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--diag-reps", type=int, default=3)
     ap.add_argument("--diagram-only", action="store_true",
                     help="only run the persistence map --diag-reps times (for profilers)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch of 64 uneven fields")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched persistence map --diag-reps times (for profilers)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -109,6 +113,48 @@ def cpu_baseline(f, crop, signal):
             "persistence_map_mverts_s": c.size / (t1 - t0) / 1e6}
 
 
+def batch_run(ts, fields, torch, args):
+    """64 Gaussian-mixture fields with axes drawn from 24..96: the batched
+    persistence map and solver steps against the same work field by field."""
+    print("[bench] batch of 64 uneven fields", file=sys.stderr, flush=True)
+    fb = [torch.from_numpy(x).cuda() for x in fields.uneven_batch(seed=args.seed)]
+    nv = sum(int(x.numel()) for x in fb)
+
+    def timed(fn, reps):
+        ts_ = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts_.append(time.perf_counter() - t0)
+        return float(np.median(ts_))
+
+    ts.diagram_batch(fb)  # warm-up
+    for x in fb:
+        ts.diagram(x)
+    stage = {}
+    walls = []
+    for _ in range(args.diag_reps):
+        walls.append(timed(lambda: ts.diagram_batch(fb), 1))
+        for k, v in ts.stage_times().items():
+            stage.setdefault(k, []).append(v)
+    dev_ms = sum(float(np.median(v)) for v in stage.values())
+    seq = timed(lambda: [ts.diagram(x) for x in fb], 1)
+    steps = args.steps
+    tb = timed(lambda: ts.simplify_batch(fb, threshold=0.1, j_max=steps), 1)
+    tsq = timed(lambda: [ts.simplify(x, threshold=0.1, j_max=steps) for x in fb], 1)
+    return {"workload": "64 fields, 8 Gaussians + U[-0.05,0.05] noise, axes drawn from 24..96",
+            "vertices": nv,
+            "persistence_map_mverts_s": nv / (dev_ms * 1e-3) / 1e6,
+            "persistence_map_ms": dev_ms,
+            "diagram_batch_wall_s": float(np.median(walls)),
+            "diagram_one_by_one_wall_s": seq,
+            "solver_steps": steps,
+            "simplify_batch_wall_s": tb, "simplify_one_by_one_wall_s": tsq,
+            "solver_mverts_s": nv * steps / tb / 1e6}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -128,6 +174,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}))
+        return
+    if args.batch_only:
+        fb = [torch.from_numpy(x).cuda() for x in fields.uneven_batch(seed=args.seed)]
+        for _ in range(args.diag_reps + 1):
+            ts.diagram_batch(fb)
+        torch.cuda.synchronize()
+        print(json.dumps({"batch_maps": args.diag_reps + 1}))
         return
     w = fields.WORKLOADS[WORKLOAD]
     dims = tuple(args.dims) if args.dims else w["dims"]
@@ -249,6 +302,8 @@ def main():
                              "wall_s": time.perf_counter() - t0,
                              "max_nonsignal_pers_rel": rc.max_nonsignal_pers / rc.range,
                              "linf": rc.linf, "max_signal_disp": rc.max_signal_disp}
+    if not args.no_batch:
+        out["batch"] = batch_run(ts, fields, torch, args)
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_crop, w["signal"])

@@ -2019,19 +2019,35 @@ __global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
 // ======================================================================
 
 // Lowest and highest rank of every field of a batch (the essential class of
-// a field is born at its lowest vertex and paired with its highest).
-__global__ void k_field_extrema(const int32_t* __restrict__ rank, GeoBatch G,
-                                unsigned int* __restrict__ fmin, unsigned int* __restrict__ fmax) {
-  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// a field is born at its lowest vertex and paired with its highest).  A lane
+// scans kAppendPer vertices (stride 256) and flushes its running extremes
+// when the field changes; a wave whose lanes end in one field reduces them
+// and issues one atomic pair.
+__global__ void __launch_bounds__(256)
+k_field_extrema(const int32_t* __restrict__ rank, GeoBatch G, unsigned int* __restrict__ fmin,
+                unsigned int* __restrict__ fmax) {
+  const int64_t base = int64_t(blockIdx.x) * 256 * kAppendPer + threadIdx.x;
   int f = -1;
-  unsigned int r = 0;
-  if (v < G.n) {
-    f = G.field(int(v));
-    r = unsigned(rank[v]);
+  unsigned int lo = 0xFFFFFFFFu, hi = 0;
+  for (int j = 0; j < kAppendPer; ++j) {
+    const int64_t v = base + j * 256;
+    if (v >= G.n) break;
+    const int fv = G.field(int(v));
+    if (fv != f) {
+      if (f >= 0) {
+        atomicMin(&fmin[f], lo);
+        atomicMax(&fmax[f], hi);
+      }
+      f = fv;
+      lo = 0xFFFFFFFFu;
+      hi = 0;
+    }
+    const unsigned int r = unsigned(rank[v]);
+    lo = min(lo, r);
+    hi = max(hi, r);
   }
   const int f0 = __shfl(f, 0, 64);
-  if (__all(f == f0) && f0 >= 0) {  // the whole wave lies in one field
-    unsigned int lo = r, hi = r;
+  if (__all(f == f0) && f0 >= 0) {
     for (int sh = 32; sh >= 1; sh >>= 1) {
       lo = min(lo, unsigned(__shfl_xor(int(lo), sh, 64)));
       hi = max(hi, unsigned(__shfl_xor(int(hi), sh, 64)));
@@ -2041,8 +2057,8 @@ __global__ void k_field_extrema(const int32_t* __restrict__ rank, GeoBatch G,
       atomicMax(&fmax[f0], hi);
     }
   } else if (f >= 0) {
-    atomicMin(&fmin[f], r);
-    atomicMax(&fmax[f], r);
+    atomicMin(&fmin[f], lo);
+    atomicMax(&fmax[f], hi);
   }
 }
 
@@ -2727,7 +2743,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     unsigned int* fmax = ws.get<unsigned int>("pm.fmax", nf);
     k_fill_u32<<<blocks_for(nf), 256, 0, s>>>(fmin, nf, 0xFFFFFFFFu);
     k_fill_u32<<<blocks_for(nf), 256, 0, s>>>(fmax, nf, 0u);
-    k_field_extrema<<<blocks_for(n), 256, 0, s>>>(R->rank, GB, fmin, fmax);
+    k_field_extrema<<<blocks_for(n, 256 * kAppendPer), 256, 0, s>>>(R->rank, GB, fmin, fmax);
     k_essential<<<blocks_for(nf), 256, 0, s>>>(fmin, fmax, R->order, nf, po, np);
     TS_HIP(hipGetLastError());
     np += nf;

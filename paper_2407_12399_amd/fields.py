@@ -128,3 +128,15 @@ def workload(name: str, seed: int = 0, dims=None) -> np.ndarray:
     if w["kind"] == "gauss":
         return gaussian_mixture(d, w["n_gauss"], w["noise"], seed)
     return filament_field(d, seed)
+
+
+def uneven_batch(n_fields: int = 64, lo: int = 24, hi: int = 96, seed: int = 0) -> list:
+    """Batch of Gaussian-mixture fields (8 Gaussians, U[-0.05,0.05] noise) whose
+    three axes are drawn independently and uniformly from lo..hi; field i has
+    generator seed 1000 + i.  Signal rule as gauss8_32 (0.1 range, all dims)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_fields):
+        d = tuple(int(a) for a in rng.integers(lo, hi + 1, 3))
+        out.append(gaussian_mixture(d, 8, 0.05, 1000 + i))
+    return out
