@@ -193,6 +193,36 @@ int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int6
                       const ts_signal* sig, const ts_options* opt, float* const* g,
                       ts_report* reps);
 
+/* ---- the learned warm start ---------------------------------------------
+ * A 3D U-Net (3 levels of 16/32/64 channels, two 3x3x3 convolutions with ReLU
+ * per level, 2x2x2 average pooling, nearest 2x upsampling with skip
+ * concatenation, a 1x1x1 head) maps (field normalised to [0, 1] by its range,
+ * signal-vertex mask) to a proposed change (g0 - f) / range.  It is not part
+ * of the paper's method: a start point g0 for the exact solver, which still
+ * decides every result (ts_options.init).  Convolutions run on BF16 MFMA
+ * tiles with FP32 accumulation; activations are BF16, parameters FP32.
+ * Volumes are channels-last, voxel v = x + Lx * (y + Ly * z); each size a
+ * multiple of 4.  Every pointer below is a device pointer. */
+
+/* Number of FP32 parameters: per convolution [27][Cout][Cin] weights and
+ * Cout biases (layers 8->16 (input channels 2..7 unused), 16->16, 16->32,
+ * 32->32, 32->64, 64->64, 96->32, 32->32, 48->16, 16->16), then the head's 16
+ * weights and bias.  No context, no GPU. */
+int ts_unet_param_count(int64_t* n);
+
+/* out[v] (V floats) = network(input), input [V][2] floats. */
+int ts_unet_forward(ts_ctx* ctx, const float* params, const float* input, const int64_t dims[3],
+                    float* out);
+
+/* Forward pass, mean squared error against target [V] (*loss, host), and the
+ * gradient of that loss with respect to every parameter (grad, overwritten). */
+int ts_unet_backward(ts_ctx* ctx, const float* params, const float* input, const float* target,
+                     const int64_t dims[3], float* grad, double* loss);
+
+/* One Adam step on n parameters (m, v: moment buffers, zero at step 1). */
+int ts_unet_adam(ts_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t n,
+                 int64_t step, float lr, float beta1, float beta2, float eps);
+
 /* ---- stage entry points (for per-stage checks and profiling) ----------- */
 
 /* Vertex order: order[i] = i-th lowest vertex, rank[order[i]] = i.

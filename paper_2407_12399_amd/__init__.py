@@ -69,7 +69,8 @@ _lib = None
 _ctx = {}
 
 EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram_batch",
-           "ts_simplify", "ts_simplify_batch",
+           "ts_simplify", "ts_simplify_batch", "ts_unet_param_count", "ts_unet_forward",
+           "ts_unet_backward", "ts_unet_adam",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
            "ts_stage_times"]
 
@@ -90,6 +91,11 @@ def lib():
         L.ts_diagram_batch.argtypes = [P, i32, P, P, i32, P, i64, P]
         L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
         L.ts_simplify_batch.argtypes = [P, i32, P, P, P, P, P, P]
+        L.ts_unet_param_count.argtypes = [P]
+        L.ts_unet_forward.argtypes = [P, P, P, P, P]
+        L.ts_unet_backward.argtypes = [P, P, P, P, P, P, P]
+        f32 = ctypes.c_float
+        L.ts_unet_adam.argtypes = [P, P, P, P, P, i64, i64, f32, f32, f32, f32]
         L.ts_order.argtypes = [P, P, i64, i32, P, P]
         L.ts_gradient.argtypes = [P, P, P, i32, P, P, P]
         L.ts_critical.argtypes = [P, P, P, i32, P, P, i64, P]
@@ -396,3 +402,53 @@ def simplify_batch(fields, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=
                                  gptrs, reps)
     _check(ctx, rc, allow=(0, 1))
     return gs, [_report(r, 1 - r.cancelled) for r in reps]
+
+
+# ---- the warm-start network (device tensors only) ----
+
+def _dev(t, shape=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def unet_param_count() -> int:
+    n = np.zeros(1, np.int64)
+    _check(None, lib().ts_unet_param_count(_ptr(n)))
+    return int(n[0])
+
+
+def _unet_dims(inp):
+    if inp.dim() != 4 or inp.shape[3] != 2:
+        raise ValueError("input must be (Lz, Ly, Lx, 2)")
+    return np.array([inp.shape[2], inp.shape[1], inp.shape[0]], np.int64)
+
+
+def unet_forward(params, inp):
+    """Network output (Lz, Ly, Lx) for input (Lz, Ly, Lx, 2)."""
+    torch = _torch()
+    dims = _unet_dims(inp)
+    out = torch.empty(inp.shape[:3], dtype=torch.float32, device=inp.device)
+    ctx = context()
+    _check(ctx, lib().ts_unet_forward(ctx, _dev(params), _dev(inp), _ptr(dims), _dev(out)))
+    return out
+
+
+def unet_grad(params, inp, target):
+    """(mean squared error, gradient w.r.t. params) of the network on one volume."""
+    torch = _torch()
+    dims = _unet_dims(inp)
+    grad = torch.empty_like(params)
+    loss = ctypes.c_double(0.0)
+    ctx = context()
+    _check(ctx, lib().ts_unet_backward(ctx, _dev(params), _dev(inp), _dev(target), _ptr(dims),
+                                       _dev(grad), ctypes.byref(loss)))
+    return loss.value, grad
+
+
+def unet_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    ctx = context()
+    _check(ctx, lib().ts_unet_adam(ctx, _dev(params), _dev(grad), _dev(m), _dev(v), params.numel(),
+                                   step, lr, beta1, beta2, eps))

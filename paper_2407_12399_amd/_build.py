@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtopsimp.so")
-SOURCES = ["sort.hip", "persistence.hip", "solver.hip", "api.cpp"]
-HEADERS = ["internal.h", "persistence.h", "solver.h"]
+SOURCES = ["sort.hip", "persistence.hip", "solver.hip", "unet.hip", "api.cpp"]
+HEADERS = ["internal.h", "persistence.h", "solver.h", "unet.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")

@@ -6,6 +6,7 @@
 
 #include "persistence.h"
 #include "solver.h"
+#include "unet.h"
 
 namespace ts {
 
@@ -405,6 +406,58 @@ int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64
     }
     if (!out && total > 0) throw Error(TS_ERR_ARG, "out is NULL");
     for (int i = 0; i < nf; ++i) out = std::copy(per[i].begin(), per[i].end(), out);
+    return int(TS_OK);
+  });
+}
+
+int ts_unet_param_count(int64_t* n) {
+  if (!n) return TS_ERR_ARG;
+  *n = unet_param_count();
+  return TS_OK;
+}
+
+namespace {
+void unet_dims(const int64_t dims[3], int* D, int* H, int* W) {
+  if (!dims) throw Error(TS_ERR_ARG, "dims is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (dims[i] < 4 || dims[i] % 4 != 0 || dims[i] > 4096)
+      throw Error(TS_ERR_ARG, "network sizes must be multiples of 4 in [4, 4096]");
+  if (dims[0] * dims[1] * dims[2] > (int64_t(1) << 25))
+    throw Error(TS_ERR_ARG, "volume larger than 2^25 voxels");
+  *W = int(dims[0]);
+  *H = int(dims[1]);
+  *D = int(dims[2]);
+}
+}  // namespace
+
+int ts_unet_forward(ts_ctx* ctx, const float* params, const float* input, const int64_t dims[3],
+                    float* out) {
+  return guarded(ctx, [&]() {
+    int D, H, W;
+    unet_dims(dims, &D, &H, &W);
+    if (!params || !input || !out) throw Error(TS_ERR_ARG, "null argument");
+    unet_forward(ctx, params, input, D, H, W, out);
+    TS_HIP(hipStreamSynchronize(ctx->stream));
+    return int(TS_OK);
+  });
+}
+
+int ts_unet_backward(ts_ctx* ctx, const float* params, const float* input, const float* target,
+                     const int64_t dims[3], float* grad, double* loss) {
+  return guarded(ctx, [&]() {
+    int D, H, W;
+    unet_dims(dims, &D, &H, &W);
+    if (!params || !input || !target || !grad || !loss) throw Error(TS_ERR_ARG, "null argument");
+    *loss = unet_backward(ctx, params, input, target, D, H, W, grad);
+    return int(TS_OK);
+  });
+}
+
+int ts_unet_adam(ts_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t n,
+                 int64_t step, float lr, float beta1, float beta2, float eps) {
+  return guarded(ctx, [&]() {
+    if (!params || !grad || !m || !v || n < 0 || step < 1) throw Error(TS_ERR_ARG, "bad arguments");
+    unet_adam(ctx, params, grad, m, v, n, step, lr, beta1, beta2, eps);
     return int(TS_OK);
   });
 }

@@ -1,0 +1,83 @@
+"""The warm-start network on the GPU (BF16 MFMA convolutions, FP32
+accumulation) against its CPU reference (FP64 with the same BF16 roundings)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_12399_amd as ts
+    ts.lib()
+    return ts
+
+
+def _params(seed):
+    from oracle import unet_ref
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in unet_ref.LAYERS:
+        parts.append(rng.normal(0, np.sqrt(2.0 / (27 * ci)), 27 * co * ci))
+        parts.append(rng.normal(0, 0.05, co))
+    parts.append(rng.normal(0, 0.25, 16))
+    parts.append(rng.normal(0, 0.05, 1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _case(seed, dims):
+    rng = np.random.default_rng(seed)
+    D, H, W = dims
+    inp = np.stack([rng.random((D, H, W)), (rng.random((D, H, W)) < 0.1)], -1).astype(np.float32)
+    target = rng.normal(0, 0.1, (D, H, W)).astype(np.float32)
+    return inp, target
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("dims", [(8, 12, 16), (4, 4, 4), (12, 8, 20)])
+def test_unet_forward_and_gradient(gpu, dims):
+    import torch
+    from oracle import unet_ref
+    p = _params(7)
+    inp, target = _case(8, dims)
+    pt = torch.from_numpy(p).cuda()
+    it = torch.from_numpy(inp).cuda()
+    tt = torch.from_numpy(target).cuda()
+    out = gpu.unet_forward(pt, it).cpu().numpy()
+    ref = unet_ref.forward(torch.as_tensor(p, dtype=torch.float64),
+                           torch.as_tensor(inp, dtype=torch.float64)).detach().numpy()
+    assert out.shape == ref.shape
+    assert _rel(out, ref) < 1e-2
+    loss, grad = gpu.unet_grad(pt, it, tt)
+    lref, gref = unet_ref.loss_and_grad(p.astype(np.float64), inp, target)
+    assert abs(loss - lref) <= 1e-2 * lref
+    grad = grad.cpu().numpy()
+    o = 0
+    for i, (ci, co) in enumerate(unet_ref.LAYERS):
+        n = 27 * ci * co
+        if i > 0:  # layer 0's padded input channels carry no signal
+            assert _rel(grad[o:o + n], gref[o:o + n]) < 5e-2, ("weights", i)
+        assert _rel(grad[o + n:o + n + co], gref[o + n:o + n + co]) < 5e-2, ("bias", i)
+        o += n + co
+    assert _rel(grad[o:], gref[o:]) < 2e-2
+
+
+def test_unet_adam_step(gpu):
+    import torch
+    rng = np.random.default_rng(3)
+    n = 1000
+    p, g = rng.normal(size=n).astype(np.float32), rng.normal(size=n).astype(np.float32)
+    m, v = rng.normal(size=n).astype(np.float32) * 0.1, rng.random(n).astype(np.float32) * 0.1
+    tp, tg, tm, tv = (torch.from_numpy(a.copy()).cuda() for a in (p, g, m, v))
+    gpu.unet_adam(tp, tg, tm, tv, step=3, lr=1e-2)
+    m2 = 0.9 * m + 0.1 * g
+    v2 = 0.999 * v + 0.001 * g * g
+    want = p - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
+    assert np.allclose(tp.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-6, atol=1e-7)
