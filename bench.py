@@ -87,6 +87,15 @@ def parse():
                     help="skip the batch of 64 uneven fields")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched persistence map --diag-reps times (for profilers)")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also train the warm-start network (512 solver runs at 64^3) and "
+                         "compare warm and cold solves on held-out 128^3 fields (minutes)")
+    ap.add_argument("--warm-start-only", action="store_true",
+                    help="only the warm-start measurement")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only time the warm-start network's forward pass and training step at 64^3")
+    ap.add_argument("--ws-examples", type=int, default=512)
+    ap.add_argument("--ws-steps", type=int, default=3000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -155,6 +164,89 @@ def batch_run(ts, fields, torch, args):
             "solver_mverts_s": nv * steps / tb / 1e6}
 
 
+def unet_run(ts, torch, reps=10):
+    """Forward pass and training step (forward, backward, Adam) of the
+    warm-start network on one 64^3 volume; achieved BF16 MFMA rate of the
+    convolutions (2 * voxels * 27 * Cin * Cout per convolution, Cin as stored;
+    a training step counts the forward, the weight gradient and the data
+    gradient of every layer but the first)."""
+    from paper_2407_12399_amd import warmstart
+    D = 64
+    rng = np.random.default_rng(0)
+    inp = torch.from_numpy(np.stack([rng.random((D, D, D)), rng.random((D, D, D)) < 0.1], -1)
+                           .astype(np.float32)).cuda()
+    tgt = torch.from_numpy(rng.normal(0, 0.01, (D, D, D)).astype(np.float32)).cuda()
+    p = warmstart.init_params(0)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    vox = [D ** 3, D ** 3, (D // 2) ** 3, (D // 2) ** 3, (D // 4) ** 3, (D // 4) ** 3,
+           (D // 2) ** 3, (D // 2) ** 3, D ** 3, D ** 3]
+    fl = [2.0 * n * 27 * ci * co for n, (ci, co) in zip(vox, warmstart.LAYERS)]
+    fwd_flops = sum(fl)
+    step_flops = fwd_flops + sum(fl) + sum(fl[1:])
+    for k in range(3):
+        ts.unet_forward(p, inp)
+        _, g = ts.unet_grad(p, inp, tgt)
+        ts.unet_adam(p, g, m, v, k + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ts.unet_forward(p, inp)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for k in range(reps):
+        _, g = ts.unet_grad(p, inp, tgt)
+        ts.unet_adam(p, g, m, v, k + 4)
+    torch.cuda.synchronize()
+    tt = (time.perf_counter() - t0) / reps
+    return {"volume": [D, D, D], "forward_ms": tf * 1e3, "train_step_ms": tt * 1e3,
+            "forward_conv_gflop": fwd_flops / 1e9, "train_step_conv_gflop": step_flops / 1e9,
+            "forward_tflop_s": fwd_flops / tf / 1e12, "train_step_tflop_s": step_flops / tt / 1e12,
+            "peak_tflop_s": 2500.0, "forward_frac": fwd_flops / tf / 1e12 / 2500.0,
+            "timing": "wall time around whole passes (host round trips included)"}
+
+
+def warm_start_run(ts, torch, args):
+    """Training of the warm-start network on plain-solver results (8 Gaussians
+    + U[-0.05,0.05] noise at 64^3, seeds 0..), then cold and warm solves of
+    held-out 128^3 fields (seeds 20000..) at the same stop rule."""
+    from paper_2407_12399_amd import fields, warmstart
+
+    def log(m):
+        print(f"[bench] warm start: {m}", file=sys.stderr, flush=True)
+
+    kw = dict(stop_mode=1, loss_ratio_s=1e-4, j_max=300)
+    t0 = time.perf_counter()
+    X, Y = warmstart.make_examples(args.ws_examples, dims=(64, 64, 64), seed0=0, log=log, **kw)
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p, hist = warmstart.train(X, Y, args.ws_steps, lr=1e-3, log=log, log_every=500)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    target_ms = float(Y.pow(2).mean())
+    del X, Y
+    evals = []
+    for sd in (20000, 20001, 20002):
+        f = torch.from_numpy(fields.gaussian_mixture((128, 128, 128), 8, 0.05, sd)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc = ts.simplify(f, threshold=0.1, **kw)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, rw, tp = warmstart.warm_solve(p, f, **kw)
+        torch.cuda.synchronize()
+        tw = time.perf_counter() - t0
+        evals.append({"seed": sd, "cold_iterations": rc.iterations, "cold_s": tc,
+                      "warm_iterations": rw.iterations, "warm_s": tw, "proposal_s": tp,
+                      "start_used": rw.init_used, "stopped": [rc.cancelled, rw.cancelled]})
+        log(json.dumps(evals[-1]))
+    return {"examples": args.ws_examples, "example_dims": [64, 64, 64], "train_steps": args.ws_steps,
+            "stop_rule": "loss <= 1e-4 * loss at f0", "data_s": data_s, "train_s": train_s,
+            "train_loss_first": hist[0][1], "train_loss_last": hist[-1][1],
+            "target_mean_square": target_ms, "eval_128": evals}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -174,6 +266,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}))
+        return
+    if args.unet_only:
+        print(json.dumps({"unet": unet_run(ts, torch)}))
+        return
+    if args.warm_start_only:
+        print(json.dumps({"warm_start": warm_start_run(ts, torch, args)}))
         return
     if args.batch_only:
         fb = [torch.from_numpy(x).cuda() for x in fields.uneven_batch(seed=args.seed)]
@@ -304,6 +402,8 @@ def main():
                              "linf": rc.linf, "max_signal_disp": rc.max_signal_disp}
     if not args.no_batch:
         out["batch"] = batch_run(ts, fields, torch, args)
+    if args.warm_start:
+        out["warm_start"] = warm_start_run(ts, torch, args)
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_crop, w["signal"])

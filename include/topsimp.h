@@ -105,6 +105,10 @@ typedef struct {
                               for vertices with a changed value in their closed star
                               (the fast update of Sec. 4.2; same result).  1: the whole
                               gradient is recomputed every iteration. */
+  const float* init;       /* NULL, or a start field g0 (n floats, same memory kind as f):
+                              the solve starts from g0 (e.g. the warm-start network's
+                              proposal) with the targets of D(f0), unless the loss of
+                              g0 exceeds the loss of f0.  Single-field solves only. */
 } ts_options;
 
 typedef struct {
@@ -126,6 +130,7 @@ typedef struct {
   double update_s;          /* time in the gradient step */
   int64_t n_regradient;     /* vertices whose lower star was processed, summed over the
                                maps after the first (n per map with full_gradient) */
+  int32_t init_used;        /* 1 if the solve started from options.init */
 } ts_report;
 
 typedef struct ts_ctx ts_ctx;

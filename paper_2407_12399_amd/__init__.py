@@ -49,7 +49,7 @@ class _Options(ctypes.Structure):
                 ("j_max", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("cancel_tol_rel", ctypes.c_float), ("loss_ratio_s", ctypes.c_float),
                 ("inputs_on_device", ctypes.c_int32), ("assign_precision", ctypes.c_float),
-                ("full_gradient", ctypes.c_int32)]
+                ("full_gradient", ctypes.c_int32), ("init", ctypes.c_void_p)]
 
 
 class _Report(ctypes.Structure):
@@ -62,7 +62,7 @@ class _Report(ctypes.Structure):
                 ("n_reduced", ctypes.c_int64), ("n_targets", ctypes.c_int64),
                 ("total_s", ctypes.c_double), ("persistence_s", ctypes.c_double),
                 ("assign_s", ctypes.c_double), ("update_s", ctypes.c_double),
-                ("n_regradient", ctypes.c_int64)]
+                ("n_regradient", ctypes.c_int64), ("init_used", ctypes.c_int32)]
 
 
 _lib = None
@@ -334,14 +334,16 @@ class Report:
     assign_s: float
     update_s: float
     n_regradient: int
+    init_used: int
     status: int
 
 
 def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
              alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
-             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False):
+             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False, init=None):
     """Topological simplification; returns (g, Report).  g has the kind of
-    the input (torch CUDA tensor in, torch CUDA tensor out)."""
+    the input (torch CUDA tensor in, torch CUDA tensor out).  init: optional
+    start field of the same kind and shape (used unless its loss is higher)."""
     ctx = context()
     fp, dims, on_dev, keep = _as_field(field)
     sig = _Signal()
@@ -355,6 +357,12 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
         sig.ties_signal = ties_signal
     opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev,
                    assign_precision, int(bool(full_gradient)))
+    init_keep = None
+    if init is not None:
+        ip, idims, ion, init_keep = _as_field(init)
+        if ion != on_dev or not np.array_equal(idims, dims):
+            raise ValueError("init must match the field's kind and shape")
+        opt.init = ip
     rep = _Report()
     torch = _torch()
     if on_dev:
@@ -373,7 +381,8 @@ def _report(rep, rc):
     return Report(rep.iterations, rep.cancelled, rep.loss0, rep.loss, rep.energy, rep.linf,
                   rep.l2, rep.max_nonsignal_pers, rep.max_signal_disp, rep.range,
                   tuple(rep.n_pairs), rep.n_still, rep.n_reduced, rep.n_targets, rep.total_s,
-                  rep.persistence_s, rep.assign_s, rep.update_s, rep.n_regradient, rc)
+                  rep.persistence_s, rep.assign_s, rep.update_s, rep.n_regradient,
+                  rep.init_used, rc)
 
 
 def simplify_batch(fields, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,

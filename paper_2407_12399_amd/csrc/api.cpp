@@ -469,6 +469,7 @@ int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int6
     const Batch B = make_batch(nf, dims);
     check_solver_args(sig, opt);
     if (sig->mode != 0) throw Error(TS_ERR_ARG, "a batch takes the threshold signal mode only");
+    if (opt->init) throw Error(TS_ERR_ARG, "a batch takes no start field");
     if (!f || !g || !reps) throw Error(TS_ERR_ARG, "null argument");
     for (int i = 0; i < nf; ++i) {
       if (!f[i] || !g[i]) throw Error(TS_ERR_ARG, "null field pointer");
@@ -489,6 +490,7 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
     check_solver_args(sig, opt);
     if (!g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
     if (f == g) throw Error(TS_ERR_ARG, "g must not alias f");
+    if (opt->init == g) throw Error(TS_ERR_ARG, "g must not alias the start field");
     ctx->timer.reset();
     const int rc = simplify(ctx, f, grid, *sig, *opt, g, rep);
     finish_timing(ctx);

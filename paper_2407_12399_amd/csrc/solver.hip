@@ -1151,8 +1151,6 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
   };
   std::vector<Pt> P;
   fetch_points(ctx, R, x, &P);
-  // still join on the device: each diagram's keys sorted once, in diagram
-  // order within equal keys (slots alternate between iterations)
   int slot = 0;
   int64_t nkeys[2] = {0, 0};
   auto sort_keys = [&](int sl, int64_t np) {
@@ -1165,7 +1163,6 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     }
     nkeys[sl] = np;
   };
-  sort_keys(slot, int64_t(P.size()));
   std::vector<std::vector<Pt>> per;
   std::vector<std::vector<int64_t>> gidx;
   std::vector<int32_t> local_prev;
@@ -1174,7 +1171,6 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     if (opt.stop_mode == 1) return Lc <= double(opt.loss_ratio_s) * r.L0;
     return r.S.max_diag_pers(r.P, r.phi) < r.tol;
   };
-  int n_active = 0;
   for (int i = 0; i < nf; ++i) {
     FieldRun& r = F[i];
     r.P.swap(per[i]);
@@ -1182,6 +1178,48 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     r.S.targets(r.P, sig, r.range, &r.phi);
     r.L0 = r.L = r.S.loss(r.P, r.phi);
     r.n_still = int64_t(r.P.size());
+  }
+  // a given start field (one field): its diagram is assigned to the targets
+  // of D(f0); it replaces f0 only if its loss is no higher
+  int init_used = 0;
+  if (opt.init && nf == 1) {
+    FieldRun& r = F[0];
+    TS_HIP(hipMemcpyAsync(x, opt.init, size_t(n) * 4,
+                          opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    tp = now_s();
+    compute_persistence(ctx, x, G, &R);
+    std::vector<Pt> Pw;
+    fetch_points(ctx, R, x, &Pw);
+    pers_s += now_s() - tp;
+    const double ta = now_s();
+    std::vector<int> none(Pw.size(), -1), phiw;
+    int64_t ns = 0, nr = 0;
+    r.S.assign(Pw, none, r.phi, &phiw, &ns, &nr);
+    const double Lw = r.S.loss(Pw, phiw);
+    assign_s += now_s() - ta;
+    if (Lw <= r.L0) {
+      init_used = 1;
+      r.P = Pw;
+      r.phi.swap(phiw);
+      r.L = Lw;
+      r.n_still = ns;
+      r.n_red = nr;
+      P.swap(Pw);
+    } else {  // back to f0 (the map must describe the current field)
+      TS_HIP(hipMemcpyAsync(x, f0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+      tp = now_s();
+      compute_persistence(ctx, x, G, &R);
+      fetch_points(ctx, R, x, &P);
+      pers_s += now_s() - tp;
+    }
+    split(P, &per, &gidx, &local_prev);
+  }
+  // still join on the device: each diagram's keys sorted once, in diagram
+  // order within equal keys (slots alternate between iterations); the device
+  // points of the current diagram are those of the last fetch
+  sort_keys(slot, int64_t(P.size()));
+  int n_active = 0;
+  for (FieldRun& r : F) {
     r.cancelled = opt.stop_mode == 0 && done(r, r.L);
     n_active += r.cancelled ? 0 : 1;
   }
@@ -1365,6 +1403,7 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     rep->assign_s = assign_s;
     rep->update_s = update_s;
     rep->n_regradient = n_regrad;
+    rep->init_used = init_used;
     rep->total_s = now_s() - t0;
   }
   return all ? TS_OK : TS_WARN_NOT_CANCELLED;

@@ -81,3 +81,38 @@ def test_unet_adam_step(gpu):
     want = p - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
     assert np.allclose(tp.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
     assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-6, atol=1e-7)
+
+
+def test_simplify_start_field(gpu):
+    """A start field with a higher loss is rejected and the solve is the cold
+    one, bit for bit; the solver's own result as the start field is used and
+    stops at once; either way the exact solver judges the result."""
+    import torch
+    from paper_2407_12399_amd import fields
+    f = torch.from_numpy(fields.gaussian_mixture((20, 16, 12), 8, 0.05, 5)).cuda()
+    kw = dict(threshold=0.1, stop_mode=1, loss_ratio_s=1e-3, j_max=300)
+    gc, rc = gpu.simplify(f, **kw)
+    noisy = (f + torch.randn(f.shape, generator=torch.Generator().manual_seed(0)).cuda()).contiguous()
+    gn, rn = gpu.simplify(f, init=noisy, **kw)
+    assert rn.init_used == 0 and rc.init_used == 0
+    assert rn.iterations == rc.iterations and torch.equal(gn, gc)
+    gi, ri = gpu.simplify(f, init=gc.contiguous(), **kw)
+    assert ri.init_used == 1 and ri.cancelled == 1
+    assert ri.iterations <= 2 < rc.iterations
+    assert ri.loss0 == rc.loss0  # the loss stays relative to the targets of D(f)
+
+
+def test_warm_start_pipeline(gpu):
+    """Examples from the batched solver, a few Adam steps with the library's
+    kernels (the training loss falls), and a warm-started solve that meets
+    the stop rule."""
+    import torch
+    from paper_2407_12399_amd import fields, warmstart
+    X, Y = warmstart.make_examples(8, dims=(16, 16, 16), seed0=100, stop_mode=1,
+                                   loss_ratio_s=1e-3, j_max=200)
+    assert X.shape == (8, 16, 16, 16, 2) and Y.shape == (8, 16, 16, 16)
+    p, hist = warmstart.train(X, Y, 80, lr=2e-3, log_every=40)
+    assert hist[-1][1] < hist[0][1]
+    f = torch.from_numpy(fields.gaussian_mixture((16, 16, 16), 8, 0.05, 999)).cuda()
+    g, r, _ = warmstart.warm_solve(p, f, stop_mode=1, loss_ratio_s=1e-3, j_max=300)
+    assert r.cancelled == 1 and r.init_used in (0, 1)
