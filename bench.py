@@ -53,6 +53,13 @@ K3_COUNTERS = {"source_sha1": "afc3e3ecb49f529a20a395d021d34ef0205180fa",
                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
+# SQ_INSTS_VALU / SQ_WAVES of K3 from the instruction-mix pass recorded in
+# profiles/k3_gradient_filament256_instruction_mix.md (same kernel source)
+K3_VALU_PER_WAVE = {"source_sha1": "afc3e3ecb49f529a20a395d021d34ef0205180fa", "valu": 19136.9}
+# one wave64 VALU instruction per CU per cycle (4 SIMDs x 16 lanes), 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK_G = 256 * 2.4
+
+
 def kernel_source_sha1(name="k_gradient"):
     """sha1 of a kernel's definition text in persistence.hip."""
     import hashlib
@@ -339,6 +346,12 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": stage_ms[dom]}
 
+    k3_issue = None
+    if dom == "K3 gradient" and kernel_source_sha1() == K3_VALU_PER_WAVE["source_sha1"]:
+        rate = n / 64 * K3_VALU_PER_WAVE["valu"] / (stage_ms[dom] * 1e-3) / 1e9
+        k3_issue = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_ISSUE_PEAK_G,
+                    "unit": "G wave-level VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK_G,
+                    "valu_per_wave": K3_VALU_PER_WAVE["valu"]}
     out = {
         "metric": "time to full non-signal cancellation (s) + persistence-map Mverts/s at 256^3",
         "value": value, "unit": "Mverts/s", "n_gpus": 1, "steps": steps,
@@ -361,6 +374,7 @@ def main():
                    "n_still_last": rep.n_still, "n_targets": rep.n_targets,
                    "stage_ms_total": solver_stage},
         "roofline": roofline,
+        "k3_issue": k3_issue,
     }
     # the paper's assignment setting (auction at relative precision 0.01)
     if not args.no_paper_auction:

@@ -375,6 +375,32 @@ def test_errors(gpu):
     del torch
 
 
+def test_batch_edges(gpu, orc):
+    """A batch of one field is the field's own diagram; host arrays give the
+    same solves as device tensors; a batch rejects a non-finite field, a
+    grid below 2 and mixed memory kinds, and the context keeps working."""
+    f = fields.gaussian_mixture((13, 11, 9), 8, 0.05, 21)
+    (d,) = gpu.diagram_batch([_t(f)])
+    _same_pairs(d, orc.diagram(f))
+    fs = _uneven_batch(3, 5, 12, 9)
+    gh, rh = gpu.simplify_batch([np.ascontiguousarray(x) for x in fs], threshold=0.1, j_max=50)
+    gd, rd = gpu.simplify_batch([_t(x) for x in fs], threshold=0.1, j_max=50)
+    for a, b, ra, rb in zip(gh, gd, rh, rd):
+        assert np.array_equal(a, b.cpu().numpy()) and ra.iterations == rb.iterations
+    bad = f.copy()
+    bad[2, 3, 4] = np.nan
+    with pytest.raises(gpu.TopsimpError) as e:
+        gpu.diagram_batch([_t(f), _t(bad)])
+    assert e.value.code == -2
+    with pytest.raises(gpu.TopsimpError) as e:
+        gpu.diagram_batch([_t(f), _t(np.zeros((1, 4, 4), np.float32))])
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        gpu.diagram_batch([_t(f), np.ascontiguousarray(f)])
+    (d,) = gpu.diagram_batch([_t(f)])
+    _same_pairs(d, orc.diagram(f))
+
+
 def test_deterministic(gpu):
     f = fields.gaussian_mixture((40, 36, 33), 64, 0.1, 5)
     a = gpu.pairs(_t(f))
