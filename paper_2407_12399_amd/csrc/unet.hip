@@ -118,22 +118,54 @@ k_conv_wgrad(const uint16_t* __restrict__ dY, const uint16_t* __restrict__ X, in
   const int co = to * 32 + m, ci = ti * 32 + m;
   const int64_t v0 = chunk * kWgradChunk, v1 = v0 + kWgradChunk < V ? v0 + kWgradChunk : V;
   f32x16 acc = {};
-  for (int64_t k0 = v0; k0 < v1; k0 += 8) {
-    bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+  if (W & 3) {  // rows not a multiple of 4 voxels: coordinates per voxel
+    for (int64_t k0 = v0; k0 < v1; k0 += 8) {
+      bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t v = k0 + 4 * half + i;
-      if (v >= v1) continue;
-      if (co < Cout) a[i] = short(dY[v * Cout + co]);
-      const int x = int(v % W), y = int((v / W) % H), z = int(v / (int64_t(W) * H));
-      const bool inside = x + dx >= 0 && x + dx < W && y + dy >= 0 && y + dy < H &&
-                          z + dz >= 0 && z + dz < D;
-      if (inside && ci < Cin) {
-        const int64_t nb = v + dx + int64_t(W) * (dy + int64_t(H) * dz);
-        b[i] = short(X[nb * Cin + ci]);
+      for (int i = 0; i < 4; ++i) {
+        const int64_t v = k0 + 4 * half + i;
+        if (v >= v1) continue;
+        if (co < Cout) a[i] = short(dY[v * Cout + co]);
+        const int x = int(v % W), y = int((v / W) % H), z = int(v / (int64_t(W) * H));
+        const bool inside = x + dx >= 0 && x + dx < W && y + dy >= 0 && y + dy < H &&
+                            z + dz >= 0 && z + dz < D;
+        if (inside && ci < Cin) {
+          const int64_t nb = v + dx + int64_t(W) * (dy + int64_t(H) * dz);
+          b[i] = short(X[nb * Cin + ci]);
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+  } else {
+    // The lane's four voxels vb .. vb + 3 (vb = k0 + 4 * half, a multiple of 4)
+    // share a row because W is a multiple of 4; their coordinates advance by 8
+    // voxels per step without divisions.
+    const int64_t s0 = v0 + 4 * half;
+    int xb = int(s0 % W), yb = int((s0 / W) % H), zb = int(s0 / (int64_t(W) * H));
+    const int64_t shift = dx + int64_t(W) * (dy + int64_t(H) * dz);
+    for (int64_t k0 = v0; k0 < v1; k0 += 8) {
+      bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+      const int64_t vb = k0 + 4 * half;
+      if (vb < v1) {
+        const bool row_ok = yb + dy >= 0 && yb + dy < H && zb + dz >= 0 && zb + dz < D;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t v = vb + i;
+          if (co < Cout) a[i] = short(dY[v * Cout + co]);
+          if (row_ok && ci < Cin && xb + i + dx >= 0 && xb + i + dx < W)
+            b[i] = short(X[(v + shift) * Cin + ci]);
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+      xb += 8;
+      while (xb >= W) {
+        xb -= W;
+        if (++yb == H) {
+          yb = 0;
+          ++zb;
+        }
       }
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
   }
   if (ci >= Cin) return;
 #pragma unroll
