@@ -1179,8 +1179,29 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     r.L0 = r.L = r.S.loss(r.P, r.phi);
     r.n_still = int64_t(r.P.size());
   }
-  // a given start field (one field): its diagram is assigned to the targets
-  // of D(f0); it replaces f0 only if its loss is no higher
+  // still join on the device: each diagram's keys sorted once, in diagram
+  // order within equal keys (slots alternate between iterations)
+  sort_keys(slot, int64_t(P.size()));
+  auto join = [&](int64_t nc, std::vector<int>* prev_of) {
+    prev_of->assign(nc, -1);
+    const int prev = slot;
+    slot ^= 1;
+    sort_keys(slot, nc);
+    const std::string c = std::to_string(slot), q = std::to_string(prev);
+    int32_t* po = dev<int32_t>(ctx, "sim.prev_of", nc + 1);
+    if (nc > 0) {
+      k_join<<<nblk(nc), 256, 0, s>>>(dev<uint64_t>(ctx, ("sim.jk" + c).c_str(), nc + 1),
+                                      dev<uint32_t>(ctx, ("sim.ji" + c).c_str(), nc + 1), nc,
+                                      dev<uint64_t>(ctx, ("sim.jk" + q).c_str(), nkeys[prev] + 1),
+                                      dev<uint32_t>(ctx, ("sim.ji" + q).c_str(), nkeys[prev] + 1),
+                                      nkeys[prev], po);
+      TS_HIP(hipGetLastError());
+      TS_HIP(hipMemcpyAsync(prev_of->data(), po, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    TS_HIP(hipStreamSynchronize(s));
+  };
+  // a given start field (one field): its diagram is joined with D(f0) and
+  // assigned like an iteration's; it replaces f0 only if its loss is no higher
   int init_used = 0;
   if (opt.init && nf == 1) {
     FieldRun& r = F[0];
@@ -1192,9 +1213,10 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     fetch_points(ctx, R, x, &Pw);
     pers_s += now_s() - tp;
     const double ta = now_s();
-    std::vector<int> none(Pw.size(), -1), phiw;
+    std::vector<int> pof, phiw;
+    join(int64_t(Pw.size()), &pof);
     int64_t ns = 0, nr = 0;
-    r.S.assign(Pw, none, r.phi, &phiw, &ns, &nr);
+    r.S.assign(Pw, pof, r.phi, &phiw, &ns, &nr);
     const double Lw = r.S.loss(Pw, phiw);
     assign_s += now_s() - ta;
     if (Lw <= r.L0) {
@@ -1205,19 +1227,17 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
       r.n_still = ns;
       r.n_red = nr;
       P.swap(Pw);
-    } else {  // back to f0 (the map must describe the current field)
+    } else {  // back to f0 (the map and the join keys must describe the current field)
       TS_HIP(hipMemcpyAsync(x, f0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
       tp = now_s();
       compute_persistence(ctx, x, G, &R);
       fetch_points(ctx, R, x, &P);
       pers_s += now_s() - tp;
+      slot ^= 1;
+      sort_keys(slot, int64_t(P.size()));
     }
     split(P, &per, &gidx, &local_prev);
   }
-  // still join on the device: each diagram's keys sorted once, in diagram
-  // order within equal keys (slots alternate between iterations); the device
-  // points of the current diagram are those of the last fetch
-  sort_keys(slot, int64_t(P.size()));
   int n_active = 0;
   for (FieldRun& r : F) {
     r.cancelled = opt.stop_mode == 0 && done(r, r.L);
@@ -1280,25 +1300,8 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     pers_s += now_s() - tp;
     // ---- still join (whole batch) and assignment (per field) ----
     const double ta = now_s();
-    const int64_t nc = int64_t(Pn.size());
-    std::vector<int> prev_of(nc, -1);
-    {
-      const int prev = slot;
-      slot ^= 1;
-      sort_keys(slot, nc);
-      const std::string c = std::to_string(slot), q = std::to_string(prev);
-      int32_t* po = dev<int32_t>(ctx, "sim.prev_of", nc + 1);
-      if (nc > 0) {
-        k_join<<<nblk(nc), 256, 0, s>>>(dev<uint64_t>(ctx, ("sim.jk" + c).c_str(), nc + 1),
-                                        dev<uint32_t>(ctx, ("sim.ji" + c).c_str(), nc + 1), nc,
-                                        dev<uint64_t>(ctx, ("sim.jk" + q).c_str(), nkeys[prev] + 1),
-                                        dev<uint32_t>(ctx, ("sim.ji" + q).c_str(), nkeys[prev] + 1),
-                                        nkeys[prev], po);
-        TS_HIP(hipGetLastError());
-        TS_HIP(hipMemcpyAsync(prev_of.data(), po, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      }
-      TS_HIP(hipStreamSynchronize(s));
-    }
+    std::vector<int> prev_of;
+    join(int64_t(Pn.size()), &prev_of);
     std::vector<int32_t> local_n;
     split(Pn, &per, &gidx, &local_n);
     // a still partner is a point of the same field (the join key holds the
