@@ -74,7 +74,7 @@ def kernel_source_sha1(name="k_gradient"):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dims", type=int, nargs=3, default=None)
