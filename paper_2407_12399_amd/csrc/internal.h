@@ -44,6 +44,37 @@ struct Workspace {
   size_t total_bytes() const;
 };
 
+// Launch-parameter autotuning.  For each key (a stage and a size class) the
+// first calls try the candidates in turn and report their time; later calls
+// get the fastest.  Only parameters that leave results unchanged are tuned.
+struct Tuner {
+  struct Entry {
+    std::vector<double> seconds;  // per candidate, < 0 until tried
+    int best = -1;
+  };
+  std::map<std::string, Entry> entries;
+  // Index of the candidate to use now (ncand > 0).
+  int pick(const std::string& key, int ncand) {
+    Entry& e = entries[key];
+    if (e.seconds.empty()) e.seconds.assign(ncand, -1.0);
+    if (e.best >= 0) return e.best;
+    for (int i = 0; i < ncand; ++i)
+      if (e.seconds[i] < 0) return i;
+    return 0;
+  }
+  void report(const std::string& key, int idx, double secs) {
+    Entry& e = entries[key];
+    if (e.best >= 0 || idx < 0 || idx >= int(e.seconds.size())) return;
+    e.seconds[idx] = secs;
+    int b = -1;
+    for (int i = 0; i < int(e.seconds.size()); ++i) {
+      if (e.seconds[i] < 0) return;  // not all tried yet
+      if (b < 0 || e.seconds[i] < e.seconds[b]) b = i;
+    }
+    e.best = b;
+  }
+};
+
 // Per-stage device timing with HIP events on the context stream.
 struct Timer {
   hipStream_t stream = nullptr;
@@ -82,6 +113,7 @@ struct ts_ctx {
   std::string err;
   ts::Workspace ws;
   ts::Timer timer;
+  ts::Tuner tuner;
   std::vector<std::string> stage_names_store;
   std::vector<const char*> stage_names;
   std::vector<double> stage_ms;

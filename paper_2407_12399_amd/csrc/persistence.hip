@@ -2152,6 +2152,13 @@ __global__ void k_decode(Grid g, NbOff off, const int32_t* __restrict__ rank,
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// An integer from the environment, clamped to [lo, hi]; dflt when unset.
+inline int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* e = std::getenv(name);
+  if (!e) return dflt;
+  return std::min(hi, std::max(lo, std::atoi(e)));
+}
+
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
   T v;
@@ -2532,7 +2539,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     BA.pool_full = bfull;
     BA.err = err;
     BA.stats = nullptr;
-    const int hcap = 64, rcap = 32;
+    // launch parameters, overridable for tuning (TS_D1_*); results do not depend on them
+    const int hcap = env_int("TS_D1_HCAP", 64, 8, 1024), rcap = env_int("TS_D1_RCAP", 32, 8, 1024);
+    const int pass0_steps = env_int("TS_D1_STEPS", 512, 16, 1 << 20);
     int64_t ntodo = ncols;
     const uint32_t* list = nullptr;  // first pass: every column
     for (int pass = 0;; ++pass) {
@@ -2550,7 +2559,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       BA.pool = pool;
       BA.col_desc = col_desc;
       BA.retry = out;
-      BA.max_steps = lds ? 64 * g.n : 512;
+      BA.max_steps = lds ? 64 * g.n : pass0_steps;
       if (!lds) {
         uint64_t* hk = ws.get<uint64_t>("d1.hk", nthreads * hcap);
         uint32_t* hr = ws.get<uint32_t>("d1.hr", nthreads * hcap);
@@ -2655,10 +2664,22 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       TS_HIP(hipGetLastError());
       pool_hint = std::max(pool_hint, pool_cap);
     };
-    const int kCheckEvery = 8;
+    const int kCheckEvery = env_int("TS_D1_CHECK", 8, 1, 256);
     // Columns are reduced block by block in index order; a block's columns
     // only interact with each other once every earlier column is final.
-    const int64_t kBlock = 1 << 16;
+    // the block size is autotuned per size class of the column count (the
+    // pairs do not depend on it); TS_D1_BLOCK_BITS fixes it
+    static const int kBlockBits[4] = {15, 16, 17, 18};
+    const std::string tune_key = "d1.block." + std::to_string(64 - __builtin_clzll(uint64_t(ncols) | 1));
+    int tune_idx = -1, block_bits = 16;
+    if (std::getenv("TS_D1_BLOCK_BITS")) {
+      block_bits = env_int("TS_D1_BLOCK_BITS", 16, 10, 24);
+    } else {
+      tune_idx = ctx->tuner.pick(tune_key, 4);
+      block_bits = kBlockBits[tune_idx];
+    }
+    const int64_t kBlock = int64_t(1) << block_bits;
+    const auto t_reduce = std::chrono::steady_clock::now();
     unsigned int* round_d = ws.get<unsigned int>("d1.round", 1);
     k_fill_u32<<<1, 1, 0, s>>>(round_d, 1, 1u);  // active members carry the round in mark[]
     int rounds = 0;
@@ -2714,6 +2735,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       }
     }
     R->rounds_d1 = rounds;
+    // (the loop ends on a host read of the active count: the stage is done)
+    ctx->tuner.report(tune_key, tune_idx,
+                      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_reduce).count());
     if (rstats) {
       unsigned long long h[8];
       TS_HIP(hipMemcpy(h, rstats, sizeof(h), hipMemcpyDeviceToHost));

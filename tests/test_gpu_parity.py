@@ -401,6 +401,15 @@ def test_batch_edges(gpu, orc):
     _same_pairs(d, orc.diagram(f))
 
 
+def test_autotuned_launches_same_result(gpu, orc):
+    """The first maps of a size class try each D1 block size in turn, later
+    ones use the fastest: every map gives the oracle's diagram."""
+    f = fields.gaussian_mixture((50, 47, 45), 64, 0.1, 13)
+    want = orc.diagram(f)
+    for _ in range(6):
+        _same_pairs(gpu.diagram(_t(f)), want)
+
+
 def test_deterministic(gpu):
     f = fields.gaussian_mixture((40, 36, 33), 64, 0.1, 5)
     a = gpu.pairs(_t(f))
