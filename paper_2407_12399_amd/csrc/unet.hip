@@ -94,6 +94,69 @@ k_conv_fwd(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
   }
 }
 
+// The same convolution for Cout = 16 and Cin a multiple of 16, where a 32 x 32
+// tile would leave half of every instruction idle: one wave computes 64
+// voxels x 16 output channels with four 16x16x16 BF16 MFMAs per k step, which
+// share the step's weights.  Lane l supplies row l % 16 of A (voxel) and column
+// l % 16 of B (output channel) at k = 4 * (l / 16) .. + 3; accumulator i of
+// lane l is row 4 * (l / 16) + i, column l % 16.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256)
+k_conv_fwd16(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
+             const uint16_t* __restrict__ Wt, const float* __restrict__ bias, int relu,
+             float* __restrict__ Yf, uint16_t* __restrict__ Yb) {
+  const int64_t V = int64_t(D) * H * W;
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= (V + 63) / 64) return;  // whole waves exit together
+  const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
+  int64_t v[4];
+  int x[4], y[4], z[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    v[s] = wave * 64 + 16 * s + m;
+    x[s] = y[s] = z[s] = 0;
+    if (v[s] < V) {
+      x[s] = int(v[s] % W);
+      y[s] = int((v[s] / W) % H);
+      z[s] = int(v[s] / (int64_t(W) * H));
+    }
+  }
+  f32x4 acc[4] = {};
+  for (int t = 0; t < 27; ++t) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const uint16_t* xa[4];
+    bool inside[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      inside[s] = v[s] < V && x[s] + dx >= 0 && x[s] + dx < W && y[s] + dy >= 0 &&
+                  y[s] + dy < H && z[s] + dz >= 0 && z[s] + dz < D;
+      xa[s] = X + (v[s] + dx + int64_t(W) * (dy + int64_t(H) * dz)) * Cin + 4 * q;
+    }
+    const uint16_t* wb = Wt + (int64_t(t) * 16 + m) * Cin + 4 * q;
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(wb + c0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bf16x4 a = {0, 0, 0, 0};
+        if (inside[s]) a = *reinterpret_cast<const bf16x4*>(xa[s] + c0);
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+      }
+    }
+  }
+  const float bc = bias ? bias[m] : 0.0f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t vv = wave * 64 + 16 * s + 4 * q + i;
+      if (vv >= V) continue;
+      float val = acc[s][i] + bc;
+      if (Yf) Yf[vv * 16 + m] = val;
+      if (relu) val = fmaxf(val, 0.0f);
+      if (Yb) Yb[vv * 16 + m] = to_bf16(val);
+    }
+}
+
 // Backward weights: dW[t][co][ci] += sum_v dY[v][co] * X[v + off_t][ci] over
 // a chunk of voxels.  One wave: tap t, 32 output x 32 input channels, with the
 // voxels as the MFMA's k; partial sums are added to dW atomically.
@@ -420,6 +483,12 @@ struct Acts {
 
 void conv_fwd(ts_ctx* ctx, const uint16_t* X, const Vol& vol, int cin, const uint16_t* Wt,
               const float* bias, int cout, bool relu, float* Yf, uint16_t* Yb) {
+  if (cout == 16 && cin % 16 == 0) {
+    const int64_t waves = (vol.V() + 63) / 64;
+    k_conv_fwd16<<<nblk(waves * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt, bias,
+                                                             relu ? 1 : 0, Yf, Yb);
+    return;
+  }
   const int64_t tiles = ((vol.V() + 31) / 32) * ((cout + 31) / 32);
   k_conv_fwd<<<nblk(tiles * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt, bias, cout,
                                                          relu ? 1 : 0, Yf, Yb);
