@@ -40,7 +40,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
 
 
-@pytest.mark.parametrize("dims", [(8, 12, 16), (4, 4, 4), (12, 8, 20)])
+@pytest.mark.parametrize("dims", [(8, 12, 16), (4, 4, 4), (12, 8, 20), (32, 32, 32), (64, 64, 64)])
 def test_unet_forward_and_gradient(gpu, dims):
     import torch
     from oracle import unet_ref
