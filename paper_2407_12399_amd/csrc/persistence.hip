@@ -1202,7 +1202,10 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
 // Per-lane scratch with an interleaved layout: element j of lane t lives at
 // [j * stride + t], so that the lanes of a wave touching the same depth hit
 // the same cache lines.
-struct LaneHeap {  // max-heap of edge keys (duplicates allowed)
+// Max-heap of edge keys (duplicates allowed), 4-ary: half the levels of a
+// binary heap, and the four children of a node are loaded together, so a pop
+// or push waits on about half as many dependent memory round trips.
+struct LaneHeap {
   uint64_t* key;
   uint32_t* ref;
   int64_t stride;
@@ -1212,7 +1215,7 @@ struct LaneHeap {  // max-heap of edge keys (duplicates allowed)
     if (len >= cap) return false;
     int i = len++;
     while (i > 0) {
-      const int p = (i - 1) >> 1;
+      const int p = (i - 1) >> 2;
       const uint64_t pk = k(p);
       if (pk >= kk) break;
       key[int64_t(i) * stride] = pk;
@@ -1232,18 +1235,21 @@ struct LaneHeap {  // max-heap of edge keys (duplicates allowed)
     const uint32_t lr = ref[int64_t(len) * stride];
     int i = 0;
     while (true) {
-      int c = 2 * i + 1;
-      if (c >= len) break;
-      uint64_t ck = k(c);
-      if (c + 1 < len) {
-        const uint64_t ck2 = k(c + 1);
-        if (ck2 > ck) {
-          ck = ck2;
-          ++c;
+      const int c0 = 4 * i + 1;
+      if (c0 >= len) break;
+      uint64_t ck[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ck[j] = c0 + j < len ? k(c0 + j) : 0ull;
+      int c = c0;
+      uint64_t best = ck[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j)
+        if (c0 + j < len && ck[j] > best) {
+          best = ck[j];
+          c = c0 + j;
         }
-      }
-      if (ck <= lk) break;
-      key[int64_t(i) * stride] = ck;
+      if (best <= lk) break;
+      key[int64_t(i) * stride] = best;
       ref[int64_t(i) * stride] = ref[int64_t(c) * stride];
       i = c;
     }
