@@ -1026,19 +1026,39 @@ __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int*
                           const int32_t* __restrict__ node_id, const uint64_t* __restrict__ node_key,
                           PairOut po) {
   const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= *nlist) return;
-  const uint32_t i = list[j];
-  if (state[i] != 0) return;
-  const int a = ca[i], b = cb[i];
-  const unsigned int pr = dual ? unsigned(nedges - 1 - i) : i;
-  // the younger endpoint component may join the older one along its lowest edge
-  const bool a_older = dual ? (a > b) : (a < b);
-  const int younger = a_older ? b : a;
-  const int elder = a_older ? a : b;
-  if (best[younger] == pr) {
+  uint32_t i = 0;
+  int younger = 0, elder = 0;
+  bool link = false, keep = false;
+  if (j < *nlist) {
+    i = list[j];
+    if (state[i] == 0) {
+      const int a = ca[i], b = cb[i];
+      const unsigned int pr = dual ? unsigned(nedges - 1 - i) : i;
+      // the younger endpoint component may join the older one along its lowest edge
+      const bool a_older = dual ? (a > b) : (a < b);
+      younger = a_older ? b : a;
+      elder = a_older ? a : b;
+      link = best[younger] == pr;
+      keep = !link;
+    }
+  }
+  // appends aggregated per wave: one atomic per list and wave
+  const uint64_t mk = __ballot(keep), ml = __ballot(link);
+  const int lane = __lane_id();
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  unsigned int qb = 0;
+  unsigned long long pb = 0;
+  if (lane == 0) {
+    if (mk) qb = atomicAdd(nnext, unsigned(__popcll(mk)));
+    if (ml) pb = atomicAdd(po.count, (unsigned long long)__popcll(ml));
+  }
+  qb = unsigned(__shfl(int(qb), 0, 64));
+  pb = (unsigned long long)__shfl((long long)pb, 0, 64);
+  if (keep) next[qb + __popcll(mk & lt)] = i;
+  if (link) {
     parent[younger] = elder;
     state[i] = 2;
-    const unsigned long long p = atomicAdd(po.count, 1ull);
+    const unsigned long long p = pb + __popcll(ml & lt);
     if ((int64_t)p < po.cap) {
       if (!dual) {
         po.dim[p] = 0;
@@ -1054,9 +1074,6 @@ __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int*
         po.dkey[p] = node_key[younger];
       }
     }
-  } else {
-    const unsigned int q = atomicAdd(nnext, 1u);
-    next[q] = i;
   }
 }
 
@@ -1992,11 +2009,25 @@ __global__ void k_fill_u8(uint8_t* a, int64_t n, uint8_t v) {
   if (i < n) a[i] = v;
 }
 
+// Slot of this lane's item in a list appended to by whole waves (one atomic
+// per wave); every lane of the wave calls it, take or not.
+__device__ __forceinline__ unsigned int wave_append(bool take, unsigned int* counter) {
+  const uint64_t m = __ballot(take);
+  const int lane = __lane_id();
+  unsigned int base = 0;
+  if (lane == 0 && m) base = atomicAdd(counter, unsigned(__popcll(m)));
+  base = unsigned(__shfl(int(base), 0, 64));
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  return base + unsigned(__popcll(m & lt));
+}
+
+// columns of D1 (triangles not paired in D2), in no particular order
 __global__ void k_collect_cols(const uint8_t* __restrict__ tri_state, int64_t nt,
                                uint32_t* __restrict__ cols, unsigned int* __restrict__ ncols) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nt) return;
-  if (tri_state[i] == 1) cols[atomicAdd(ncols, 1u)] = uint32_t(i);
+  const bool take = i < nt && tri_state[i] == 1;
+  const unsigned int at = wave_append(take, ncols);
+  if (take) cols[at] = uint32_t(i);
 }
 
 __global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
@@ -2005,12 +2036,20 @@ __global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
                            const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
                            PairOut po) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  const uint64_t d = col_desc[c];
-  if ((d & 0xFFFFFFu) == 0) return;
+  uint64_t d = 0;
+  if (c < ncols) d = col_desc[c];
+  const bool take = c < ncols && (d & 0xFFFFFFu) != 0;  // an empty column pairs nothing
+  // one atomic per wave on the pair count
+  const uint64_t m = __ballot(take);
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == 0 && m) base = atomicAdd(po.count, (unsigned long long)__popcll(m));
+  base = (unsigned long long)__shfl((long long)base, 0, 64);
+  if (!take) return;
   const uint32_t row = pool[d >> 24];
   const uint32_t ti = cols[c];
-  const unsigned long long p = atomicAdd(po.count, 1ull);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long p = base + __popcll(m & lt);
   if ((int64_t)p < po.cap) {
     po.dim[p] = 1;
     po.birth[p] = edge_ids[row];
@@ -2086,10 +2125,14 @@ __global__ void k_diag_keys(const int32_t* __restrict__ pdim, const uint64_t* __
                             const uint64_t* __restrict__ dkey, int64_t np, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ idx, unsigned int* __restrict__ nd) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const uint64_t rb = bkey[i] >> 12, rd = dkey[i] >> 12;
-  if (rb == rd) return;  // zero persistence
-  const unsigned int p = atomicAdd(nd, 1u);
+  uint64_t rb = 0, rd = 0;
+  if (i < np) {
+    rb = bkey[i] >> 12;
+    rd = dkey[i] >> 12;
+  }
+  const bool take = i < np && rb != rd;  // zero persistence is dropped
+  const unsigned int p = wave_append(take, nd);
+  if (!take) return;
   keys[p] = (rb << 39) | (rd << 14) | (uint64_t(pdim[i]) << 12) | (bkey[i] & 0xFFFu);
   idx[p] = uint32_t(i);
 }
