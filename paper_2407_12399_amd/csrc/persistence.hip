@@ -2718,13 +2718,15 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     // only interact with each other once every earlier column is final.
     // the block size is autotuned per size class of the column count (the
     // pairs do not depend on it); TS_D1_BLOCK_BITS fixes it
-    static const int kBlockBits[4] = {15, 16, 17, 18};
+    // (24 bits: every column in one block, so the last columns start their
+    // chains as soon as their owners are final)
+    static const int kBlockBits[5] = {16, 17, 18, 20, 24};
     const std::string tune_key = "d1.block." + std::to_string(64 - __builtin_clzll(uint64_t(ncols) | 1));
     int tune_idx = -1, block_bits = 16;
     if (std::getenv("TS_D1_BLOCK_BITS")) {
       block_bits = env_int("TS_D1_BLOCK_BITS", 16, 10, 24);
     } else {
-      tune_idx = ctx->tuner.pick(tune_key, 4);
+      tune_idx = ctx->tuner.pick(tune_key, 5);
       block_bits = kBlockBits[tune_idx];
     }
     const int64_t kBlock = int64_t(1) << block_bits;
