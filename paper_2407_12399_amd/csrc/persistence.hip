@@ -1719,26 +1719,31 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
 // ---- workgroup reduction of a long column -------------------------------
 constexpr int kLongThreads = 1024;
 
-// exclusive prefix sum of v over the workgroup; *total receives the sum
-__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+// Exclusive prefix sums over the workgroup of two 0/1 flags packed as
+// fa | fb << 16 (a workgroup holds at most 1024 lanes, so each sum fits in
+// 16 bits); *total receives both sums packed the same way.  The per-wave
+// totals are scanned by the first wave with shuffles.
+__device__ __forceinline__ uint32_t block_scan2(uint32_t v, uint32_t* s_wave, uint32_t* total) {
   const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const unsigned nw = blockDim.x / 64;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t m = __ballot(v != 0);  // v is 0 or 1
-  const uint32_t in_wave = __popcll(m & lt);
-  if (lane == 0) s_wave[wave] = __popcll(m);
+  const uint64_t ma = __ballot(v & 1u), mb = __ballot((v >> 16) & 1u);
+  const uint32_t in_wave = uint32_t(__popcll(ma & lt)) | (uint32_t(__popcll(mb & lt)) << 16);
+  if (lane == 0) s_wave[wave] = uint32_t(__popcll(ma)) | (uint32_t(__popcll(mb)) << 16);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (unsigned w = 0; w < blockDim.x / 64; ++w) {
-      const uint32_t t = s_wave[w];
-      s_wave[w] = acc;
-      acc += t;
+  if (wave == 0) {
+    const uint32_t c = lane < nw ? s_wave[lane] : 0u;
+    uint32_t x = c;  // inclusive scan; packed halves never carry (sums <= 1024)
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = uint32_t(__shfl_up(int(x), d, 64));
+      if (int(lane) >= d) x += y;
     }
-    s_wave[blockDim.x / 64] = acc;
+    if (lane < nw) s_wave[lane] = x - c;
+    if (lane == nw - 1) s_wave[nw] = x;
   }
   __syncthreads();
   const uint32_t r = s_wave[wave] + in_wave;
-  *total = s_wave[blockDim.x / 64];
+  *total = s_wave[nw];
   __syncthreads();
   return r;
 }
@@ -1758,30 +1763,29 @@ __device__ __forceinline__ uint32_t count_greater_g(const uint32_t* __restrict__
 // by the whole workgroup; returns the result length.
 __device__ uint32_t block_xor(const uint32_t* A, uint32_t a, const uint32_t* B, uint32_t b,
                               uint32_t* out, uint32_t* s_wave) {
+  // one pass: lane t of chunk k takes A[k * 1024 + t] and B[k * 1024 + t]; an
+  // element kept from A lands at 2 * (kept A before it) - i + (B elements
+  // greater than it), and symmetrically for B
   uint32_t keptA = 0, keptB = 0, tot;
-  for (uint32_t base = 0; base < a; base += kLongThreads) {
+  const uint32_t n = a > b ? a : b;
+  for (uint32_t base = 0; base < n; base += kLongThreads) {
     const uint32_t i = base + threadIdx.x;
-    uint32_t keep = 0, r = 0, x = 0;
+    uint32_t ka = 0, kb = 0, ra = 0, rb = 0, xa = 0, xb = 0;
     if (i < a) {
-      x = A[i];
-      r = count_greater_g(B, b, x);
-      keep = !(r < b && B[r] == x);
+      xa = A[i];
+      ra = count_greater_g(B, b, xa);
+      ka = !(ra < b && B[ra] == xa);
     }
-    const uint32_t pre = keptA + block_scan(keep, s_wave, &tot);
-    if (keep) out[2 * pre - i + r] = x;
-    keptA += tot;
-  }
-  for (uint32_t base = 0; base < b; base += kLongThreads) {
-    const uint32_t j = base + threadIdx.x;
-    uint32_t keep = 0, r = 0, x = 0;
-    if (j < b) {
-      x = B[j];
-      r = count_greater_g(A, a, x);
-      keep = !(r < a && A[r] == x);
+    if (i < b) {
+      xb = B[i];
+      rb = count_greater_g(A, a, xb);
+      kb = !(rb < a && A[rb] == xb);
     }
-    const uint32_t pre = keptB + block_scan(keep, s_wave, &tot);
-    if (keep) out[2 * pre - j + r] = x;
-    keptB += tot;
+    const uint32_t pre = block_scan2(ka | (kb << 16), s_wave, &tot);
+    if (ka) out[2 * (keptA + (pre & 0xFFFFu)) - i + ra] = xa;
+    if (kb) out[2 * (keptB + (pre >> 16)) - i + rb] = xb;
+    keptA += tot & 0xFFFFu;
+    keptB += tot >> 16;
   }
   __syncthreads();
   return keptA + keptB;
