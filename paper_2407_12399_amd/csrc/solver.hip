@@ -462,16 +462,20 @@ namespace {
 
 // 2D KD-tree over the targets (birth, death).  Every target j carries a
 // score s_j (or "masked"); a node keeps the largest unmasked score below it.
-// best(p) returns the unmasked target minimising |p - q_j|^2 - s_j.
+// best(p) returns the unmasked target minimising |p - q_j|^2 - s_j.  Leaf
+// members are stored contiguously in tree order (coordinates, score, mask,
+// id), so that a leaf scan reads one short run of memory.
 struct KDTree {
   struct Node {
     double x0, x1, y0, y1, smax;
     int left, right, parent, begin, end;
   };
   std::vector<Node> nodes;
-  std::vector<int> idx, leaf_of;
-  std::vector<double> s;
-  std::vector<char> masked;
+  std::vector<int> idx, leaf_of, pos_of;
+  std::vector<double> s;     // score by target id
+  std::vector<char> masked;  // mask by target id
+  std::vector<double> lx, ly, ls;  // coordinates and score in tree order
+  std::vector<char> lm;            // mask in tree order
   const double* X = nullptr;
   const double* Y = nullptr;
   static constexpr double NEG = -std::numeric_limits<double>::infinity();
@@ -486,6 +490,16 @@ struct KDTree {
     masked.assign(k, 0);
     nodes.clear();
     if (k > 0) make(0, k, -1);
+    pos_of.assign(k, -1);
+    lx.resize(k);
+    ly.resize(k);
+    ls.assign(k, 0.0);
+    lm.assign(k, 0);
+    for (int t = 0; t < k; ++t) {
+      pos_of[idx[t]] = t;
+      lx[t] = X[idx[t]];
+      ly[t] = Y[idx[t]];
+    }
   }
   int make(int b, int e, int parent) {
     Node nd;
@@ -523,6 +537,8 @@ struct KDTree {
   void set_all(const std::vector<double>& sc) {
     s = sc;
     std::fill(masked.begin(), masked.end(), 0);
+    std::fill(lm.begin(), lm.end(), 0);
+    for (size_t t = 0; t < idx.size(); ++t) ls[t] = s[idx[t]];
     for (int i = int(nodes.size()) - 1; i >= 0; --i) refresh(i);
   }
   void refresh(int id) {
@@ -530,7 +546,7 @@ struct KDTree {
     if (nd.left < 0) {
       double m = NEG;
       for (int t = nd.begin; t < nd.end; ++t)
-        if (!masked[idx[t]]) m = std::max(m, s[idx[t]]);
+        if (!lm[t]) m = std::max(m, ls[t]);
       nd.smax = m;
     } else {
       nd.smax = std::max(nodes[nd.left].smax, nodes[nd.right].smax);
@@ -540,6 +556,8 @@ struct KDTree {
   void update(int j, double sj, bool mask) {
     s[j] = sj;
     masked[j] = mask;
+    ls[pos_of[j]] = sj;
+    lm[pos_of[j]] = mask;
     for (int id = leaf_of[j]; id >= 0; id = nodes[id].parent) {
       const double before = nodes[id].smax;
       refresh(id);
@@ -552,7 +570,9 @@ struct KDTree {
     return dx * dx + dy * dy;
   }
   // the two smallest values of |p - q_j|^2 - s_j over unmasked j (depth
-  // first, nearer child first, pruned by the node bounds)
+  // first, nearer child first, pruned by the node bounds); the result does
+  // not depend on the visiting order: v1 is the minimum, the returned id the
+  // lowest id attaining it, v2 the second smallest value of the multiset
   mutable std::vector<std::pair<double, int>> stack_;
   int best2(double px, double py, double* v1, double* v2) const {
     *v1 = *v2 = std::numeric_limits<double>::infinity();
@@ -567,14 +587,13 @@ struct KDTree {
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
         for (int t = nd.begin; t < nd.end; ++t) {
-          const int j = idx[t];
-          if (masked[j]) continue;
-          const double dx = X[j] - px, dy = Y[j] - py;
-          const double v = (dx * dx + dy * dy) - s[j];
-          if (v < *v1 || (v == *v1 && j < bj)) {
+          if (lm[t]) continue;
+          const double dx = lx[t] - px, dy = ly[t] - py;
+          const double v = (dx * dx + dy * dy) - ls[t];
+          if (v < *v1 || (v == *v1 && idx[t] < bj)) {
             *v2 = *v1;
             *v1 = v;
-            bj = j;
+            bj = idx[t];
           } else if (v < *v2) {
             *v2 = v;
           }
@@ -611,13 +630,12 @@ struct KDTree {
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
         for (int t = nd.begin; t < nd.end; ++t) {
-          const int j = idx[t];
-          if (masked[j]) continue;
-          const double dx = X[j] - px, dy = Y[j] - py;
-          const double v = (dx * dx + dy * dy) - s[j];
-          if (v < *val || (v == *val && j < bj)) {
+          if (lm[t]) continue;
+          const double dx = lx[t] - px, dy = ly[t] - py;
+          const double v = (dx * dx + dy * dy) - ls[t];
+          if (v < *val || (v == *val && idx[t] < bj)) {
             *val = v;
-            bj = j;
+            bj = idx[t];
           }
         }
       } else {
@@ -626,6 +644,45 @@ struct KDTree {
       }
     }
     return bj;
+  }
+};
+
+// Smallest and second smallest of n prices with the lowest index attaining
+// the smallest (a tournament tree; one leaf-to-root pass per price change).
+struct MinTwo {
+  int size = 1;
+  std::vector<double> mn1, mn2;
+  std::vector<int> id1;
+  void build(const std::vector<double>& v) {
+    const int n = int(v.size());
+    size = 1;
+    while (size < n) size <<= 1;
+    const double inf = std::numeric_limits<double>::infinity();
+    mn1.assign(2 * size, inf);
+    mn2.assign(2 * size, inf);
+    id1.assign(2 * size, std::numeric_limits<int>::max());
+    for (int i = 0; i < n; ++i) {
+      mn1[size + i] = v[i];
+      id1[size + i] = i;
+    }
+    for (int x = size - 1; x >= 1; --x) pull(x);
+  }
+  void pull(int x) {
+    const int l = 2 * x, r = 2 * x + 1;
+    if (mn1[l] < mn1[r] || (mn1[l] == mn1[r] && id1[l] < id1[r])) {
+      mn1[x] = mn1[l];
+      id1[x] = id1[l];
+      mn2[x] = std::min(mn2[l], mn1[r]);
+    } else {
+      mn1[x] = mn1[r];
+      id1[x] = id1[r];
+      mn2[x] = std::min(mn2[r], mn1[l]);
+    }
+  }
+  void set(int i, double v) {
+    int x = size + i;
+    mn1[x] = v;
+    for (x >>= 1; x >= 1; x >>= 1) pull(x);
   }
 };
 
@@ -659,21 +716,12 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
     std::vector<double> sc(k, 0.0);
     tree.set_all(sc);  // s_j = -price_j
   }
-  typedef std::pair<double, int> PI;
-  std::priority_queue<PI, std::vector<PI>, std::greater<PI>> copies;  // (price, i), lazy
-  for (int i = 0; i < m; ++i) copies.push({0.0, i});
+  MinTwo copies;  // prices of the points' diagonal copies
+  copies.build(std::vector<double>(m, 0.0));
   auto two_cheapest = [&](int* i1, double* p1, double* p2) {
-    while (!copies.empty() && copies.top().first != price[k + copies.top().second]) copies.pop();
-    *i1 = -1;
-    *p1 = *p2 = std::numeric_limits<double>::infinity();
-    if (copies.empty()) return;
-    const PI a = copies.top();
-    copies.pop();
-    while (!copies.empty() && copies.top().first != price[k + copies.top().second]) copies.pop();
-    *i1 = a.second;
-    *p1 = a.first;
-    if (!copies.empty()) *p2 = copies.top().first;
-    copies.push(a);
+    *i1 = m > 0 ? copies.id1[1] : -1;
+    *p1 = copies.mn1[1];
+    *p2 = copies.mn2[1];
   };
   double eps = W / 4.0;
   const double eps_final = W * eps_rel;
@@ -727,7 +775,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       const double inc = (v1 - v2) + eps;
       price[o1] += inc;
       if (o1 < k) tree.update(o1, -price[o1], false);
-      else copies.push({price[o1], o1 - k});
+      else copies.set(o1 - k, price[o1]);
       const int prev = owner[o1];
       owner[o1] = x;
       holds[x] = o1;
