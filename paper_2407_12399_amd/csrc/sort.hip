@@ -1,10 +1,14 @@
 // sort.hip -- device scan and stable LSD radix sort for gfx950 (wave64).
 //
 // Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
-// pass.  A block owns a tile of kTile consecutive keys; the scatter keeps
-// the input order of equal digits (stability) by ranking keys round by round
-// (256 keys per round, in index order) with wave64 ballots for the
-// within-wave rank and LDS counters across the block's waves.
+// pass.  A block owns a tile of rs_tile<K>() consecutive keys (4096 32-bit or
+// 2048 64-bit keys).  The scatter keeps
+// the input order of equal digits (stability) by ranking the tile's keys
+// round by round (256 keys per round, in index order) with wave64 ballots
+// for the within-wave rank and LDS counters across the block's waves; the
+// ranked keys are placed in LDS in digit order and then written out by
+// consecutive threads to consecutive addresses of each digit's output run,
+// so that the global writes are coalesced.
 #include "internal.h"
 
 namespace ts {
@@ -14,6 +18,12 @@ constexpr int kThreads = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
 constexpr int kWaves = kThreads / 64;
+// keys per thread of a radix tile: 16 for 32-bit keys, 8 for 64-bit keys
+// (the scatter stages a whole tile of keys and values in LDS)
+template <class K>
+constexpr int rs_items() { return sizeof(K) == 8 ? 8 : 16; }
+template <class K>
+constexpr int rs_tile() { return kThreads * rs_items<K>(); }
 
 // ---------------------------------------------------------------- scan
 
@@ -86,9 +96,10 @@ __global__ void __launch_bounds__(kThreads) rs_hist(const K* keys, size_t n, int
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const size_t base = size_t(blockIdx.x) * kTile;
+  constexpr int kRsItems = rs_items<K>();
+  const size_t base = size_t(blockIdx.x) * rs_tile<K>();
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
+  for (int i = 0; i < kRsItems; ++i) {
     const size_t idx = base + size_t(i) * kThreads + threadIdx.x;
     if (idx < n) atomicAdd(&cnt[uint32_t(keys[idx] >> shift) & 0xFFu], 1u);
   }
@@ -96,25 +107,48 @@ __global__ void __launch_bounds__(kThreads) rs_hist(const K* keys, size_t n, int
   hist[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// offsets[d * nblocks + b]: first output position of digit d's keys of tile b
 template <class K>
 __global__ void __launch_bounds__(kThreads) rs_scatter(const K* kin, const uint32_t* vin,
                                                        K* kout, uint32_t* vout, size_t n,
                                                        int shift, const uint32_t* offsets,
                                                        int nblocks) {
-  __shared__ uint32_t running[256];
+  constexpr int kRsItems = rs_items<K>();
+  constexpr int kRsTile = rs_tile<K>();
+  __shared__ K lk[kRsTile];
+  __shared__ uint32_t lv[kRsTile];
+  __shared__ uint32_t start[256];    // first tile slot of each digit
+  __shared__ uint32_t running[256];  // keys of each digit placed so far
   __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t scan_tmp[kWaves + 1];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  running[threadIdx.x] = offsets[size_t(threadIdx.x) * nblocks + blockIdx.x];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const size_t base = size_t(blockIdx.x) * kTile;
-  for (int r = 0; r < kItems; ++r) {
+  const size_t base = size_t(blockIdx.x) * kRsTile;
+  const int tile_n = int(n - base < size_t(kRsTile) ? n - base : size_t(kRsTile));
+  K key[kRsItems];
+  uint32_t val[kRsItems];
+  running[threadIdx.x] = 0;  // the tile's digit histogram first
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    const size_t idx = base + size_t(r) * kThreads + threadIdx.x;
+    key[r] = idx < n ? kin[idx] : K(0);
+    val[r] = idx < n ? vin[idx] : 0u;
+    if (idx < n) atomicAdd(&running[uint32_t(key[r] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  uint32_t total;
+  start[threadIdx.x] = block_exclusive_scan(running[threadIdx.x], scan_tmp, &total);
+  running[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+#pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
-    const size_t idx = base + size_t(r) * kThreads + threadIdx.x;
-    const bool valid = idx < n;
-    K key = valid ? kin[idx] : K(0);
-    const uint32_t d = uint32_t(key >> shift) & 0xFFu;
+    const bool valid = r * kThreads + int(threadIdx.x) < tile_n;
+    const uint32_t d = uint32_t(key[r] >> shift) & 0xFFu;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -126,16 +160,26 @@ __global__ void __launch_bounds__(kThreads) rs_scatter(const K* kin, const uint3
     if (valid && rank_in_wave == 0) wcnt[wave][d] = __popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = running[d] + rank_in_wave;
+      uint32_t pos = start[d] + running[d] + rank_in_wave;
       for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = key;
-      vout[pos] = vin[idx];
+      lk[pos] = key[r];
+      lv[pos] = val[r];
     }
     __syncthreads();
     uint32_t add = 0;
+#pragma unroll
     for (int w = 0; w < kWaves; ++w) add += wcnt[w][threadIdx.x];
     running[threadIdx.x] += add;
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < tile_n; p += kThreads) {
+    const K k = lk[p];
+    const uint32_t d = uint32_t(k >> shift) & 0xFFu;
+    const size_t g = size_t(offsets[size_t(d) * nblocks + blockIdx.x]) + size_t(p - int(start[d]));
+    if (g < n) {
+      kout[g] = k;
+      vout[g] = lv[p];
+    }
   }
 }
 
@@ -152,7 +196,7 @@ template <class K>
 void radix_sort_impl(Workspace& ws, K* keys, uint32_t* vals, size_t n, int begin_bit,
                      int end_bit, hipStream_t s, const char* tag) {
   if (n <= 1 || end_bit <= begin_bit) return;
-  const int nblocks = int((n + kTile - 1) / kTile);
+  const int nblocks = int((n + rs_tile<K>() - 1) / rs_tile<K>());
   std::string t(tag);
   K* ktmp = ws.get<K>(t + ".k", n);
   uint32_t* vtmp = ws.get<uint32_t>(t + ".v", n);
