@@ -48,14 +48,14 @@ ALGO_BYTES_PER_VERTEX = {
 # WRITE_SIZE passes (KiB per dispatch), each scaled by what the same counter
 # reads for a plain 256 MiB device copy (fetch x2.0, write x1.0).  It belongs
 # to the kernel source it was measured on: a changed kernel reports null.
-K3_COUNTERS = {"source_sha1": "afc3e3ecb49f529a20a395d021d34ef0205180fa",
-               "dims": (256, 256, 256), "fetch_kib": 98228.1, "write_kib": 404380.4,
+K3_COUNTERS = {"source_sha1": "bc8c6567d936d94f39c2c5d8425661550676767c",
+               "dims": (256, 256, 256), "fetch_kib": 98221.3, "write_kib": 404298.2,
                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # SQ_INSTS_VALU / SQ_WAVES of K3 from the instruction-mix pass recorded in
 # profiles/k3_gradient_filament256_instruction_mix.md (same kernel source)
-K3_VALU_PER_WAVE = {"source_sha1": "afc3e3ecb49f529a20a395d021d34ef0205180fa", "valu": 19136.9}
+K3_VALU_PER_WAVE = {"source_sha1": "bc8c6567d936d94f39c2c5d8425661550676767c", "valu": 19138.0}
 # untimed persistence maps before timing: the launch tuner tries 5 D1 block sizes
 WARM_MAPS = 6
 # one wave64 VALU instruction per CU per cycle (4 SIMDs x 16 lanes), 256 CUs at 2.4 GHz

@@ -370,7 +370,9 @@ __device__ __forceinline__ uint32_t nib(uint64_t packed, int i) {
 }
 
 // code layout: w0,w1[0:10) = 14 edge codes of 3 bits; w1[10:18) = triangle
-// codes 32..35; w2,w3 = triangle codes 0..31 (2 bits each).
+// codes 32..35; w1[18:32) = lower-neighbour mask (bit k: neighbour k is in
+// the grid and precedes the vertex in the order); w2,w3 = triangle codes
+// 0..31 (2 bits each).
 //   edge code: 0..5 paired with the j-th star triangle containing the edge,
 //              6 critical, 7 paired with the centre vertex
 //   triangle code: 0 paired with a facet (or not in the lower star),
@@ -379,6 +381,7 @@ __device__ __forceinline__ uint32_t edge_code(const uint4& c, int k) {
   const uint64_t e = uint64_t(c.x) | (uint64_t(c.y & 0x3FFu) << 32);
   return uint32_t(e >> (3 * k)) & 7u;
 }
+__device__ __forceinline__ uint32_t lower_mask(const uint4& c) { return c.y >> 18; }
 __device__ __forceinline__ uint32_t tri_code(const uint4& c, int t) {
   if (t < 32) {
     const uint64_t e = uint64_t(c.z) | (uint64_t(c.w) << 32);
@@ -681,7 +684,7 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
     }
     uint4 c;
     c.x = uint32_t(ecode);
-    c.y = uint32_t(ecode >> 32) | (tcode1 << 10);
+    c.y = uint32_t(ecode >> 32) | (tcode1 << 10) | (low << 18);
     c.z = uint32_t(tcode0);
     c.w = uint32_t(tcode0 >> 32);
     code_out[v] = c;
@@ -1100,8 +1103,8 @@ __global__ void k_uf_init(int32_t* __restrict__ parent, unsigned int* __restrict
 // Follows the ascending gradient path from star tet l of vertex y to a
 // maximum; returns the canonical id of the maximum, or -1 for the outside.
 template <class Site>
-__device__ int ascend(const Site& S, int total, const int32_t* __restrict__ rank,
-                      const uint4* __restrict__ code, int y, int l, int* err) {
+__device__ int ascend(const Site& S, int total, const uint4* __restrict__ code, int y, int l,
+                      int* err) {
   int steps = 0;
   while (true) {
     if (++steps > 6 * total) {
@@ -1132,7 +1135,7 @@ __device__ int ascend(const Site& S, int total, const int32_t* __restrict__ rank
     const uint32_t valid = S.valid_at(x, yy, z);
     if (!((valid >> k) & 1u)) return -1;  // the facet lies on the box boundary
     const int cv = y + S.nb(k);
-    if (rank[cv] < rank[y]) {
+    if ((lower_mask(c) >> k) & 1u) {  // cv precedes y: the tet stays in y's lower star
       l = other;
     } else {
       // the next tet belongs to the lower star of its new apex cv
@@ -1151,8 +1154,8 @@ __device__ int ascend(const Site& S, int total, const int32_t* __restrict__ rank
 
 template <class Geo>
 __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* __restrict__ tri_keys,
-                          int64_t nt, Geo G, const int32_t* __restrict__ rank,
-                          const int32_t* __restrict__ order, const uint4* __restrict__ code,
+                          int64_t nt, Geo G, const int32_t* __restrict__ order,
+                          const uint4* __restrict__ code,
                           const int32_t* __restrict__ max_pos_of,
                           const int32_t* __restrict__ max_ids, int64_t nmax,
                           int32_t* __restrict__ ca, int32_t* __restrict__ cb,
@@ -1172,6 +1175,7 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
   int x, yy, z;
   S.xyz(y, &x, &yy, &z);
   const uint32_t valid = S.valid_at(x, yy, z);
+  const uint32_t lowy = lower_mask(code[y]);
   int comp[2];
   for (int s = 0; s < 2; ++s) {
     const int q = c_st.tri_tet[lt][s];
@@ -1184,7 +1188,7 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
     const int k = ffs32(third);
     const int cv = y + S.nb(k);
     int yv = y, l = q;
-    if (rank[cv] > rank[y]) {
+    if (!((lowy >> k) & 1u)) {  // cv follows y
       const int anc = y + S.step(c_st.tet_anc[q][0], c_st.tet_anc[q][1], c_st.tet_anc[q][2]);
       const int qt = c_st.tet_type[q];
       int bx, by, bz, vx, vy, vz;
@@ -1194,7 +1198,7 @@ __global__ void k_d2_init(const int32_t* __restrict__ tri_ids, const uint64_t* _
       l = c_st.tet_local[qt][__popc(m2)];
       yv = cv;
     }
-    const int mid = ascend(S, G.total(), rank, code, yv, l, err);
+    const int mid = ascend(S, G.total(), code, yv, l, err);
     if (mid < 0) {
       comp[s] = int(nmax);
     } else {
@@ -2530,8 +2534,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     uint32_t* listA = ws.get<uint32_t>("uf2.listA", ntri + 1);
     k_fill_u8<<<blocks_for(ntri), 256, 0, s>>>(tstate, ntri, 0);
     with_geo([&](auto G) {
-      k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, G, R->rank,
-                                                 R->order, R->code, max_pos_of, R->cid[3], nmax,
+      k_d2_init<<<blocks_for(ntri), 256, 0, s>>>(R->cid[2], R->ckey[2], ntri, G, R->order,
+                                                 R->code, max_pos_of, R->cid[3], nmax,
                                                  ca, cb, listA, err);
     });
     ctx->timer.stop();
