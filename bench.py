@@ -351,6 +351,18 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": stage_ms[dom]}
+    # algorithmic HBM rate of every streaming stage (order and gradient)
+    stage_hbm = {k: {"algo_bytes_per_vertex": ALGO_BYTES_PER_VERTEX[k], "ms": stage_ms[k],
+                     "achieved_gbs": ALGO_BYTES_PER_VERTEX[k] * n / (stage_ms[k] * 1e-3) / 1e9,
+                     "frac": ALGO_BYTES_PER_VERTEX[k] * n / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                 for k in ALGO_BYTES_PER_VERTEX if stage_ms.get(k)}
+    order_keys = [k for k in ("K1 order keys", "K1 radix sort", "K2 rank") if stage_ms.get(k)]
+    order_ms = sum(stage_ms[k] for k in order_keys)
+    order_bytes = sum(ALGO_BYTES_PER_VERTEX[k] for k in order_keys) * n
+    stage_hbm["vertex order (K1 + K2)"] = {
+        "algo_bytes_per_vertex": order_bytes / n, "ms": order_ms,
+        "achieved_gbs": order_bytes / (order_ms * 1e-3) / 1e9,
+        "frac": order_bytes / (order_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     k3_issue = None
     if dom == "K3 gradient" and kernel_source_sha1() == K3_VALU_PER_WAVE["source_sha1"]:
@@ -381,6 +393,7 @@ def main():
                    "stage_ms_total": solver_stage},
         "roofline": roofline,
         "k3_issue": k3_issue,
+        "stage_hbm": stage_hbm,
     }
     # the paper's assignment setting (auction at relative precision 0.01)
     if not args.no_paper_auction:
