@@ -394,6 +394,11 @@ def main():
         "roofline": roofline,
         "k3_issue": k3_issue,
         "stage_hbm": stage_hbm,
+        # the map's largest stage by device time; it is latency-bound (rounds of
+        # dependent column additions), so it has no byte or flop roofline
+        "map_dominant_stage": {"stage": max(stage_ms, key=stage_ms.get),
+                               "ms": max(stage_ms.values()),
+                               "share": max(stage_ms.values()) / pm_ms},
     }
     # the paper's assignment setting (auction at relative precision 0.01)
     if not args.no_paper_auction:
