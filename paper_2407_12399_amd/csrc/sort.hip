@@ -2,13 +2,13 @@
 //
 // Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
 // pass.  A block owns a tile of rs_tile<K>() consecutive keys (4096 32-bit or
-// 2048 64-bit keys).  The scatter keeps
-// the input order of equal digits (stability) by ranking the tile's keys
-// round by round (256 keys per round, in index order) with wave64 ballots
-// for the within-wave rank and LDS counters across the block's waves; the
-// ranked keys are placed in LDS in digit order and then written out by
-// consecutive threads to consecutive addresses of each digit's output run,
-// so that the global writes are coalesced.
+// 2048 64-bit keys).  The scatter keeps the input order of equal digits
+// (stability) by ranking the tile's keys round by round (256 keys per round,
+// in index order) with wave64 ballots for the within-wave rank and LDS
+// counters across the block's waves; the ranked keys are placed in LDS in
+// digit order and then written out by consecutive threads to consecutive
+// addresses of each digit's output run, so that the global writes are
+// coalesced.
 #include "internal.h"
 
 namespace ts {
