@@ -990,8 +990,13 @@ __global__ void k_uf_hook(const uint32_t* __restrict__ list, const unsigned int*
                           int32_t* __restrict__ parent, unsigned int* __restrict__ best,
                           uint8_t* __restrict__ state, int descending, int64_t nedges) {
   const unsigned int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= *nlist) return;
-  const uint32_t i = list[j];
+  const unsigned int n = *nlist;
+  if (j >= n) return;
+  // the list holds edges in about increasing index order; visit them in about
+  // increasing priority (reversed for the descending order), so that a
+  // component's lowest edge tends to come first and the plain read below
+  // filters out the later ones (the result does not depend on the order)
+  const uint32_t i = list[descending ? n - 1 - j : j];
   const int a = uf_find(parent, ca[i]), b = uf_find(parent, cb[i]);
   ca[i] = a;
   cb[i] = b;
