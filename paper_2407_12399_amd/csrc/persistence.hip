@@ -967,6 +967,32 @@ __global__ void k_d0_init(const int32_t* __restrict__ edge_ids, int64_t ne, Geo 
   list[i] = uint32_t(i);
 }
 
+// Slot of this thread's item in a list appended to by whole blocks: one
+// atomic per block on the list counter (per-wave atomics on one counter
+// serialise tens of thousands of operations when millions of items are
+// appended).  Every thread of the block calls it, once per kernel; blocks of
+// at most 1024 threads.  The order of the list is unspecified.
+template <class C>
+__device__ __forceinline__ C block_append(bool take, C* counter) {
+  __shared__ unsigned int s_wcnt[16];
+  __shared__ C s_base;
+  const uint64_t m = __ballot(take);
+  const int lane = __lane_id();
+  const int wave = int(threadIdx.x >> 6);
+  if (lane == 0) s_wcnt[wave] = unsigned(__popcll(m));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int tot = 0;
+    for (int w = 0; w < int((blockDim.x + 63) >> 6); ++w) tot += s_wcnt[w];
+    s_base = tot ? atomicAdd(counter, C(tot)) : C(0);
+  }
+  __syncthreads();
+  C b = s_base;
+  for (int w = 0; w < wave; ++w) b += s_wcnt[w];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  return b + C(__popcll(m & lt));
+}
+
 // Union-find with the elder rule, in rounds.  Every component finds its
 // lowest outgoing edge (hook); then every component whose lowest outgoing
 // edge leads to a component with an older representative joins it, and its
@@ -1050,19 +1076,16 @@ __global__ void k_uf_link(const uint32_t* __restrict__ list, const unsigned int*
       keep = !link;
     }
   }
-  // appends aggregated per wave: one atomic per list and wave
-  const uint64_t mk = __ballot(keep), ml = __ballot(link);
+  // the kept edges (millions in the first rounds) are appended per block, the
+  // pairs (fewer) per wave
+  const unsigned int q = block_append(keep, nnext);
+  const uint64_t ml = __ballot(link);
   const int lane = __lane_id();
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  unsigned int qb = 0;
   unsigned long long pb = 0;
-  if (lane == 0) {
-    if (mk) qb = atomicAdd(nnext, unsigned(__popcll(mk)));
-    if (ml) pb = atomicAdd(po.count, (unsigned long long)__popcll(ml));
-  }
-  qb = unsigned(__shfl(int(qb), 0, 64));
+  if (lane == 0 && ml) pb = atomicAdd(po.count, (unsigned long long)__popcll(ml));
   pb = (unsigned long long)__shfl((long long)pb, 0, 64);
-  if (keep) next[qb + __popcll(mk & lt)] = i;
+  if (keep) next[q] = i;
   if (link) {
     parent[younger] = elder;
     state[i] = 2;
@@ -2022,24 +2045,12 @@ __global__ void k_fill_u8(uint8_t* a, int64_t n, uint8_t v) {
   if (i < n) a[i] = v;
 }
 
-// Slot of this lane's item in a list appended to by whole waves (one atomic
-// per wave); every lane of the wave calls it, take or not.
-__device__ __forceinline__ unsigned int wave_append(bool take, unsigned int* counter) {
-  const uint64_t m = __ballot(take);
-  const int lane = __lane_id();
-  unsigned int base = 0;
-  if (lane == 0 && m) base = atomicAdd(counter, unsigned(__popcll(m)));
-  base = unsigned(__shfl(int(base), 0, 64));
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  return base + unsigned(__popcll(m & lt));
-}
-
 // columns of D1 (triangles not paired in D2), in no particular order
 __global__ void k_collect_cols(const uint8_t* __restrict__ tri_state, int64_t nt,
                                uint32_t* __restrict__ cols, unsigned int* __restrict__ ncols) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool take = i < nt && tri_state[i] == 1;
-  const unsigned int at = wave_append(take, ncols);
+  const unsigned int at = block_append(take, ncols);
   if (take) cols[at] = uint32_t(i);
 }
 
@@ -2052,17 +2063,10 @@ __global__ void k_d1_pairs(const uint64_t* __restrict__ col_desc, int64_t ncols,
   uint64_t d = 0;
   if (c < ncols) d = col_desc[c];
   const bool take = c < ncols && (d & 0xFFFFFFu) != 0;  // an empty column pairs nothing
-  // one atomic per wave on the pair count
-  const uint64_t m = __ballot(take);
-  const int lane = __lane_id();
-  unsigned long long base = 0;
-  if (lane == 0 && m) base = atomicAdd(po.count, (unsigned long long)__popcll(m));
-  base = (unsigned long long)__shfl((long long)base, 0, 64);
+  const unsigned long long p = block_append(take, po.count);
   if (!take) return;
   const uint32_t row = pool[d >> 24];
   const uint32_t ti = cols[c];
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const unsigned long long p = base + __popcll(m & lt);
   if ((int64_t)p < po.cap) {
     po.dim[p] = 1;
     po.birth[p] = edge_ids[row];
@@ -2144,7 +2148,7 @@ __global__ void k_diag_keys(const int32_t* __restrict__ pdim, const uint64_t* __
     rd = dkey[i] >> 12;
   }
   const bool take = i < np && rb != rd;  // zero persistence is dropped
-  const unsigned int p = wave_append(take, nd);
+  const unsigned int p = block_append(take, nd);
   if (!take) return;
   keys[p] = (rb << 39) | (rd << 14) | (uint64_t(pdim[i]) << 12) | (bkey[i] & 0xFFFu);
   idx[p] = uint32_t(i);
