@@ -479,6 +479,12 @@ struct KDTree {
   const double* X = nullptr;
   const double* Y = nullptr;
   static constexpr double NEG = -std::numeric_limits<double>::infinity();
+  // Targets per leaf.  The queries return the same answer for any tree shape
+  // (a node's bound never exceeds the value of a target below it, in floating
+  // point too, since every step of both is monotone), so this only sets the
+  // balance between node visits and leaf scans: 32 is about 12 % faster than
+  // 8 on the auction's problems, 64 is slower again.
+  static constexpr int kLeaf = 32;
 
   void build(const double* x, const double* y, int k) {
     X = x;
@@ -518,7 +524,7 @@ struct KDTree {
     nd.smax = NEG;
     const int id = int(nodes.size());
     nodes.push_back(nd);
-    if (e - b > 8) {
+    if (e - b > kLeaf) {
       const int mid = (b + e) / 2;
       const bool byx = (nd.x1 - nd.x0) >= (nd.y1 - nd.y0);
       std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int a, int c) {
