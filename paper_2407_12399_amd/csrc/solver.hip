@@ -560,14 +560,22 @@ struct KDTree {
   }
   // change target j (score / mask) and the maxima above it
   void update(int j, double sj, bool mask) {
+    const double old = masked[j] ? NEG : s[j];  // j's contribution to the maxima
+    const double now = mask ? NEG : sj;
     s[j] = sj;
     masked[j] = mask;
     ls[pos_of[j]] = sj;
     lm[pos_of[j]] = mask;
-    for (int id = leaf_of[j]; id >= 0; id = nodes[id].parent) {
+    const int leaf = leaf_of[j];
+    if (now >= old) {  // the maxima on the path can only rise, to `now`
+      for (int id = leaf; id >= 0 && nodes[id].smax < now; id = nodes[id].parent) nodes[id].smax = now;
+      return;
+    }
+    if (old < nodes[leaf].smax) return;  // j was not a maximiser: nothing changes
+    for (int id = leaf; id >= 0; id = nodes[id].parent) {
       const double before = nodes[id].smax;
       refresh(id);
-      if (nodes[id].smax == before && id != leaf_of[j]) break;
+      if (nodes[id].smax == before && id != leaf) break;
     }
   }
   static double d2box(const Node& nd, double px, double py) {
@@ -579,16 +587,21 @@ struct KDTree {
   // first, nearer child first, pruned by the node bounds); the result does
   // not depend on the visiting order: v1 is the minimum, the returned id the
   // lowest id attaining it, v2 the second smallest value of the multiset
-  mutable std::vector<std::pair<double, int>> stack_;
   int best2(double px, double py, double* v1, double* v2) const {
     *v1 = *v2 = std::numeric_limits<double>::infinity();
     int bj = -1;
     if (nodes.empty() || nodes[0].smax == NEG) return -1;
-    stack_.clear();
-    stack_.push_back({d2box(nodes[0], px, py) - nodes[0].smax, 0});
-    while (!stack_.empty()) {
-      const auto top = stack_.back();
-      stack_.pop_back();
+    // depth-first stack: it grows by at most one entry per tree level (the
+    // median splits keep the depth below 26 for any int-sized target set)
+    double sb[64];
+    int sn[64];
+    int top_n = 0;
+    sb[0] = d2box(nodes[0], px, py) - nodes[0].smax;
+    sn[0] = 0;
+    top_n = 1;
+    while (top_n > 0) {
+      --top_n;
+      const std::pair<double, int> top = {sb[top_n], sn[top_n]};
       if (top.first > *v2) continue;
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
@@ -611,11 +624,11 @@ struct KDTree {
         const double br = R.smax == NEG ? INFINITY : d2box(R, px, py) - R.smax;
         // push the farther child first so that the nearer one is visited first
         if (bl <= br) {
-          if (br <= *v2) stack_.push_back({br, nd.right});
-          if (bl <= *v2) stack_.push_back({bl, nd.left});
+          if (br <= *v2) { sb[top_n] = br; sn[top_n++] = nd.right; }
+          if (bl <= *v2) { sb[top_n] = bl; sn[top_n++] = nd.left; }
         } else {
-          if (bl <= *v2) stack_.push_back({bl, nd.left});
-          if (br <= *v2) stack_.push_back({br, nd.right});
+          if (bl <= *v2) { sb[top_n] = bl; sn[top_n++] = nd.left; }
+          if (br <= *v2) { sb[top_n] = br; sn[top_n++] = nd.right; }
         }
       }
     }
