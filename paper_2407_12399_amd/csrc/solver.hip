@@ -605,10 +605,19 @@ struct KDTree {
       if (top.first > *v2) continue;
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
-        for (int t = nd.begin; t < nd.end; ++t) {
-          if (lm[t]) continue;
+        // values of the whole leaf first (a straight loop the compiler
+        // vectorises), then the running two smallest
+        double vals[kLeaf];
+        const int cnt = nd.end - nd.begin;
+        for (int u = 0; u < cnt; ++u) {
+          const int t = nd.begin + u;
           const double dx = lx[t] - px, dy = ly[t] - py;
-          const double v = (dx * dx + dy * dy) - ls[t];
+          vals[u] = lm[t] ? INFINITY : (dx * dx + dy * dy) - ls[t];
+        }
+        for (int u = 0; u < cnt; ++u) {
+          const double v = vals[u];
+          if (!(v <= *v2)) continue;  // neither of the two smallest (or masked)
+          const int t = nd.begin + u;
           if (v < *v1 || (v == *v1 && idx[t] < bj)) {
             *v2 = *v1;
             *v1 = v;
