@@ -675,42 +675,43 @@ struct KDTree {
   }
 };
 
-// Smallest and second smallest of n prices with the lowest index attaining
-// the smallest (a tournament tree; one leaf-to-root pass per price change).
-struct MinTwo {
-  int size = 1;
-  std::vector<double> mn1, mn2;
-  std::vector<int> id1;
-  void build(const std::vector<double>& v) {
-    const int n = int(v.size());
-    size = 1;
-    while (size < n) size <<= 1;
-    const double inf = std::numeric_limits<double>::infinity();
-    mn1.assign(2 * size, inf);
-    mn2.assign(2 * size, inf);
-    id1.assign(2 * size, std::numeric_limits<int>::max());
-    for (int i = 0; i < n; ++i) {
-      mn1[size + i] = v[i];
-      id1[size + i] = i;
-    }
-    for (int x = size - 1; x >= 1; --x) pull(x);
+// Prices that only rise, with the lowest price (the lowest id among equal
+// ones) and the second lowest price at hand: a binary heap ordered by
+// (price, id) that knows where every id sits, so that a raised price sinks
+// from its own slot (a raised minimum, the common case in an auction, stops
+// as soon as it passes the next cheapest prices).
+struct RisingMinHeap {
+  std::vector<double> p;     // slot -> price
+  std::vector<int> id, pos;  // slot -> id, id -> slot
+  int n = 0;
+  void build(int count) {  // every price 0: the id order is a valid heap
+    n = count;
+    p.assign(n, 0.0);
+    id.resize(n);
+    pos.resize(n);
+    for (int i = 0; i < n; ++i) id[i] = pos[i] = i;
   }
-  void pull(int x) {
-    const int l = 2 * x, r = 2 * x + 1;
-    if (mn1[l] < mn1[r] || (mn1[l] == mn1[r] && id1[l] < id1[r])) {
-      mn1[x] = mn1[l];
-      id1[x] = id1[l];
-      mn2[x] = std::min(mn2[l], mn1[r]);
-    } else {
-      mn1[x] = mn1[r];
-      id1[x] = id1[r];
-      mn2[x] = std::min(mn2[r], mn1[l]);
+  bool before(int a, int b) const { return p[a] < p[b] || (p[a] == p[b] && id[a] < id[b]); }
+  void raise(int i, double v) {  // v is at least the current price of i
+    int sl = pos[i];
+    p[sl] = v;
+    for (;;) {
+      int c = 2 * sl + 1;
+      if (c >= n) break;
+      if (c + 1 < n && before(c + 1, c)) ++c;
+      if (!before(c, sl)) break;
+      std::swap(p[sl], p[c]);
+      std::swap(id[sl], id[c]);
+      pos[id[sl]] = sl;
+      pos[id[c]] = c;
+      sl = c;
     }
   }
-  void set(int i, double v) {
-    int x = size + i;
-    mn1[x] = v;
-    for (x >>= 1; x >= 1; x >>= 1) pull(x);
+  int min_id() const { return n > 0 ? id[0] : -1; }
+  double min_price() const { return n > 0 ? p[0] : std::numeric_limits<double>::infinity(); }
+  double second_price() const {  // the second smallest sits below the root
+    if (n < 2) return std::numeric_limits<double>::infinity();
+    return n > 2 ? std::min(p[1], p[2]) : p[1];
   }
 };
 
@@ -744,12 +745,12 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
     std::vector<double> sc(k, 0.0);
     tree.set_all(sc);  // s_j = -price_j
   }
-  MinTwo copies;  // prices of the points' diagonal copies
-  copies.build(std::vector<double>(m, 0.0));
+  RisingMinHeap copies;  // prices of the points' diagonal copies
+  copies.build(m);
   auto two_cheapest = [&](int* i1, double* p1, double* p2) {
-    *i1 = m > 0 ? copies.id1[1] : -1;
-    *p1 = copies.mn1[1];
-    *p2 = copies.mn2[1];
+    *i1 = copies.min_id();
+    *p1 = copies.min_price();
+    *p2 = copies.second_price();
   };
   double eps = W / 4.0;
   const double eps_final = W * eps_rel;
@@ -803,7 +804,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       const double inc = (v1 - v2) + eps;
       price[o1] += inc;
       if (o1 < k) tree.update(o1, -price[o1], false);
-      else copies.set(o1 - k, price[o1]);
+      else copies.raise(o1 - k, price[o1]);
       const int prev = owner[o1];
       owner[o1] = x;
       holds[x] = o1;
