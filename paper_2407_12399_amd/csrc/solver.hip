@@ -586,11 +586,33 @@ struct KDTree {
   // the two smallest values of |p - q_j|^2 - s_j over unmasked j (depth
   // first, nearer child first, pruned by the node bounds); the result does
   // not depend on the visiting order: v1 is the minimum, the returned id the
-  // lowest id attaining it, v2 the second smallest value of the multiset
-  int best2(double px, double py, double* v1, double* v2) const {
+  // lowest id attaining it, v2 the second smallest value of the multiset.
+  // hint[0..1]: two target ids (or -1) counted before the descent, so that
+  // the pruning starts from their values (a caller passes the previous
+  // answer of the same point); on return, the best id and an id attaining v2.
+  int best2(double px, double py, double* v1, double* v2, int* hint) const {
     *v1 = *v2 = std::numeric_limits<double>::infinity();
-    int bj = -1;
+    int bj = -1, j2 = -1;
+    const int h0 = hint[0], h1 = hint[1] != hint[0] ? hint[1] : -1;
+    hint[0] = hint[1] = -1;
     if (nodes.empty() || nodes[0].smax == NEG) return -1;
+    auto offer = [&](double v, int j) {
+      if (v < *v1 || (v == *v1 && j < bj)) {
+        *v2 = *v1;
+        j2 = bj;
+        *v1 = v;
+        bj = j;
+      } else if (v < *v2) {
+        *v2 = v;
+        j2 = j;
+      }
+    };
+    for (const int h : {h0, h1})
+      if (h >= 0 && !masked[h]) {
+        const int t = pos_of[h];
+        const double dx = lx[t] - px, dy = ly[t] - py;
+        offer((dx * dx + dy * dy) - ls[t], h);
+      }
     // depth-first stack: it grows by at most one entry per tree level (the
     // median splits keep the depth below 26 for any int-sized target set)
     double sb[64];
@@ -617,14 +639,8 @@ struct KDTree {
         for (int u = 0; u < cnt; ++u) {
           const double v = vals[u];
           if (!(v <= *v2)) continue;  // neither of the two smallest (or masked)
-          const int t = nd.begin + u;
-          if (v < *v1 || (v == *v1 && idx[t] < bj)) {
-            *v2 = *v1;
-            *v1 = v;
-            bj = idx[t];
-          } else if (v < *v2) {
-            *v2 = v;
-          }
+          const int j = idx[nd.begin + u];
+          if (j != h0 && j != h1) offer(v, j);  // the hints are counted already
         }
       } else {
         const Node& L = nodes[nd.left];
@@ -641,6 +657,8 @@ struct KDTree {
         }
       }
     }
+    hint[0] = bj;
+    hint[1] = j2;
     return bj;
   }
   // argmin over unmasked j of |p - q_j|^2 - s_j; ties to the lower index
@@ -752,6 +770,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
     *p1 = copies.min_price();
     *p2 = copies.second_price();
   };
+  std::vector<int> hints(2 * size_t(m), -1);  // each point's last best and second-best targets
   double eps = W / 4.0;
   const double eps_final = W * eps_rel;
   std::vector<int> queue;
@@ -770,7 +789,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       int o1;
       if (x < m) {
         double c1, c2;
-        const int j = tree.best2(pb[x], pd[x], &c1, &c2);  // c = |p-q|^2 + price
+        const int j = tree.best2(pb[x], pd[x], &c1, &c2, &hints[2 * size_t(x)]);  // c = |p-q|^2 + price
         const double vd = -dp[x] - price[k + x];
         v1 = vd;
         o1 = k + x;
