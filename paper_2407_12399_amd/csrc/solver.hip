@@ -661,11 +661,19 @@ struct KDTree {
     hint[1] = j2;
     return bj;
   }
-  // argmin over unmasked j of |p - q_j|^2 - s_j; ties to the lower index
-  int best(double px, double py, double* val) const {
+  // argmin over unmasked j of |p - q_j|^2 - s_j; ties to the lower index.
+  // seed (or -1): a target counted before the descent, so that the search
+  // starts from its value (same answer).
+  int best(double px, double py, double* val, int seed = -1) const {
     *val = std::numeric_limits<double>::infinity();
     int bj = -1;
     if (nodes.empty() || nodes[0].smax == NEG) return -1;
+    if (seed >= 0 && !masked[seed]) {
+      const int t = pos_of[seed];
+      const double dx = lx[t] - px, dy = ly[t] - py;
+      *val = (dx * dx + dy * dy) - ls[t];
+      bj = seed;
+    }
     typedef std::pair<double, int> NI;  // (lower bound, node)
     std::priority_queue<NI, std::vector<NI>, std::greater<NI>> todo;
     todo.push({d2box(nodes[0], px, py) - nodes[0].smax, 0});
@@ -846,7 +854,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       for (int o = 0; o < k + m; ++o) dual += price[o];
       for (int i = 0; i < m; ++i) {
         double val;
-        const int j = tree.best(pb[i], pd[i], &val);  // min_j c_ij + p_j
+        const int j = tree.best(pb[i], pd[i], &val, hints[2 * size_t(i)]);  // min_j c_ij + p_j
         double prof = -dp[i] - price[k + i];
         if (j >= 0) prof = std::max(prof, -val);
         dual += prof;
