@@ -188,7 +188,7 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
  * n_regradient of every report are those of the whole batch.
  *   nf:   number of fields (>= 1); the batch holds at most 2^25 vertices
  *   f, g: host arrays of nf pointers (device or host per opt->inputs_on_device);
- *         no g[i] may alias an f[k]
+ *         no g[i] may overlap an f[k] or another g[k]
  *   dims: host array of 3 * nf sizes
  *   sig:  mode 0 (persistence threshold) only
  *   reps: host array of nf reports
@@ -197,6 +197,17 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
 int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64_t* dims,
                       const ts_signal* sig, const ts_options* opt, float* const* g,
                       ts_report* reps);
+
+/* Signal-vertex mask of D(f) (Sec. 3): mask[v] = 1 at the birth and death
+ * vertices of every pair that `sig` keeps as signal (the rule ts_simplify
+ * applies to D(f0): threshold relative to max f - min f, or the explicit
+ * list; the essential pair always counts), 0 elsewhere.  This is the second
+ * input channel of the warm-start network.
+ *   f:        n floats, device or host (on_device)
+ *   mask:     n floats (output), same memory kind as f, must not overlap f
+ *   n_signal: receives the number of signal pairs (may be NULL) */
+int ts_signal_mask(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
+                   int32_t on_device, float* mask, int64_t* n_signal);
 
 /* ---- the learned warm start ---------------------------------------------
  * A 3D U-Net (3 levels of 16/32/64 channels, two 3x3x3 convolutions with ReLU

@@ -81,9 +81,10 @@ def lib():
         L.tso_assign.argtypes = [i64, P, P, i64, P, P, P, P]
         L.tso_bottleneck.argtypes = [P, i64, P, i64, P]
         L.tso_simplify.argtypes = [P, P, P, P, P, P, P, i64]
+        L.tso_assign_step.argtypes = [P, i64, P, P, i64, P, i64, P, P, P]
         for fn in ("tso_order", "tso_gradient", "tso_gradient_at", "tso_critical",
                    "tso_pairs", "tso_diagram", "tso_assign", "tso_bottleneck",
-                   "tso_simplify"):
+                   "tso_simplify", "tso_assign_step"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -197,6 +198,25 @@ def assign(pb, pd, qb, qd):
     _check(lib().tso_assign(len(pb), _ptr(pb), _ptr(pd), len(qb), _ptr(qb), _ptr(qd),
                             _ptr(match), _ptr(cost)), "tso_assign")
     return match[: len(pb)].copy(), float(cost[0])
+
+
+def assign_step(prev, phi_prev, cur, targets):
+    """One iteration's assignment (Sec. 4.3): still join of `cur` against
+    `prev` (records in diagram order), inheritance of `phi_prev`, exact
+    reduced problem against the targets no still point holds, canonical
+    form.  Returns (phi, n_still, n_reduced)."""
+    prev = np.ascontiguousarray(prev, dtype=PAIR_DTYPE)
+    cur = np.ascontiguousarray(cur, dtype=PAIR_DTYPE)
+    targets = np.ascontiguousarray(targets, dtype=PAIR_DTYPE)
+    phi_prev = np.ascontiguousarray(phi_prev, dtype=np.int32)
+    assert len(phi_prev) == len(prev)
+    phi = np.empty(max(len(cur), 1), np.int32)
+    ns = np.zeros(1, np.int64)
+    nr = np.zeros(1, np.int64)
+    _check(lib().tso_assign_step(_ptr(prev), len(prev), _ptr(phi_prev), _ptr(cur), len(cur),
+                                 _ptr(targets), len(targets), _ptr(phi), _ptr(ns), _ptr(nr)),
+           "tso_assign_step")
+    return phi[: len(cur)].copy(), int(ns[0]), int(nr[0])
 
 
 def bottleneck(a, b):

@@ -773,8 +773,14 @@ void persistence(const Grid& g, const float* f, Persistence* P) {
 
 const double kBig = 1e300;
 
-/* Dense Hungarian algorithm (shortest augmenting paths with potentials) for
- * a square cost matrix a[1..N][1..N]; returns col_of_row. */
+/* Dense Hungarian algorithm (Kuhn-Munkres) for a square cost matrix
+ * a[1..N][1..N], in its O(N^3) shortest-augmenting-path form with row and
+ * column potentials (u, v), the column-to-row map p and the path links way:
+ * the textbook formulation (Kuhn 1955, Munkres 1957; the potentials version
+ * as given, e.g., by Lawler, "Combinatorial Optimization", 1976).  Rows are
+ * added one at a time; each addition grows a Dijkstra-like search over
+ * columns by reduced cost until it reaches a free column, then flips the
+ * path.  Returns col_of_row. */
 std::vector<int> hungarian(const std::vector<std::vector<double>>& a) {
   const int N = int(a.size());
   std::vector<double> u(N + 1, 0), v(N + 1, 0), minv(N + 1);
@@ -1315,6 +1321,38 @@ int tso_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt,
   std::vector<int> m;
   assign_dense(PB, PD, QB, QD, &m, cost);
   for (int64_t i = 0; i < n_pts; ++i) match[i] = m[i];
+  return 0;
+}
+
+int tso_assign_step(const tso_pair* prev, int64_t n_prev, const int32_t* phi_prev,
+                    const tso_pair* cur, int64_t n_cur, const tso_pair* targets,
+                    int64_t n_tgt, int32_t* phi_out, int64_t* n_still, int64_t* n_reduced) {
+  if (n_prev < 0 || n_cur < 0 || n_tgt < 0 || !phi_out || !n_still || !n_reduced) return -1;
+  if ((n_prev > 0 && (!prev || !phi_prev)) || (n_cur > 0 && !cur) || (n_tgt > 0 && !targets))
+    return -1;
+  const int64_t dims[3] = {2, 2, 2};
+  Grid g(dims);
+  Solver S(g);
+  for (int64_t j = 0; j < n_tgt; ++j) {
+    const tso_pair& t = targets[j];
+    if (t.essential) {
+      if (S.ess_target >= 0) return -1;
+      S.ess_target = int(j);
+    }
+    S.T.push_back({t.dim, t.essential, t.v_birth, t.v_death, t.birth, t.death});
+  }
+  std::vector<tso_pair> A(prev, prev + n_prev), B(cur, cur + n_cur);
+  const std::vector<Point> Pp = points_of(A), Pc = points_of(B);
+  std::vector<int> phip(n_prev);
+  for (int64_t i = 0; i < n_prev; ++i) {
+    if (phi_prev[i] < -1 || phi_prev[i] >= n_tgt) return -1;
+    phip[i] = phi_prev[i];
+  }
+  for (const Point& p : Pc)
+    if (p.essential && S.ess_target < 0) return -1;
+  std::vector<int> phi;
+  S.assign(Pc, Pp, phip, &phi, n_still, n_reduced);
+  for (int64_t i = 0; i < n_cur; ++i) phi_out[i] = phi[i];
   return 0;
 }
 

@@ -136,6 +136,24 @@ int tso_assign(int64_t n_pts, const double* pb, const double* pd,
                int64_t n_tgt, const double* qb, const double* qd,
                int32_t* match, double* cost);
 
+/* One assignment step of the solver (Sec. 4.3, with Eq. (1) on the reduced
+ * problem), exactly as tso_simplify runs it at iteration j >= 1:
+ *   prev[n_prev], phi_prev: D(f_{j-1}) in diagram order and its assignment
+ *                           (target index or -1 for the diagonal);
+ *   cur[n_cur]:             D(f_j) in diagram order;
+ *   targets[n_tgt]:         D_T (v_birth, v_death = the vertices in D(f0);
+ *                           birth, death = the target coordinates; at most
+ *                           one essential entry);
+ *   phi_out[n_cur]:         receives the assignment of D(f_j).
+ * Still points (same (dim, v_birth, v_death) as a point of prev, the k-th
+ * occurrence of a key matched with the k-th) keep phi_prev; the essential
+ * point always takes the essential target; the other points are assigned
+ * exactly, per dimension, to the targets that no still point holds, then
+ * put in canonical form.  *n_still, *n_reduced receive the counts. */
+int tso_assign_step(const tso_pair* prev, int64_t n_prev, const int32_t* phi_prev,
+                    const tso_pair* cur, int64_t n_cur, const tso_pair* targets,
+                    int64_t n_tgt, int32_t* phi_out, int64_t* n_still, int64_t* n_reduced);
+
 /* Bottleneck distance (L-infinity ground metric) between two diagrams;
  * finite points of equal dimension and the essential classes are matched
  * separately.  Small inputs only. */

@@ -72,7 +72,7 @@ EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram
            "ts_simplify", "ts_simplify_batch", "ts_unet_param_count", "ts_unet_forward",
            "ts_unet_backward", "ts_unet_adam",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
-           "ts_stage_times"]
+           "ts_stage_times", "ts_signal_mask"]
 
 
 def lib():
@@ -91,6 +91,7 @@ def lib():
         L.ts_diagram_batch.argtypes = [P, i32, P, P, i32, P, i64, P]
         L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
         L.ts_simplify_batch.argtypes = [P, i32, P, P, P, P, P, P]
+        L.ts_signal_mask.argtypes = [P, P, P, P, i32, P, P]
         L.ts_unet_param_count.argtypes = [P]
         L.ts_unet_forward.argtypes = [P, P, P, P, P]
         L.ts_unet_backward.argtypes = [P, P, P, P, P, P, P]
@@ -338,15 +339,11 @@ class Report:
     status: int
 
 
-def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
-             alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
-             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False, init=None):
-    """Topological simplification; returns (g, Report).  g has the kind of
-    the input (torch CUDA tensor in, torch CUDA tensor out).  init: optional
-    start field of the same kind and shape (used unless its loss is higher)."""
-    ctx = context()
-    fp, dims, on_dev, keep = _as_field(field)
+def _signal(threshold, nonsignal_dims, ties_signal, signal_pairs):
+    """ts_signal of the threshold rule, or of an explicit list; returns
+    (struct, list array kept alive)."""
     sig = _Signal()
+    sp = None
     if signal_pairs is not None:
         sp = np.ascontiguousarray(signal_pairs, dtype=PAIR_DTYPE)
         sig.mode, sig.signal, sig.n_signal = 1, sp.ctypes.data, len(sp)
@@ -355,6 +352,38 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
         sig.threshold_rel = threshold
         sig.nonsignal_dim_mask = sum(1 << d for d in nonsignal_dims)
         sig.ties_signal = ties_signal
+    return sig, sp
+
+
+def signal_mask(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0,
+                signal_pairs=None):
+    """Signal-vertex mask of D(field) under the solver's signal rule (Sec. 3):
+    1.0 at the birth and death vertices of the signal pairs, 0.0 elsewhere;
+    same kind and shape as the field.  Returns (mask, number of signal pairs)."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    sig, _sp = _signal(threshold, nonsignal_dims, ties_signal, signal_pairs)
+    if on_dev:
+        m = _torch().empty_like(keep)
+        mp = ctypes.c_void_p(m.data_ptr())
+    else:
+        m = np.empty_like(keep)
+        mp = _ptr(m)
+    cnt = ctypes.c_int64(0)
+    _check(ctx, lib().ts_signal_mask(ctx, fp, _ptr(dims), ctypes.byref(sig), on_dev, mp,
+                                     ctypes.byref(cnt)))
+    return m, int(cnt.value)
+
+
+def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
+             alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
+             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False, init=None):
+    """Topological simplification; returns (g, Report).  g has the kind of
+    the input (torch CUDA tensor in, torch CUDA tensor out).  init: optional
+    start field of the same kind and shape (used unless its loss is higher)."""
+    ctx = context()
+    fp, dims, on_dev, keep = _as_field(field)
+    sig, _sp = _signal(threshold, nonsignal_dims, ties_signal, signal_pairs)
     opt = _Options(alpha_b, alpha_d, j_max, stop_mode, cancel_tol_rel, loss_ratio_s, on_dev,
                    assign_precision, int(bool(full_gradient)))
     init_keep = None

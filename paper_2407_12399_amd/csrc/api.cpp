@@ -187,6 +187,13 @@ ts_pair local_record(const ts_pair& r, int64_t base) {
   return q;
 }
 
+// Whether [a, a + na) and [b, b + nb) (float counts) share memory.
+bool overlaps(const float* a, int64_t na, const float* b, int64_t nb) {
+  const uintptr_t a0 = uintptr_t(a), a1 = a0 + uintptr_t(na) * sizeof(float);
+  const uintptr_t b0 = uintptr_t(b), b1 = b0 + uintptr_t(nb) * sizeof(float);
+  return a0 < b1 && b0 < a1;
+}
+
 void check_solver_args(const ts_signal* sig, const ts_options* opt) {
   if (!sig || !opt) throw Error(TS_ERR_ARG, "null argument");
   if (!(opt->assign_precision >= 0) || !std::isfinite(opt->assign_precision))
@@ -471,11 +478,15 @@ int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int6
     if (sig->mode != 0) throw Error(TS_ERR_ARG, "a batch takes the threshold signal mode only");
     if (opt->init) throw Error(TS_ERR_ARG, "a batch takes no start field");
     if (!f || !g || !reps) throw Error(TS_ERR_ARG, "null argument");
-    for (int i = 0; i < nf; ++i) {
+    for (int i = 0; i < nf; ++i)
       if (!f[i] || !g[i]) throw Error(TS_ERR_ARG, "null field pointer");
-      for (int k = 0; k < nf; ++k)
-        if (f[k] == g[i]) throw Error(TS_ERR_ARG, "an output must not alias an input");
-    }
+    for (int i = 0; i < nf; ++i)
+      for (int k = 0; k < nf; ++k) {
+        if (overlaps(g[i], B.grids[i].n, f[k], B.grids[k].n))
+          throw Error(TS_ERR_ARG, "an output must not overlap an input");
+        if (k != i && overlaps(g[i], B.grids[i].n, g[k], B.grids[k].n))
+          throw Error(TS_ERR_ARG, "outputs must not overlap");
+      }
     ctx->timer.reset();
     const int rc = simplify_batch(ctx, B, f, *sig, *opt, g, reps);
     finish_timing(ctx);
@@ -489,12 +500,32 @@ int ts_simplify(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_sig
     const Grid grid = make_grid(dims);
     check_solver_args(sig, opt);
     if (!g || !rep || !f) throw Error(TS_ERR_ARG, "null argument");
-    if (f == g) throw Error(TS_ERR_ARG, "g must not alias f");
-    if (opt->init == g) throw Error(TS_ERR_ARG, "g must not alias the start field");
+    if (overlaps(f, grid.n, g, grid.n)) throw Error(TS_ERR_ARG, "g must not overlap f");
+    if (opt->init && overlaps(opt->init, grid.n, g, grid.n))
+      throw Error(TS_ERR_ARG, "g must not overlap the start field");
     ctx->timer.reset();
     const int rc = simplify(ctx, f, grid, *sig, *opt, g, rep);
     finish_timing(ctx);
     return rc;
+  });
+}
+
+int ts_signal_mask(ts_ctx* ctx, const float* f, const int64_t dims[3], const ts_signal* sig,
+                   int32_t on_device, float* mask, int64_t* n_signal) {
+  return guarded(ctx, [&]() {
+    const Grid grid = make_grid(dims);
+    if (!sig || !mask) throw Error(TS_ERR_ARG, "null argument");
+    if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
+    if (sig->mode == 1 && sig->n_signal > 0 && !sig->signal)
+      throw Error(TS_ERR_ARG, "signal list is NULL");
+    if (!f || overlaps(mask, grid.n, f, grid.n))
+      throw Error(TS_ERR_ARG, "mask must not overlap f");
+    ctx->timer.reset();
+    const float* fd = device_field(ctx, f, grid.n, on_device);
+    const int64_t c = signal_mask(ctx, fd, grid, *sig, mask, on_device);
+    finish_timing(ctx);
+    if (n_signal) *n_signal = c;
+    return int(TS_OK);
   });
 }
 

@@ -13,6 +13,13 @@ Grid make_grid(const int64_t dims[3]);
 int simplify(ts_ctx* ctx, const float* f, const Grid& grid, const ts_signal& sig,
              const ts_options& opt, float* g, ts_report* rep);
 
+// Signal-vertex mask (Sec. 3): mask[v] = 1 at the birth and death vertices of
+// the pairs of D(f) that the signal rule keeps (the rule ts_simplify applies
+// to D(f0)), 0 elsewhere.  mask is a device pointer when on_device.  Returns
+// the number of signal pairs.
+int64_t signal_mask(ts_ctx* ctx, const float* f_dev, const Grid& grid, const ts_signal& sig,
+                    float* mask, int on_device);
+
 struct Batch;
 
 // The solver on a batch of fields (f[i], g[i], reps[i] per field): the

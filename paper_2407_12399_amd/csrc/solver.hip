@@ -11,6 +11,7 @@
 //      assigned exactly, per dimension, to the targets no still point holds
 //      (host, sparse shortest augmenting paths).
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -268,33 +269,51 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Signal selection (Sec. 3).  Threshold mode: a finite pair is non-signal
+// iff its dimension is in the mask and its persistence is below
+// threshold_rel * range(f0) (or equal to it, unless ties count as signal).
+// List mode: a finite pair is signal iff the list holds its
+// (dim, birth cell, death cell), looked up in a sorted copy of the list.  The
+// essential pair is always signal.
+struct SignalRule {
+  const ts_signal& sig;
+  double thr;
+  std::vector<std::array<int64_t, 3>> listed;
+  SignalRule(const ts_signal& s, double range) : sig(s), thr(double(s.threshold_rel) * range) {
+    if (sig.mode == 1) {
+      listed.reserve(size_t(std::max<int64_t>(sig.n_signal, 0)));
+      for (int64_t q = 0; q < sig.n_signal; ++q)
+        listed.push_back({int64_t(sig.signal[q].dim), sig.signal[q].birth_cell,
+                          sig.signal[q].death_cell});
+      std::sort(listed.begin(), listed.end());
+    }
+  }
+  bool signal(const Pt& p) const {
+    if (p.ess) return true;
+    if (sig.mode == 1)
+      return std::binary_search(listed.begin(), listed.end(),
+                                std::array<int64_t, 3>{int64_t(p.dim), int64_t(p.bcell),
+                                                       int64_t(p.dcell)});
+    const double pers = double(p.d) - double(p.b);
+    const bool masked = (sig.nonsignal_dim_mask >> p.dim) & 1u;
+    const bool below = pers < thr || (pers == thr && !sig.ties_signal);
+    return !(masked && below);
+  }
+};
+
 struct Solver {
   std::vector<Tgt> T;
   int ess_target = -1;
   double gap = 0;  // assignment precision (0: exact / tight auction)
 
-  // Signal selection (Sec. 3): D_T = D(f0) minus the non-signal pairs.
+  // D_T = D(f0) minus the non-signal pairs (Sec. 3).
   void targets(const std::vector<Pt>& P0, const ts_signal& sig, double range,
                std::vector<int>* phi) {
     phi->assign(P0.size(), -1);
-    const double thr = double(sig.threshold_rel) * range;
+    const SignalRule rule(sig, range);
     for (size_t i = 0; i < P0.size(); ++i) {
       const Pt& p = P0[i];
-      bool keep;
-      if (p.ess) {
-        keep = true;
-      } else if (sig.mode == 1) {
-        keep = false;
-        for (int64_t q = 0; q < sig.n_signal && !keep; ++q)
-          keep = sig.signal[q].dim == p.dim && sig.signal[q].birth_cell == p.bcell &&
-                 sig.signal[q].death_cell == p.dcell;
-      } else {
-        const double pers = double(p.d) - double(p.b);
-        const bool masked = (sig.nonsignal_dim_mask >> p.dim) & 1u;
-        const bool below = pers < thr || (pers == thr && !sig.ties_signal);
-        keep = !(masked && below);
-      }
-      if (keep) {
+      if (rule.signal(p)) {
         if (p.ess) ess_target = int(T.size());
         (*phi)[i] = int(T.size());
         T.push_back({p.dim, p.ess, p.vb, p.vd, p.b, p.d});
@@ -1528,6 +1547,43 @@ int simplify_batch(ts_ctx* ctx, const Batch& B, const float* const* f, const ts_
   const int nf = int(B.grids.size());
   const Grid G{0, 0, 0, int(B.base[nf])};
   return simplify_fields(ctx, nf, f, G, &B, sig, opt, g_out, reps);
+}
+
+int64_t signal_mask(ts_ctx* ctx, const float* f_dev, const Grid& G, const ts_signal& sig,
+                    float* mask, int on_device) {
+  hipStream_t s = ctx->stream;
+  PersistenceResult R;
+  compute_persistence(ctx, f_dev, G, &R);  // also rejects non-finite values
+  std::vector<Pt> P;
+  fetch_points(ctx, R, f_dev, &P);
+  const int nb = 256;
+  float* mm = dev<float>(ctx, "sim.mm", 2 * nb);
+  k_minmax<<<nb, 256, 0, s>>>(f_dev, G.n, mm);
+  TS_HIP(hipGetLastError());
+  std::vector<float> h(2 * nb);
+  TS_HIP(hipMemcpyAsync(h.data(), mm, h.size() * 4, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipStreamSynchronize(s));
+  double mn = h[0], mx = h[1];
+  for (int b = 0; b < nb; ++b) {
+    mn = std::min(mn, double(h[2 * b]));
+    mx = std::max(mx, double(h[2 * b + 1]));
+  }
+  const SignalRule rule(sig, mx - mn);
+  std::vector<float> m(G.n, 0.0f);
+  int64_t count = 0;
+  for (const Pt& p : P)
+    if (rule.signal(p)) {
+      m[p.vb] = 1.0f;
+      m[p.vd] = 1.0f;
+      ++count;
+    }
+  if (on_device) {
+    TS_HIP(hipMemcpyAsync(mask, m.data(), size_t(G.n) * 4, hipMemcpyHostToDevice, s));
+    TS_HIP(hipStreamSynchronize(s));
+  } else {
+    std::copy(m.begin(), m.end(), mask);
+  }
+  return count;
 }
 
 }  // namespace ts

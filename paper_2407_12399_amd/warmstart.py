@@ -16,8 +16,9 @@ import time
 
 import numpy as np
 
-from . import (_torch, diagram, simplify, simplify_batch, unet_adam, unet_forward, unet_grad,
+from . import (_torch, simplify, simplify_batch, unet_adam, unet_forward, unet_grad,
                unet_param_count)
+from . import signal_mask as _signal_mask
 from . import fields
 
 # (input channels as stored, output channels) of the ten convolutions
@@ -45,19 +46,10 @@ def init_params(seed: int = 0):
 
 def signal_mask(f, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0):
     """1 at the birth and death vertices of the signal pairs of D(f) (the
-    solver's threshold rule), 0 elsewhere; same shape as f (device)."""
-    torch = _torch()
-    D = diagram(f)
-    rng = float(f.max() - f.min())
-    pers = D["death"].astype(np.float64) - D["birth"].astype(np.float64)
-    thr = threshold * rng
-    below = (pers < thr) | ((pers == thr) & (ties_signal == 0))
-    masked = np.isin(D["dim"], list(nonsignal_dims))
-    keep = (D["essential"] == 1) | ~(masked & below)
-    m = torch.zeros(f.numel(), dtype=torch.float32, device=f.device)
-    idx = np.concatenate([D["v_birth"][keep], D["v_death"][keep]]).astype(np.int64)
-    m[torch.from_numpy(idx).to(f.device)] = 1.0
-    return m.reshape(f.shape)
+    solver's own signal rule, applied by the library), 0 elsewhere; same
+    shape as f (device)."""
+    m, _ = _signal_mask(f, threshold, nonsignal_dims, ties_signal)
+    return m
 
 
 def net_input(f, mask):

@@ -1,0 +1,108 @@
+"""Writes the stored expected values under tests/golden/ from the CPU oracle.
+
+Every value written here comes from `oracle/` (the plain CPU implementation)
+on fields from `paper_2407_12399_amd.fields` (seeded generators that hold none
+of the method's arithmetic).  Nothing here calls the HIP library.
+
+  python tests/golden/make_golden.py filament256        # 256^3 gradient + diagram digests
+  python tests/golden/make_golden.py gauss32 SEED ...   # 32^3 solves to the stop rule
+  python tests/golden/make_golden.py filament64         # 64^3 solve, large reduced problems
+
+Digests are SHA-256 of the arrays' raw little-endian bytes: the gradient's
+dense partner arrays (vup[n], eup[7n], tup[12n] as int32; Sec. 4.2), the
+diagram records (48-byte pairs in diagram order; Sec. 2.2) and solver outputs
+(float32 g; Alg. 1).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2407_12399_amd import fields  # noqa: E402
+
+
+def sha(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _write(name, obj):
+    path = os.path.join(HERE, name)
+    with open(path, "w") as fp:
+        json.dump(obj, fp, indent=1, sort_keys=True)
+        fp.write("\n")
+    print("wrote", path, flush=True)
+
+
+def filament256():
+    """Gradient (Sec. 4.2) and diagram (Sec. 2.2) of the 256^3 filament field, seed 0."""
+    f = fields.workload("filament_256", 0)
+    out = {"workload": "filament_256", "seed": 0, "dims": [256, 256, 256],
+           "cite": "Sec. 2.2 (diagram), Sec. 4.2 (discrete gradient)",
+           "field_sha256": sha(f)}
+    t = time.time()
+    vup, eup, tup = oracle.gradient(f)
+    out["gradient_s"] = round(time.time() - t, 1)
+    out["vup_sha256"], out["eup_sha256"], out["tup_sha256"] = sha(vup), sha(eup), sha(tup)
+    out["critical_counts"] = [int((vup == -1).sum()), int((eup == -1).sum()),
+                              int((tup == -1).sum())]
+    del vup, eup, tup
+    print("gradient done", out["gradient_s"], "s", flush=True)
+    t = time.time()
+    D = oracle.diagram(f)
+    out["diagram_s"] = round(time.time() - t, 1)
+    out["diagram_sha256"] = sha(D)
+    out["diagram_size"] = int(len(D))
+    out["diagram_dims"] = [int((D["dim"] == d).sum()) for d in range(3)]
+    _write("filament256_seed0.json", out)
+
+
+def gauss32(seed: int):
+    """The 32^3 workload (8 Gaussians + U[-0.05, 0.05] noise) solved to full
+    cancellation or 1000 iterations (Alg. 1; signal iff persistence > 0.1 range)."""
+    f = fields.workload("gauss8_32", seed)
+    t = time.time()
+    g, r = oracle.simplify(f, threshold=0.1, j_max=1000)
+    out = {"workload": "gauss8_32", "seed": seed, "j_max": 1000, "stop": "full cancellation",
+           "cite": "Alg. 1, Sec. 4.1, Sec. 4.3", "field_sha256": sha(f), "g_sha256": sha(g),
+           "iterations": r.iterations, "cancelled": r.cancelled, "loss": r.loss,
+           "max_nonsignal_pers_rel": r.max_nonsignal_pers / r.range,
+           "oracle_s": round(time.time() - t, 1)}
+    _write(f"gauss8_32_seed{seed}.json", out)
+
+
+def filament64():
+    """The filament generator at 64^3 under its signal rule (only saddle-saddle
+    pairs below 0.1 range are non-signal), 4 iterations: its reduced
+    assignment problems are larger than 1000 points + targets."""
+    f = fields.filament_field((64, 64, 64), 0)
+    t = time.time()
+    g, r = oracle.simplify(f, threshold=0.1, nonsignal_dims=(1,), ties_signal=1, j_max=4)
+    out = {"workload": "filament", "dims": [64, 64, 64], "seed": 0, "j_max": 4,
+           "signal": "non-signal = saddle-saddle pairs with persistence < 0.1 range",
+           "cite": "Alg. 1, Eq. (1), Sec. 4.3", "field_sha256": sha(f), "g_sha256": sha(g),
+           "iterations": r.iterations, "loss": r.loss, "n_reduced_last": r.n_reduced,
+           "n_still_last": r.n_still, "oracle_s": round(time.time() - t, 1)}
+    _write("filament64_seed0.json", out)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1]
+    if what == "filament256":
+        filament256()
+    elif what == "gauss32":
+        for s in sys.argv[2:]:
+            gauss32(int(s))
+    elif what == "filament64":
+        filament64()
+    else:
+        raise SystemExit(__doc__)

@@ -415,3 +415,86 @@ def test_deterministic(gpu):
     a = gpu.pairs(_t(f))
     b = gpu.pairs(_t(f))
     _same_pairs(a, b)
+
+
+def _two_dips():
+    from tests.test_oracle_still import _two_dips as make
+    return make()
+
+
+@pytest.mark.parametrize("keep", [(), (0,), (1,), (0, 1)])
+def test_list_mode_parity(gpu, orc, keep):
+    """Explicit signal lists (Sec. 3): the listed pairs are held, the others
+    cancelled; same iterations and bit-identical g as the oracle."""
+    f, dips = _two_dips()
+    D = orc.diagram(f)
+    fin = D[D["essential"] == 0]
+    by_v = {int(p["v_birth"]): p for p in fin}
+    lst = np.array([by_v[dips[k][0]] for k in keep], dtype=orc.PAIR_DTYPE)
+    g, rep = gpu.simplify(_t(f), signal_pairs=lst)
+    go, ro = orc.simplify(f, signal_pairs=lst)
+    assert (rep.iterations, rep.n_targets) == (ro.iterations, ro.n_targets)
+    assert np.array_equal(g.cpu().numpy(), go)
+
+
+def test_list_equal_to_threshold_set(gpu, orc):
+    """The list of the threshold rule's signal pairs gives the threshold
+    solve, on the GPU as in the oracle; dropping the most persistent listed
+    pair from the list changes the solve exactly as in the oracle."""
+    f = fields.gaussian_mixture((12, 11, 10), 8, 0.05, 0)
+    D = orc.diagram(f)
+    rng = float(f.max()) - float(f.min())
+    thr = float(np.float32(0.1)) * rng
+    pers = D["death"].astype(np.float64) - D["birth"].astype(np.float64)
+    lst = D[(D["essential"] == 0) & (pers > thr)]
+    g1, r1 = gpu.simplify(_t(f), threshold=0.1, j_max=30)
+    g2, r2 = gpu.simplify(_t(f), signal_pairs=lst, j_max=30)
+    assert r1.iterations == r2.iterations
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+    short = np.delete(lst, int(np.argmax(lst["death"] - lst["birth"])))
+    g3, r3 = gpu.simplify(_t(f), signal_pairs=short, j_max=30)
+    go, ro = orc.simplify(f, signal_pairs=short, j_max=30)
+    assert r3.iterations == ro.iterations and r3.n_targets == len(short) + 1
+    assert np.array_equal(g3.cpu().numpy(), go)
+
+
+@pytest.mark.parametrize("kw", [dict(threshold=0.1), dict(threshold=0.1, nonsignal_dims=(1,),
+                                                           ties_signal=1)])
+def test_signal_mask(gpu, orc, kw):
+    """The signal-vertex mask marks exactly the birth and death vertices of
+    the pairs of D(f) that the threshold rule keeps (Sec. 3)."""
+    f = fields.gaussian_mixture((20, 18, 16), 8, 0.05, 4)
+    m, cnt = gpu.signal_mask(_t(f), **kw)
+    D = orc.diagram(f)
+    rng = float(f.max()) - float(f.min())
+    thr = float(np.float32(kw["threshold"])) * rng
+    pers = D["death"].astype(np.float64) - D["birth"].astype(np.float64)
+    below = (pers < thr) | ((pers == thr) & (kw.get("ties_signal", 0) == 0))
+    masked = np.isin(D["dim"], list(kw.get("nonsignal_dims", (0, 1, 2))))
+    keep = (D["essential"] == 1) | ~(masked & below)
+    want = np.zeros(f.size, np.float32)
+    want[D["v_birth"][keep]] = 1.0
+    want[D["v_death"][keep]] = 1.0
+    assert cnt == int(keep.sum())
+    assert np.array_equal(m.cpu().numpy().ravel(), want)
+    # list mode: the mask of the list's own pairs
+    lst = D[keep & (D["essential"] == 0)][:3]
+    ml, cl = gpu.signal_mask(f, signal_pairs=lst)
+    want = np.zeros(f.size, np.float32)
+    for p in list(lst) + list(D[D["essential"] == 1]):
+        want[p["v_birth"]] = want[p["v_death"]] = 1.0
+    assert cl == 4 and np.array_equal(ml.ravel(), want)
+
+
+def test_overlapping_buffers_rejected(gpu):
+    import torch
+    f = _t(fields.gaussian_mixture((8, 8, 8), 8, 0.05, 0))
+    buf = torch.empty(2 * f.numel(), dtype=torch.float32, device=f.device)
+    buf[: f.numel()] = f.ravel()
+    src = buf[: f.numel()].view(f.shape)
+    dst = buf[f.numel() // 2: f.numel() // 2 + f.numel()].view(f.shape)
+    with pytest.raises(gpu.TopsimpError) as e:
+        gpu.simplify(src, out=dst)
+    assert e.value.code == -1
+    g, _ = gpu.simplify(src, out=buf[f.numel():].view(f.shape), j_max=2)
+    assert g.data_ptr() == buf[f.numel():].data_ptr()
