@@ -94,9 +94,8 @@ typedef struct {
   float cancel_tol_rel;    /* 1e-6 */
   float loss_ratio_s;      /* 0.01 */
   int32_t inputs_on_device; /* f and g are device pointers */
-  float assign_precision;  /* 0: the reduced assignment is exact up to 1000 points +
-                              targets and an auction within (points + targets) *
-                              1e-9 * W above (the default).  > 0: an auction for
+  float assign_precision;  /* 0: the reduced assignment is exact (the default; see
+                              ts_assign).  > 0: an auction for
                               every size, stopped once its W2^2 total is within
                               (1 + assign_precision)^2 of a dual lower bound; the
                               paper runs 0.01 (Sec. 5).  Results then can differ
@@ -270,18 +269,20 @@ int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_devi
  * match[i] receives the target index or -1 (diagonal); *cost the total
  * (matched squared distances + diagonal costs of everything else).
  * A point and a target with c(p,q) >= diag(p) + diag(q) are never matched.
- * After exact reductions, a problem of at most 1000 points + targets is
- * solved exactly (successive shortest paths); a larger one by an
- * epsilon-scaled auction whose total is within (points + targets) * 1e-9 * W
- * of the optimum, W = max diag(p) + max diag(q).
+ * The result is the exact optimum: after exact reductions, a problem of at
+ * most 1000 points + targets is solved by successive shortest paths; a
+ * larger one by an epsilon-scaled auction (final eps 1e-10 * W, W = max
+ * diag(p) + max diag(q)) whose result is then proved optimal by
+ * complementary slackness with exact duals, trading along cost-reducing
+ * cycles where it is not.  TS_ERR_INTERNAL if no certificate is reached.
  * Needs no context and no GPU. */
 int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
               const double* qd, int32_t* match, double* cost);
 
 /* The same problem by the epsilon-scaled auction alone, as ts_simplify runs it
  * with assign_precision = rel_precision (Sec. 5 uses 0.01): the returned total
- * is at most (1 + rel_precision)^2 times the optimum.  rel_precision = 0 runs
- * the auction to its final epsilon 1e-9 * W.  Host arrays as in ts_assign;
+ * is at most (1 + rel_precision)^2 times the optimum.  rel_precision = 0 gives
+ * the exact assignment of ts_assign.  Host arrays as in ts_assign;
  * TS_ERR_ARG for a negative or non-finite rel_precision.  Needs no context
  * and no GPU. */
 int ts_assign_auction(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt,

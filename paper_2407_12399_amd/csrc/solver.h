@@ -35,15 +35,19 @@ double assign_exact(const std::vector<double>& pb, const std::vector<double>& pd
                     const std::vector<double>& qb, const std::vector<double>& qd,
                     std::vector<int>* match);
 
-// Near-optimal assignment of the same problem by an epsilon-scaled auction;
-// the total cost is within (points + targets) * eps_rel * W of the optimum,
-// W = max diag(p) + max diag(q).  With gap_rel > 0 it stops after the first
-// phase whose total is within (1 + gap_rel)^2 of the dual lower bound.
+// The same problem by an epsilon-scaled auction to eps_rel * W, W = max
+// diag(p) + max diag(q).  With gap_rel == 0 its result is then proved optimal
+// (complementary slackness with exact duals, trading along cost-reducing
+// cycles where it is not), so the return is the exact optimum; if the
+// certificate's work budget runs out it throws CertificateMissing.  With
+// gap_rel > 0 it stops after the first phase whose total is within
+// (1 + gap_rel)^2 of the dual lower bound, with no certificate.
 double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
                       std::vector<int>* match, double eps_rel, double gap_rel = 0.0);
 
-// The solver's choice: exact up to a problem size, the auction above; with
+// The solver's choice: exact reductions, then successive shortest paths up
+// to a problem size and the certified auction above it (both exact); with
 // gap_rel > 0 the auction with that stopping gap for every size.
 double assign_reduced(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,

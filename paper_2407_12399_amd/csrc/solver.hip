@@ -9,7 +9,8 @@
 //   3. still pairs (Sec. 4.3): points with the same (dim, v_birth, v_death)
 //      as a point of the previous diagram keep its assignment; the others are
 //      assigned exactly, per dimension, to the targets no still point holds
-//      (host, sparse shortest augmenting paths).
+//      (host: shortest augmenting paths for small problems, an auction with
+//      an optimality certificate for large ones).
 #include <algorithm>
 #include <array>
 #include <atomic>
@@ -680,6 +681,28 @@ struct KDTree {
     hint[1] = j2;
     return bj;
   }
+  // Every unmasked j with |p - q_j|^2 - s_j < thr, appended to out (nodes
+  // whose bound d2box - smax is already >= thr are skipped).
+  void collect(double px, double py, double thr, std::vector<int>* out) const {
+    if (nodes.empty() || nodes[0].smax == NEG) return;
+    int sn[64];
+    int top_n = 0;
+    sn[top_n++] = 0;
+    while (top_n > 0) {
+      const Node& nd = nodes[sn[--top_n]];
+      if (nd.smax == NEG || !(d2box(nd, px, py) - nd.smax < thr)) continue;
+      if (nd.left < 0) {
+        for (int t = nd.begin; t < nd.end; ++t) {
+          if (lm[t]) continue;
+          const double dx = lx[t] - px, dy = ly[t] - py;
+          if ((dx * dx + dy * dy) - ls[t] < thr) out->push_back(idx[t]);
+        }
+      } else {
+        sn[top_n++] = nd.left;
+        sn[top_n++] = nd.right;
+      }
+    }
+  }
   // argmin over unmasked j of |p - q_j|^2 - s_j; ties to the lower index.
   // seed (or -1): a target counted before the descent, so that the search
   // starts from its value (same answer).
@@ -760,6 +783,222 @@ struct RisingMinHeap {
   }
 };
 
+// Optimality certificate for an assignment of the square augmented problem
+// (min-cost form).  Persons are the points 0..m-1 and one diagonal copy per
+// target (m + j); objects are the targets 0..k-1 and one diagonal copy per
+// point (k + i).  Point i may take any target j at c(p_i, q_j) or its own
+// copy at diag(p_i); target copy m + j may take target j at diag(q_j) or any
+// point copy at 0.  With object prices p, an assignment is optimal when every
+// person x holding o_x attains the minimum over its objects of cost(x, o) +
+// p_o (complementary slackness with the feasible duals u_x = that minimum,
+// v_o = -p_o).  An epsilon-scaled auction leaves every person within eps of
+// its minimum.  The check lowers the price of a person's object until the
+// person attains its minimum, p_o = min - cost(x, o): a label-correcting
+// shortest-path computation over the fixed assignment, in which the object
+// whose price fell can become the strict minimum of other persons, who are
+// checked in turn.  When no person is left above its minimum the assignment
+// is optimal.  If it is not, prices keep falling around a cycle of persons
+// who would all gain by trading objects: every lowering records the object
+// that set the new price, and a cycle among those records has negative total
+// cost (Bellman-Ford predecessor graphs), so the persons on it trade along
+// it, which lowers the total cost, and the checks go on.  A person counts as
+// above its minimum by more than 4 ulps of the values compared only.
+struct Certificate {
+  int64_t lowerings = 0, trades = 0;
+  bool ok = false;
+};
+
+struct CertificateMissing {};
+
+Certificate certify_assignment(const std::vector<double>& pb, const std::vector<double>& pd,
+                               const std::vector<double>& qb, const std::vector<double>& qd,
+                               const std::vector<double>& dp, const std::vector<double>& dq,
+                               std::vector<double>* price_io, std::vector<int>* holds_io) {
+  const int m = int(pb.size()), k = int(qb.size());
+  const int NP = m + k;
+  std::vector<double>& price = *price_io;
+  std::vector<int>& holds = *holds_io;
+  std::vector<int> owner(k + m, -1);
+  for (int x = 0; x < NP; ++x) owner[holds[x]] = x;
+  const double INF = std::numeric_limits<double>::infinity();
+  auto cost = [&](int x, int o) {
+    if (x < m) return o < k ? pair_cost(pb[x], pd[x], qb[o], qd[o]) : (o == k + x ? dp[x] : INF);
+    const int j = x - m;
+    return o < k ? (o == j ? dq[j] : INF) : 0.0;
+  };
+  auto slack_tol = [](double a, double b) {
+    return 4.0 * std::numeric_limits<double>::epsilon() * std::max(std::fabs(a), std::fabs(b)) +
+           1e-300;
+  };
+  std::vector<double> lam(NP);
+  for (int x = 0; x < NP; ++x) lam[x] = cost(x, holds[x]) + price[holds[x]];
+  double scale = 0;  // cost scale: largest diagonal costs
+  for (double v : dp) scale = std::max(scale, v);
+  for (double v : dq) scale = std::max(scale, v);
+  // targets by (c + price): s_j = -p_j
+  KDTree tt;
+  tt.build(qb.data(), qd.data(), k);
+  {
+    std::vector<double> sc(k);
+    for (int j = 0; j < k; ++j) sc[j] = -price[j];
+    tt.set_all(sc);
+  }
+  // points by their current value lam_i, for the reverse question "which
+  // points now prefer target j"
+  KDTree pt;
+  pt.build(pb.data(), pd.data(), m);
+  pt.set_all(std::vector<double>(lam.begin(), lam.begin() + m));
+  // lowest point-copy price (lazy min-heap) and target copies by lam (lazy max-heap)
+  typedef std::pair<double, int> DI;
+  std::priority_queue<DI, std::vector<DI>, std::greater<DI>> cheap;
+  for (int i = 0; i < m; ++i) cheap.push({price[k + i], i});
+  auto min_copy = [&](int* who) {
+    while (!cheap.empty() && cheap.top().first != price[k + cheap.top().second]) cheap.pop();
+    if (cheap.empty()) {
+      *who = -1;
+      return INF;
+    }
+    *who = k + cheap.top().second;
+    return cheap.top().first;
+  };
+  std::priority_queue<DI> tcl;
+  for (int j = 0; j < k; ++j) tcl.push({lam[m + j], m + j});
+  std::vector<int> queue;
+  std::vector<char> inq(NP, 1);
+  queue.reserve(NP);
+  for (int x = 0; x < NP; ++x) queue.push_back(x);
+  std::vector<int> from(k + m, -1), count(k + m, 0), seen(k + m, -1);
+  std::vector<int> hits;
+  std::vector<int> hint(2 * size_t(std::max(m, 1)), -1);
+  Certificate cert;
+  const int64_t budget = int64_t(64) * NP + 100000;
+  int walk = 0;
+  auto push = [&](int y) {
+    if (!inq[y]) {
+      inq[y] = 1;
+      queue.push_back(y);
+    }
+  };
+  // the exact minimum of person x and the object attaining it
+  auto minimum = [&](int x, int* arg) {
+    if (x < m) {
+      double v1, v2;
+      int j = tt.best2(pb[x], pd[x], &v1, &v2, &hint[2 * size_t(x)]);
+      double best = INF;
+      *arg = -1;
+      if (j >= 0) {
+        best = v1;
+        *arg = j;
+      }
+      const double vd = dp[x] + price[k + x];
+      if (vd < best) {
+        best = vd;
+        *arg = k + x;
+      }
+      return best;
+    }
+    const int j = x - m;
+    int c;
+    const double pc = min_copy(&c);
+    const double vt = dq[j] + price[j];
+    if (pc < vt) {
+      *arg = c;
+      return pc;
+    }
+    *arg = j;
+    return vt;
+  };
+  auto set_lam = [&](int x) {
+    lam[x] = cost(x, holds[x]) + price[holds[x]];
+    if (x < m) pt.update(x, lam[x], false);
+    else tcl.push({lam[x], x});
+  };
+  // objects whose price fell: who else may now prefer them
+  auto after_lowering = [&](int o) {
+    if (o < k) {
+      tt.update(o, -price[o], false);
+      hits.clear();
+      // superset by a small margin; every hit is checked exactly
+      const double thr = -price[o] + 1e-12 * (std::fabs(price[o]) + scale);
+      pt.collect(qb[o], qd[o], thr, &hits);
+      for (int i : hits) push(i);
+      push(m + o);
+    } else {
+      const int i = o - k;
+      cheap.push({price[o], i});
+      push(i);
+      while (!tcl.empty()) {
+        const DI top = tcl.top();
+        if (top.first != lam[top.second] || inq[top.second]) {
+          tcl.pop();
+          continue;
+        }
+        if (!(top.first > price[o])) break;
+        tcl.pop();
+        push(top.second);
+      }
+    }
+  };
+  size_t head = 0;
+  while (head < queue.size()) {
+    const int x = queue[head++];
+    inq[x] = 0;
+    if (head > (size_t(1) << 22) && head * 2 > queue.size()) {  // compact the queue
+      queue.erase(queue.begin(), queue.begin() + head);
+      head = 0;
+    }
+    int arg;
+    const double mu = minimum(x, &arg);
+    if (x >= m) tcl.push({lam[x], x});  // keep it findable by lam
+    if (!(mu < lam[x] - slack_tol(mu, lam[x]))) continue;
+    const int o = holds[x];
+    if (arg == o) continue;  // cannot happen with exact minima; be safe
+    price[o] = mu - cost(x, o);
+    from[o] = arg;
+    set_lam(x);
+    after_lowering(o);
+    if (++cert.lowerings > budget) return cert;
+    if (++count[o] % 8 != 0) continue;
+    // look for a cycle among the recorded objects, starting from o
+    ++walk;
+    int cur = o;
+    while (cur >= 0 && seen[cur] != walk) {
+      seen[cur] = walk;
+      cur = from[cur];
+    }
+    if (cur < 0) continue;
+    // cur lies on a cycle: trade along it if it really saves cost
+    std::vector<int> cyc;
+    int c = cur;
+    do {
+      cyc.push_back(c);
+      c = from[c];
+    } while (c != cur && int(cyc.size()) <= k + m);
+    if (c != cur) continue;
+    double gain = 0;
+    for (size_t t = 0; t < cyc.size(); ++t) {
+      const int ob = cyc[t], nb = cyc[(t + 1) % cyc.size()];
+      gain += cost(owner[ob], nb) - cost(owner[ob], ob);
+    }
+    if (!(gain < 0) || !std::isfinite(gain)) continue;
+    std::vector<int> who(cyc.size());
+    for (size_t t = 0; t < cyc.size(); ++t) who[t] = owner[cyc[t]];
+    for (size_t t = 0; t < cyc.size(); ++t) {
+      const int nb = cyc[(t + 1) % cyc.size()];
+      holds[who[t]] = nb;
+      owner[nb] = who[t];
+    }
+    for (size_t t = 0; t < cyc.size(); ++t) {
+      from[cyc[t]] = -1;
+      set_lam(who[t]);
+      push(who[t]);
+    }
+    ++cert.trades;
+  }
+  cert.ok = true;
+  return cert;
+}
+
 }  // namespace
 
 // Forward auction with epsilon scaling (Bertsekas) on the square augmented
@@ -767,9 +1006,10 @@ struct RisingMinHeap {
 // are the targets and one diagonal copy per point; a point values target j
 // at -c(p,q_j) and its own diagonal copy at -diag(p); the diagonal copy of
 // target j values target j at -diag(q_j) and every point's diagonal copy at
-// 0.  Bids use the KD-tree (best and second-best target) and a lazy heap of
-// the diagonal copies' prices.  The final assignment is within
-// (m + k) * eps_final of the optimum.
+// 0.  Bids use the KD-tree (best and second-best target) and a rising-price
+// heap of the diagonal copies' prices.  The final assignment is within
+// (m + k) * eps_final of the optimum; in exact mode (gap_rel == 0) it is then
+// certified optimal (certify_assignment).
 double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
                       std::vector<int>* match, double eps_rel, double gap_rel) {
@@ -891,6 +1131,17 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       if (lower > 0 && primal <= (1 + gap_rel) * (1 + gap_rel) * lower) break;
     }
     eps = std::max(eps / 4.0, eps_final);  // a factor of 4 needs the fewest bids on noisy diagrams
+  }
+  if (gap_rel == 0) {
+    // exact mode: prove the assignment optimal, trading along cycles where
+    // it is not (the auction alone is only within (m + k) * eps)
+    const double tc = now_s();
+    const Certificate c = certify_assignment(pb, pd, qb, qd, dp, dq, &price, &holds);
+    if (std::getenv("TS_TRACE"))
+      std::fprintf(stderr, "[topsimp] certificate %s: %lld lowerings, %lld trades, %.3f s\n",
+                   c.ok ? "ok" : "not reached", (long long)c.lowerings, (long long)c.trades,
+                   now_s() - tc);
+    if (!c.ok) throw CertificateMissing();
   }
   double total = 0;
   std::vector<char> used(k, 0);
@@ -1083,9 +1334,10 @@ std::vector<int> has_candidate(const KDTree& tree, const std::vector<double>& ab
 
 }  // namespace
 
-// The solver's assignment: exact reductions first, then the exact method up
-// to a problem size (TS_EXACT_MAX, default 1000 points + targets) and the
-// auction above it.  Reductions, each of which keeps every optimum:
+// The solver's assignment: exact reductions first, then successive shortest
+// paths up to a problem size (TS_EXACT_MAX, default 1000 points + targets)
+// and the certified auction above it.  Reductions, each of which keeps every
+// optimum:
 //  (a) a point (target) with no target (point) at a positive saving
 //      w = diag(p) + diag(q) - c(p,q) goes to the diagonal;
 //  (b) with k targets left, a target is matched in an optimum to one of its
@@ -1165,7 +1417,23 @@ double assign_reduced(const std::vector<double>& pb, const std::vector<double>& 
   if (int64_t(rows.size() + cols.size()) <= limit) {
     assign_exact(rb, rd, cb, cd, &sub);
   } else {
-    assign_auction(rb, rd, cb, cd, &sub, 1e-9, gap_rel);
+    // exact mode: the auction to eps = 1e-10 W, then the optimality
+    // certificate; if the certificate's work budget runs out (many cycles
+    // left), once more from a 100 times smaller eps
+    const double eps0 = std::getenv("TS_AUCTION_EPS") ? std::atof(std::getenv("TS_AUCTION_EPS")) : 1e-10;
+    if (gap_rel > 0) {
+      assign_auction(rb, rd, cb, cd, &sub, eps0, gap_rel);
+    } else {
+      try {
+        assign_auction(rb, rd, cb, cd, &sub, eps0, 0.0);
+      } catch (const CertificateMissing&) {
+        try {
+          assign_auction(rb, rd, cb, cd, &sub, eps0 * 1e-2, 0.0);
+        } catch (const CertificateMissing&) {
+          throw Error(TS_ERR_INTERNAL, "assignment: no optimality certificate");
+        }
+      }
+    }
   }
   std::vector<char> used(k, 0);
   for (size_t t = 0; t < rows.size(); ++t)

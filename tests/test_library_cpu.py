@@ -93,22 +93,40 @@ def test_assignment_reductions_match_oracle(ts, orc, seed, m, k):
 
 
 @pytest.mark.parametrize("seed,dense", [(0, True), (1, False)])
-def test_large_assignment_within_auction_bound(ts, orc, seed, dense):
-    """Above 1000 points + targets the library runs the epsilon-scaled
-    auction: its total is within (m + k) * 1e-9 * W of the oracle's exact
-    optimum, and the returned matching realises the returned total."""
+def test_large_assignment_matches_oracle(ts, orc, seed, dense):
+    """Above 1000 points + targets the library runs an epsilon-scaled auction
+    and then proves its result optimal (trading along cycles where it is
+    not): the matching is the oracle's exact optimum, match by match."""
     rng = np.random.default_rng(500 + seed)
     pb, pd, qb, qd = _instance(rng, 700, 650, dense)
     mt, ct = ts.assign(pb, pd, qb, qd)
     mo, co = orc.assign(pb, pd, qb, qd)
-    W = ((pd - pb) ** 2 / 2).max() + ((qd - qb) ** 2 / 2).max()
-    assert abs(ct - co) <= (700 + 650) * 1e-9 * W
-    used = mt[mt >= 0]
-    assert len(set(used.tolist())) == len(used)
-    real = sum((pb[i] - qb[t]) ** 2 + (pd[i] - qd[t]) ** 2 if t >= 0 else (pd[i] - pb[i]) ** 2 / 2
-               for i, t in enumerate(mt))
-    real += sum((qd[j] - qb[j]) ** 2 / 2 for j in range(len(qb)) if j not in set(used.tolist()))
-    assert real == pytest.approx(ct, rel=1e-12)
+    assert np.array_equal(mt, mo)
+    assert ct == pytest.approx(co, rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def dense_2200(orc):
+    """A dense 2200 x 2100 instance (noise pairs near the diagonal, every
+    point with hundreds of targets at a positive saving) and the oracle's
+    exact optimum (dense Hungarian)."""
+    rng = np.random.default_rng(900)
+    inst = _instance(rng, 2200, 2100, True)
+    return inst, orc.assign(*inst)
+
+
+@pytest.mark.parametrize("eps", [None, "1e-6", "1e-4"])
+def test_certified_auction_matches_oracle_2200(ts, dense_2200, monkeypatch, eps):
+    """Match by match on a dense 2200 + 2100 instance, also when the auction
+    stops early (final eps 1e-6 W or 1e-4 W instead of 1e-10 W), so that
+    its result is not optimal and the certificate has to trade along
+    cycles (or run out of budget and restart from a smaller eps)."""
+    if eps is not None:
+        monkeypatch.setenv("TS_AUCTION_EPS", eps)
+    (pb, pd, qb, qd), (mo, co) = dense_2200
+    mt, ct = ts.assign(pb, pd, qb, qd)
+    assert np.array_equal(mt, mo)
+    assert ct == pytest.approx(co, rel=1e-12)
 
 
 @pytest.mark.parametrize("precision", [0.01, 0.1])
@@ -127,10 +145,9 @@ def test_auction_relative_precision(ts, orc, precision):
                for i, t in enumerate(mt))
     real += sum((qd[j] - qb[j]) ** 2 / 2 for j in range(len(qb)) if j not in set(used.tolist()))
     assert real == pytest.approx(ct, rel=1e-12)
-    # precision 0 runs to the final epsilon
+    # precision 0 is the exact (certified) assignment
     _, c0 = ts.assign_auction(pb, pd, qb, qd, 0.0)
-    W = ((pd - pb) ** 2 / 2).max() + ((qd - qb) ** 2 / 2).max()
-    assert abs(c0 - co) <= (300 + 280) * 1e-9 * W
+    assert c0 == pytest.approx(co, rel=1e-12)
     with pytest.raises(ts.TopsimpError):
         ts.assign_auction(pb, pd, qb, qd, -1.0)
 
