@@ -11,12 +11,22 @@ iterations from the input field with the field already resident in HBM
 (one ts_simplify call with j_max = steps; the initial diagram is inside
 the timed region).  value = vertices * steps / time (Mverts/s).
 
-Also reported: the persistence-map throughput (vertices / device time of
-the persistence kernels per map), the per-stage device times (HIP events on
-the library's stream), the roofline of the dominant kernel, and the CPU
-oracle timed on a bounded crop of the same field.
+The metric's two halves are reported next to it:
+  - the solve towards full non-signal cancellation (Alg. 1 with the
+    1e-6 * range stop rule), capped at --cancel-cap iterations: time to
+    cancellation, or, when the cap is hit, the iterations and the largest
+    non-signal persistence left; from the same run's per-iteration trace,
+    the time to the paper's stop rule L <= 0.01 * L0 (the trajectory does
+    not depend on the stop rule, so this is the time a solve with that rule
+    takes);
+  - the persistence-map throughput (vertices / device time of the
+    persistence kernels per map), with per-stage device times (HIP events on
+    the library's stream) and the HBM roofline of the lower-star gradient
+    kernel at the algorithmic 20 bytes per vertex.
+Also: the 32^3 and 128^3 Gaussian workloads, the batch of 64 uneven fields,
+and the CPU oracle on the filament generator at 64^3 (full extent).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cancel] [--paper-stop] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cancel-cap J] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -34,14 +44,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "filament_256"
 
-# Algorithmic HBM bytes per vertex of each persistence-map stage (per launch
-# = per map): what the stage must read and write at minimum.
-ALGO_BYTES_PER_VERTEX = {
-    "K1 order keys": 4 + 8,      # read f, write (key, id)
-    "K1 radix sort": 8 + 8,      # read (key, id), write sorted (key, id)
-    "K2 rank": 4 + 8,            # read sorted id, write rank and order
-    "K3 gradient": 4 + 16 + 4,   # read rank, write 16-byte code and descending neighbour
-}
+# Algorithmic HBM bytes per vertex (per map) of the streaming steps, as the
+# method needs them: the vertex order reads f and writes order and rank
+# (4 + 4 + 4); the lower-star gradient reads ranks and writes a 16-byte
+# gradient code (4 + 16).  The implementation's own intermediate arrays
+# (sort keys, the descent pointer) are not counted.
+ORDER_BYTES_PER_VERTEX = 12
+K3_BYTES_PER_VERTEX = 20
+ORDER_STAGES = ("K1 order keys", "K1 radix sort", "K2 rank")
 
 
 # HBM traffic of one k_gradient launch at 256^3, from rocprofv3 FETCH_SIZE and
@@ -80,15 +90,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dims", type=int, nargs=3, default=None)
-    ap.add_argument("--cancel", action="store_true",
-                    help="also run the solver to full cancellation (or j_max)")
-    ap.add_argument("--paper-stop", action="store_true",
-                    help="also time the solve to the paper's stop rule L <= 0.01 L0")
-    ap.add_argument("--j-max", type=int, default=1000)
+    ap.add_argument("--cancel-cap", type=int, default=60,
+                    help="iteration cap of the solve towards full cancellation (0: skip it)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-paper-auction", action="store_true",
-                    help="skip the extra run with the paper's auction precision")
-    ap.add_argument("--cpu-crop", type=int, default=48)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 32^3 and 128^3 Gaussian workloads")
+    ap.add_argument("--paper-auction", action="store_true",
+                    help="also run the timed steps with the paper's auction precision 0.01")
+    ap.add_argument("--cpu-dims", type=int, default=64,
+                    help="grid of the oracle's sample (the filament generator, full extent)")
     ap.add_argument("--diag-reps", type=int, default=3)
     ap.add_argument("--diagram-only", action="store_true",
                     help="only run the persistence map --diag-reps times (for profilers)")
@@ -110,25 +120,99 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(f, crop, signal):
-    """The oracle on a crop of the field: per-iteration time of its solver
-    (two iterations minus the initial diagram), single-threaded."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(dims, signal):
+    """The oracle on the filament generator at dims^3 (the full extent of the
+    workload's geometry at a lower resolution), seed 0:
+      - value: one solver iteration, timed as the GPU value is
+        (vertices x iterations / time of a solve with j_max = 1, the initial
+        diagram included), single-threaded;
+      - the persistence map (one diagram), single-threaded and with the
+        OpenMP build (gradient and vertex-order loops on every thread)."""
     import oracle
+    from paper_2407_12399_amd import fields
     oracle.build()
-    c = np.ascontiguousarray(f[:crop, :crop, :crop])
+    f = fields.filament_field((dims, dims, dims), 0)
     thr, mask, ties = signal
-    dims = [d for d in range(3) if (mask >> d) & 1]
+    nd = [d for d in range(3) if (mask >> d) & 1]
     t0 = time.perf_counter()
-    oracle.simplify(c, threshold=thr, nonsignal_dims=dims, ties_signal=ties, j_max=0)
-    t1 = time.perf_counter()
-    _, rep = oracle.simplify(c, threshold=thr, nonsignal_dims=dims, ties_signal=ties, j_max=2)
-    t2 = time.perf_counter()
-    iters = max(rep.iterations, 1)
-    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / iters
-    return {"value": c.size / per_iter / 1e6, "unit": "Mverts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{crop}^3 crop of the same field, {iters} solver iterations "
-                      f"(time of 2 iterations minus the initial diagram)",
-            "persistence_map_mverts_s": c.size / (t1 - t0) / 1e6}
+    oracle.diagram(f)
+    t_map = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    D, threads = oracle.diagram_omp(f)
+    t_map_omp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, rep = oracle.simplify(f, threshold=thr, nonsignal_dims=nd, ties_signal=ties, j_max=1)
+    t_solve = time.perf_counter() - t0
+    n = f.size
+    return {"value": n * rep.iterations / t_solve / 1e6, "unit": "Mverts/s", "cores": 1,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "sample": f"filament generator at {dims}^3 (full extent, seed 0): one solve with "
+                      f"j_max = 1 ({t_solve:.1f} s), as the GPU value is timed",
+            "persistence_map_mverts_s": n / t_map / 1e6,
+            "persistence_map_s": t_map,
+            "persistence_map_omp": {"mverts_s": n / t_map_omp / 1e6, "s": t_map_omp,
+                                    "cores": threads,
+                                    "parallel_parts": "vertex order and lower-star gradient"},
+            "diagram_points": int(len(D))}
+
+
+def trace_stop(tr, s=0.01):
+    """(iterations, seconds) to the first iteration whose loss is at most s
+    times the initial loss, from a solver trace, or (None, None)."""
+    for j in range(1, len(tr)):
+        if tr[j, 1] <= s * tr[0, 1]:
+            return j, float(tr[j, 0])
+    return None, None
+
+
+def config_runs(ts, fields, torch):
+    """The 32^3 workload solved to full cancellation (j_max 1000; the oracle
+    parity case) and the 128^3 workload's map and solve to the paper's stop
+    rule (cap 100 iterations)."""
+    out = {}
+    f = torch.from_numpy(fields.workload("gauss8_32", 0)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = ts.simplify(f, threshold=0.1, j_max=1000, trace=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    js, tsp = trace_stop(r.trace)
+    out["gauss8_32"] = {"dims": [32, 32, 32], "seed": 0, "wall_s": dt, "iterations": r.iterations,
+                        "cancelled": r.cancelled, "j_max": 1000,
+                        "max_nonsignal_pers_rel": r.max_nonsignal_pers / r.range,
+                        "paper_stop_iterations": js, "paper_stop_s": tsp}
+    f = torch.from_numpy(fields.workload("gauss64_128", 0)).cuda()
+    for _ in range(2):
+        ts.diagram(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts.diagram(f)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev = sum(ts.stage_times().values())
+    t0 = time.perf_counter()
+    _, r = ts.simplify(f, threshold=0.1, j_max=100, stop_mode=1, trace=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = f.numel()
+    out["gauss64_128"] = {"dims": [128, 128, 128], "seed": 0,
+                          "persistence_map_ms": dev, "persistence_map_wall_ms": wall * 1e3,
+                          "persistence_map_mverts_s": n / (dev * 1e-3) / 1e6,
+                          "paper_stop": {"wall_s": dt, "iterations": r.iterations,
+                                         "stopped": r.cancelled, "j_max": 100,
+                                         "solver_mverts_s": n * r.iterations / dt / 1e6}}
+    return out
 
 
 def batch_run(ts, fields, torch, args):
@@ -340,36 +424,32 @@ def main():
     solver_stage = ts.stage_times()
     value = n * steps / dt / 1e6 if steps > 0 else 0.0
 
-    # dominant persistence kernel and its roofline
-    dom = max((k for k in stage_ms if k in ALGO_BYTES_PER_VERTEX), key=lambda k: stage_ms[k])
-    algo_bytes = ALGO_BYTES_PER_VERTEX[dom] * n
-    achieved = algo_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    # the lower-star gradient kernel against the HBM roofline
+    k3_ms = stage_ms["K3 gradient"]
+    algo_bytes = K3_BYTES_PER_VERTEX * n
+    achieved = algo_bytes / (k3_ms * 1e-3) / 1e9
     traffic = None
     c = K3_COUNTERS
-    if dom == "K3 gradient" and tuple(dims) == c["dims"] and kernel_source_sha1() == c["source_sha1"]:
+    if tuple(dims) == c["dims"] and kernel_source_sha1() == c["source_sha1"]:
         traffic = (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": stage_ms[dom]}
-    # algorithmic HBM rate of every streaming stage (order and gradient)
-    stage_hbm = {k: {"algo_bytes_per_vertex": ALGO_BYTES_PER_VERTEX[k], "ms": stage_ms[k],
-                     "achieved_gbs": ALGO_BYTES_PER_VERTEX[k] * n / (stage_ms[k] * 1e-3) / 1e9,
-                     "frac": ALGO_BYTES_PER_VERTEX[k] * n / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-                 for k in ALGO_BYTES_PER_VERTEX if stage_ms.get(k)}
-    order_keys = [k for k in ("K1 order keys", "K1 radix sort", "K2 rank") if stage_ms.get(k)]
-    order_ms = sum(stage_ms[k] for k in order_keys)
-    order_bytes = sum(ALGO_BYTES_PER_VERTEX[k] for k in order_keys) * n
-    stage_hbm["vertex order (K1 + K2)"] = {
-        "algo_bytes_per_vertex": order_bytes / n, "ms": order_ms,
-        "achieved_gbs": order_bytes / (order_ms * 1e-3) / 1e9,
-        "frac": order_bytes / (order_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-
+    roofline = {"bound": "hbm", "kernel": "K3 gradient (k_gradient)", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "algo_bytes_per_vertex": K3_BYTES_PER_VERTEX,
+                "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": k3_ms}
+    order_ms = sum(stage_ms.get(k, 0.0) for k in ORDER_STAGES)
+    order_gbs = ORDER_BYTES_PER_VERTEX * n / (order_ms * 1e-3) / 1e9
+    stage_hbm = {
+        "vertex order (K1 + K2)": {"algo_bytes_per_vertex": ORDER_BYTES_PER_VERTEX,
+                                   "ms": order_ms, "achieved_gbs": order_gbs,
+                                   "frac": order_gbs / HBM_PEAK_GBS},
+        "K3 gradient": {"algo_bytes_per_vertex": K3_BYTES_PER_VERTEX, "ms": k3_ms,
+                        "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS}}
     k3_issue = None
-    if dom == "K3 gradient" and kernel_source_sha1() == K3_VALU_PER_WAVE["source_sha1"]:
-        rate = n / 64 * K3_VALU_PER_WAVE["valu"] / (stage_ms[dom] * 1e-3) / 1e9
-        k3_issue = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_ISSUE_PEAK_G,
-                    "unit": "G wave-level VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK_G,
-                    "valu_per_wave": K3_VALU_PER_WAVE["valu"]}
+    if kernel_source_sha1() == K3_VALU_PER_WAVE["source_sha1"]:
+        rate = n / 64 * K3_VALU_PER_WAVE["valu"] / (k3_ms * 1e-3) / 1e9
+        k3_issue = {"bound": "alu", "kernel": "K3 gradient", "achieved": rate,
+                    "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-level VALU instructions/s",
+                    "frac": rate / VALU_ISSUE_PEAK_G, "valu_per_wave": K3_VALU_PER_WAVE["valu"]}
     out = {
         "metric": "time to full non-signal cancellation (s) + persistence-map Mverts/s at 256^3",
         "value": value, "unit": "Mverts/s", "n_gpus": 1, "steps": steps,
@@ -378,7 +458,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "dims": list(dims), "seed": args.seed,
                    "signal": "non-signal = saddle-saddle pairs with persistence < 0.1 range",
-                   "step": "one solver iteration (update + persistence map + assignment)"},
+                   "step": "one solver iteration (update + persistence map + exact assignment)"},
         "persistence_map_mverts_s": n / (pm_ms * 1e-3) / 1e6,
         "persistence_map_ms": pm_ms,
         "persistence_map_wall_ms": float(np.median(wall)) * 1e3,
@@ -400,8 +480,34 @@ def main():
                                "ms": max(stage_ms.values()),
                                "share": max(stage_ms.values()) / pm_ms},
     }
-    # the paper's assignment setting (auction at relative precision 0.01)
-    if not args.no_paper_auction:
+    # towards full cancellation (the metric's first half), with the paper's
+    # stop rule read off the same trajectory
+    if args.cancel_cap > 0:
+        print(f"[bench] solve towards full cancellation (cap {args.cancel_cap})",
+              file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc = ts.simplify(ft, j_max=args.cancel_cap, trace=True, **sig)
+        torch.cuda.synchronize()
+        wall_c = time.perf_counter() - t0
+        js, tsp = trace_stop(rc.trace)
+        tr = rc.trace
+        out["time_to_cancel_s"] = wall_c if rc.cancelled else None
+        out["time_to_paper_stop_s"] = tsp
+        out["cancel_run"] = {
+            "cap": args.cancel_cap, "iterations": rc.iterations, "cancelled": rc.cancelled,
+            "wall_s": wall_c, "tolerance_rel": 1e-6,
+            "max_nonsignal_pers_rel": rc.max_nonsignal_pers / rc.range,
+            "paper_stop_iterations": js, "paper_stop_s": tsp,
+            "loss0": rc.loss0, "loss": rc.loss, "assign_s": rc.assign_s,
+            "persistence_s": rc.persistence_s, "linf": rc.linf,
+            "max_signal_disp": rc.max_signal_disp,
+            "residual_by_iteration": [float(x) / rc.range for x in
+                                      tr[[j for j in (1, 2, 5, 10, 20, 40, 60, 100, 200)
+                                          if j < len(tr)] + [len(tr) - 1], 2]],
+            "note": "residual_by_iteration: largest non-signal persistence / range after "
+                    "iterations 1, 2, 5, 10, 20, 40, ... and at the end"}
+    if args.paper_auction:
         print(f"[bench] {args.steps} steps with the paper's auction precision", file=sys.stderr,
               flush=True)
         torch.cuda.synchronize()
@@ -415,36 +521,16 @@ def main():
             "assign_s": rp.assign_s, "loss": rp.loss,
             "note": "assignment by an auction stopped at relative precision 0.01 (the paper's "
                     "setting); not parity with the exact oracle"}
-    if args.paper_stop:
-        print(f"[bench] solve to the paper's stop rule (j_max {args.j_max})", file=sys.stderr,
-              flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, rs = ts.simplify(ft, j_max=args.j_max, stop_mode=1, loss_ratio_s=0.01, **sig)
-        torch.cuda.synchronize()
-        out["paper_stop_run"] = {"wall_s": time.perf_counter() - t0, "iterations": rs.iterations,
-                                 "stopped": rs.cancelled, "loss0": rs.loss0, "loss": rs.loss,
-                                 "persistence_s": rs.persistence_s, "assign_s": rs.assign_s,
-                                 "regradient_frac":
-                                     rs.n_regradient / (n * max(rs.iterations, 1))}
-    if args.cancel:
-        print(f"[bench] full solve (j_max {args.j_max})", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g, rc = ts.simplify(ft, j_max=args.j_max, **sig)
-        torch.cuda.synchronize()
-        out["time_to_cancel_s"] = time.perf_counter() - t0 if rc.cancelled else None
-        out["cancel_run"] = {"iterations": rc.iterations, "cancelled": rc.cancelled,
-                             "wall_s": time.perf_counter() - t0,
-                             "max_nonsignal_pers_rel": rc.max_nonsignal_pers / rc.range,
-                             "linf": rc.linf, "max_signal_disp": rc.max_signal_disp}
+    if not args.no_configs:
+        print("[bench] 32^3 and 128^3 Gaussian workloads", file=sys.stderr, flush=True)
+        out["configs"] = config_runs(ts, fields, torch)
     if not args.no_batch:
         out["batch"] = batch_run(ts, fields, torch, args)
     if args.warm_start:
         out["warm_start"] = warm_start_run(ts, torch, args)
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(f, args.cpu_crop, w["signal"])
+        out["cpu_baseline"] = cpu_baseline(args.cpu_dims, w["signal"])
     print(json.dumps(out))
 
 

@@ -108,6 +108,14 @@ typedef struct {
                               the solve starts from g0 (e.g. the warm-start network's
                               proposal) with the targets of D(f0), unless the loss of
                               g0 exceeds the loss of f0.  Single-field solves only. */
+  double* trace;           /* NULL, or a host array of 4 * trace_cap doubles: entry j
+                              (j = 0 .. iterations, up to trace_cap entries) holds the
+                              wall seconds since the call began, the loss L_j, the
+                              largest persistence among diagonal-assigned points and
+                              the cumulative assignment seconds, after iteration j
+                              (j = 0: the state of the start field).  Single-field
+                              solves only. */
+  int64_t trace_cap;
 } ts_options;
 
 typedef struct {

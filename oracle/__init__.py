@@ -28,15 +28,24 @@ PAIR_DTYPE = np.dtype([
 assert PAIR_DTYPE.itemsize == 48
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (plain FP32, no contraction)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+OMP_LIB_PATH = os.path.join(HERE, "liboracle_omp.so")
+
+
+def _compile(path, extra, force):
+    if force or not os.path.exists(path) or os.path.getmtime(path) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "tso.h"))):
-        tmp = LIB_PATH + ".tmp"
+        tmp = path + ".tmp"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC",
-                               "-shared", SRC, "-o", tmp])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+                               "-shared"] + extra + [SRC, "-o", tmp])
+        os.replace(tmp, path)
+    return path
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain FP32, no contraction), and its
+    multi-core timing build (-fopenmp; same source, same results)."""
+    _compile(OMP_LIB_PATH, ["-fopenmp"], force)
+    return _compile(LIB_PATH, [], force)
 
 
 class _Signal(ctypes.Structure):
@@ -82,9 +91,10 @@ def lib():
         L.tso_bottleneck.argtypes = [P, i64, P, i64, P]
         L.tso_simplify.argtypes = [P, P, P, P, P, P, P, i64]
         L.tso_assign_step.argtypes = [P, i64, P, P, i64, P, i64, P, P, P]
+        L.tso_threads.argtypes = []
         for fn in ("tso_order", "tso_gradient", "tso_gradient_at", "tso_critical",
                    "tso_pairs", "tso_diagram", "tso_assign", "tso_bottleneck",
-                   "tso_simplify", "tso_assign_step"):
+                   "tso_simplify", "tso_assign_step", "tso_threads"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -189,6 +199,31 @@ def pairs(f, method=0):
 
 def diagram(f):
     return _pairs_call(lib().tso_diagram, f)
+
+
+_omp = None
+
+
+def omp_lib():
+    """The OpenMP timing build (gradient and vertex-order loops on all
+    threads of OMP_NUM_THREADS); for the benchmark's CPU baseline only."""
+    global _omp
+    if _omp is None:
+        build()
+        L = ctypes.CDLL(OMP_LIB_PATH)
+        P, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.tso_diagram.argtypes = [P, P, P, i64, P]
+        L.tso_diagram.restype = ctypes.c_int
+        L.tso_threads.argtypes = []
+        L.tso_threads.restype = ctypes.c_int
+        _omp = L
+    return _omp
+
+
+def diagram_omp(f):
+    """diagram(f) by the OpenMP build; returns (records, threads used)."""
+    L = omp_lib()
+    return _pairs_call(L.tso_diagram, f), int(L.tso_threads())
 
 
 def assign(pb, pd, qb, qd):

@@ -10,6 +10,10 @@
  * (-ffp-contract=off: the gradient step is specified in plain FP32 with no
  * fused multiply-add, so that its rounding is reproducible.)
  */
+#ifdef _OPENMP
+#include <omp.h>
+#include <parallel/algorithm>
+#endif
 #include "tso.h"
 
 #include <algorithm>
@@ -181,11 +185,18 @@ void vertex_order(const float* f, int64_t n, std::vector<int32_t>* order,
   order->resize(n);
   rank->resize(n);
   for (int64_t i = 0; i < n; ++i) (*order)[i] = int32_t(i);
-  std::sort(order->begin(), order->end(), [&](int32_t a, int32_t b) {
+  auto before = [&](int32_t a, int32_t b) {
     const float fa = canon(f[a]), fb = canon(f[b]);
     if (fa != fb) return fa < fb;
     return a < b;
-  });
+  };
+#ifdef _OPENMP
+  /* the multi-core timing build only: a parallel sort under the same total
+     order gives the same permutation */
+  __gnu_parallel::sort(order->begin(), order->end(), before);
+#else
+  std::sort(order->begin(), order->end(), before);
+#endif
   for (int64_t i = 0; i < n; ++i) (*rank)[(*order)[i]] = int32_t(i);
 }
 
@@ -337,34 +348,45 @@ void compute_gradient(const Grid& g, const int32_t* rank, Gradient* G) {
   G->edown.assign(7 * n, -2);
   G->tdown.assign(12 * n, -2);
   G->qdown.assign(6 * n, -2);
-  Cell c;
-  for (int64_t id = 0; id < 7 * n; ++id)
-    if (make_cell(g, 1, id, &c)) G->eup[id] = G->edown[id] = -1;
-  for (int64_t id = 0; id < 12 * n; ++id)
-    if (make_cell(g, 2, id, &c)) G->tup[id] = G->tdown[id] = -1;
-  for (int64_t id = 0; id < 6 * n; ++id)
-    if (make_cell(g, 3, id, &c)) G->qdown[id] = -1;
+  /* The multi-core timing build (-fopenmp) splits these loops over threads;
+     every cell lies in the lower star of exactly one vertex (its highest),
+     so the writes of different vertices never meet and the result is the
+     single-threaded one.  The checker is built without OpenMP. */
+#pragma omp parallel
+  {
+    Cell c;
+#pragma omp for schedule(static)
+    for (int64_t id = 0; id < 7 * n; ++id)
+      if (make_cell(g, 1, id, &c)) G->eup[id] = G->edown[id] = -1;
+#pragma omp for schedule(static)
+    for (int64_t id = 0; id < 12 * n; ++id)
+      if (make_cell(g, 2, id, &c)) G->tup[id] = G->tdown[id] = -1;
+#pragma omp for schedule(static)
+    for (int64_t id = 0; id < 6 * n; ++id)
+      if (make_cell(g, 3, id, &c)) G->qdown[id] = -1;
 
-  std::vector<Cell> scratch;
-  LowerStar ls;
-  LSResult res;
-  for (int64_t x = 0; x < n; ++x) {
-    build_lower_star(g, rank, x, &scratch, &ls);
-    process_lower_star(ls, &res);
-    for (const auto& pr : res.pairs) {
-      const Cell& hi = ls.cells[pr.second];
-      if (pr.first < 0) {
-        G->vup[x] = hi.id;
-        G->edown[hi.id] = x;
-        continue;
-      }
-      const Cell& lo = ls.cells[pr.first];
-      if (lo.dim == 1) {
-        G->eup[lo.id] = hi.id;
-        G->tdown[hi.id] = lo.id;
-      } else {
-        G->tup[lo.id] = hi.id;
-        G->qdown[hi.id] = lo.id;
+    std::vector<Cell> scratch;
+    LowerStar ls;
+    LSResult res;
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t x = 0; x < n; ++x) {
+      build_lower_star(g, rank, x, &scratch, &ls);
+      process_lower_star(ls, &res);
+      for (const auto& pr : res.pairs) {
+        const Cell& hi = ls.cells[pr.second];
+        if (pr.first < 0) {
+          G->vup[x] = hi.id;
+          G->edown[hi.id] = x;
+          continue;
+        }
+        const Cell& lo = ls.cells[pr.first];
+        if (lo.dim == 1) {
+          G->eup[lo.id] = hi.id;
+          G->tdown[hi.id] = lo.id;
+        } else {
+          G->tup[lo.id] = hi.id;
+          G->qdown[hi.id] = lo.id;
+        }
       }
     }
   }
@@ -1354,6 +1376,14 @@ int tso_assign_step(const tso_pair* prev, int64_t n_prev, const int32_t* phi_pre
   S.assign(Pc, Pp, phip, &phi, n_still, n_reduced);
   for (int64_t i = 0; i < n_cur; ++i) phi_out[i] = phi[i];
   return 0;
+}
+
+int tso_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 int tso_bottleneck(const tso_pair* a, int64_t na, const tso_pair* b, int64_t nb,

@@ -154,6 +154,11 @@ int tso_assign_step(const tso_pair* prev, int64_t n_prev, const int32_t* phi_pre
                     const tso_pair* cur, int64_t n_cur, const tso_pair* targets,
                     int64_t n_tgt, int32_t* phi_out, int64_t* n_still, int64_t* n_reduced);
 
+/* Threads the gradient (Sec. 4.2) and vertex-order loops use: 1 for the
+ * checker; the OpenMP timing build (same source, -fopenmp) reports its
+ * thread count. */
+int tso_threads(void);
+
 /* Bottleneck distance (L-infinity ground metric) between two diagrams;
  * finite points of equal dimension and the essential classes are matched
  * separately.  Small inputs only. */

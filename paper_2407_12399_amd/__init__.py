@@ -49,7 +49,8 @@ class _Options(ctypes.Structure):
                 ("j_max", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("cancel_tol_rel", ctypes.c_float), ("loss_ratio_s", ctypes.c_float),
                 ("inputs_on_device", ctypes.c_int32), ("assign_precision", ctypes.c_float),
-                ("full_gradient", ctypes.c_int32), ("init", ctypes.c_void_p)]
+                ("full_gradient", ctypes.c_int32), ("init", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64)]
 
 
 class _Report(ctypes.Structure):
@@ -337,6 +338,7 @@ class Report:
     n_regradient: int
     init_used: int
     status: int
+    trace: object = None  # (iterations + 1, 4): wall s, loss, max non-signal persistence, assign s
 
 
 def _signal(threshold, nonsignal_dims, ties_signal, signal_pairs):
@@ -377,7 +379,8 @@ def signal_mask(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0,
 
 def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alpha_b=0.5,
              alpha_d=0.5, j_max=1000, stop_mode=0, cancel_tol_rel=1e-6, loss_ratio_s=0.01,
-             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False, init=None):
+             signal_pairs=None, out=None, assign_precision=0.0, full_gradient=False, init=None,
+             trace=False):
     """Topological simplification; returns (g, Report).  g has the kind of
     the input (torch CUDA tensor in, torch CUDA tensor out).  init: optional
     start field of the same kind and shape (used unless its loss is higher)."""
@@ -392,6 +395,10 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
         if ion != on_dev or not np.array_equal(idims, dims):
             raise ValueError("init must match the field's kind and shape")
         opt.init = ip
+    tr = None
+    if trace:
+        tr = np.zeros((j_max + 1, 4), np.float64)
+        opt.trace, opt.trace_cap = tr.ctypes.data, j_max + 1
     rep = _Report()
     torch = _torch()
     if on_dev:
@@ -403,7 +410,10 @@ def simplify(field, threshold=0.1, nonsignal_dims=(0, 1, 2), ties_signal=0, alph
     rc = lib().ts_simplify(ctx, fp, _ptr(dims), ctypes.byref(sig), ctypes.byref(opt), gp,
                            ctypes.byref(rep))
     _check(ctx, rc, allow=(0, 1))
-    return g, _report(rep, rc)
+    r = _report(rep, rc)
+    if tr is not None:
+        r.trace = tr[: rep.iterations + 1].copy()
+    return g, r
 
 
 def _report(rep, rc):

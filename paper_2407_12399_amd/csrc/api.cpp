@@ -200,6 +200,7 @@ void check_solver_args(const ts_signal* sig, const ts_options* opt) {
     throw Error(TS_ERR_ARG, "assign_precision must be finite and >= 0");
   if (opt->j_max < 0 || opt->stop_mode < 0 || opt->stop_mode > 1)
     throw Error(TS_ERR_ARG, "bad options");
+  if (opt->trace && opt->trace_cap < 0) throw Error(TS_ERR_ARG, "bad trace capacity");
   if (sig->mode != 0 && sig->mode != 1) throw Error(TS_ERR_ARG, "bad signal mode");
   if (sig->mode == 1 && sig->n_signal > 0 && !sig->signal)
     throw Error(TS_ERR_ARG, "signal list is NULL");
@@ -477,6 +478,7 @@ int ts_simplify_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int6
     check_solver_args(sig, opt);
     if (sig->mode != 0) throw Error(TS_ERR_ARG, "a batch takes the threshold signal mode only");
     if (opt->init) throw Error(TS_ERR_ARG, "a batch takes no start field");
+    if (opt->trace) throw Error(TS_ERR_ARG, "a batch takes no trace");
     if (!f || !g || !reps) throw Error(TS_ERR_ARG, "null argument");
     for (int i = 0; i < nf; ++i)
       if (!f[i] || !g[i]) throw Error(TS_ERR_ARG, "null field pointer");

@@ -1634,6 +1634,16 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     r.cancelled = opt.stop_mode == 0 && done(r, r.L);
     n_active += r.cancelled ? 0 : 1;
   }
+  // per-iteration trace of a single-field solve
+  auto trace = [&](int jj) {
+    if (!opt.trace || nf != 1 || jj >= opt.trace_cap) return;
+    double* t = opt.trace + 4 * size_t(jj);
+    t[0] = now_s() - t0;
+    t[1] = F[0].L;
+    t[2] = F[0].S.max_diag_pers(F[0].P, F[0].phi);
+    t[3] = assign_s;
+  };
+  trace(0);
   int j = 0;
   while (n_active > 0 && j < opt.j_max) {
     ++j;
@@ -1739,6 +1749,7 @@ int simplify_fields(ts_ctx* ctx, int nf, const float* const* f, const Grid& G,
     for (const FieldRun& r : F) n_active += r.cancelled ? 0 : 1;
     local_prev.swap(local_n);
     assign_s += now_s() - ta;
+    trace(j);
   }
   for (FieldRun& r : F)
     if (!r.cancelled) r.iterations = j;

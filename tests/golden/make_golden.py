@@ -53,8 +53,6 @@ def filament256():
     vup, eup, tup = oracle.gradient(f)
     out["gradient_s"] = round(time.time() - t, 1)
     out["vup_sha256"], out["eup_sha256"], out["tup_sha256"] = sha(vup), sha(eup), sha(tup)
-    out["critical_counts"] = [int((vup == -1).sum()), int((eup == -1).sum()),
-                              int((tup == -1).sum())]
     del vup, eup, tup
     print("gradient done", out["gradient_s"], "s", flush=True)
     t = time.time()

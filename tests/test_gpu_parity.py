@@ -498,3 +498,17 @@ def test_overlapping_buffers_rejected(gpu):
     assert e.value.code == -1
     g, _ = gpu.simplify(src, out=buf[f.numel():].view(f.shape), j_max=2)
     assert g.data_ptr() == buf[f.numel():].data_ptr()
+
+
+def test_trace_matches_oracle(gpu, orc):
+    """The per-iteration trace of a solve: the losses are the oracle's
+    (Alg. 1, iteration by iteration), the last entry's largest non-signal
+    persistence is the report's, and the times do not decrease."""
+    f = fields.gaussian_mixture((16, 14, 13), 8, 0.05, 2)
+    g, rep = gpu.simplify(_t(f), threshold=0.1, j_max=1000, trace=True)
+    go, ro = orc.simplify(f, threshold=0.1, j_max=1000)
+    assert rep.trace.shape == (rep.iterations + 1, 4)
+    assert rep.iterations == ro.iterations
+    np.testing.assert_allclose(rep.trace[:, 1], ro.trace, rtol=1e-9, atol=1e-15)
+    assert rep.trace[-1, 2] == rep.max_nonsignal_pers
+    assert np.all(np.diff(rep.trace[:, 0]) >= 0) and np.all(np.diff(rep.trace[:, 3]) >= 0)

@@ -40,8 +40,30 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
 
 
+def _close(a, ref, rtol, atol_frac, what):
+    """Element by element: |a - ref| <= rtol * |ref| + atol_frac * max |ref|.
+    The device stores weights and activations in BF16 (8-bit significand,
+    relative rounding 2^-9) at the same places as the reference; where an
+    FP32 sum (device) and an FP64 sum (reference) fall on different sides of
+    a BF16 rounding boundary, one value differs by a BF16 ulp (2^-8
+    relative), and that difference travels through the later layers, so
+    the bound has a relative part and a part scaled to the tensor."""
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = float(np.abs(ref).max()) if ref.size else 0.0
+    err = np.abs(a - ref)
+    bound = rtol * np.abs(ref) + atol_frac * scale
+    worst = int(np.argmax(err - bound)) if ref.size else 0
+    assert np.all(err <= bound), (what, "worst", worst, float(a.ravel()[worst]),
+                                  float(ref.ravel()[worst]), "max err / scale",
+                                  float(err.max() / max(scale, 1e-300)))
+
+
 @pytest.mark.parametrize("dims", [(8, 12, 16), (4, 4, 4), (12, 8, 20), (32, 32, 32), (64, 64, 64)])
 def test_unet_forward_and_gradient(gpu, dims):
+    """Forward output and every parameter gradient, element by element, against
+    the FP64 reference with the same BF16 roundings; the first layer's
+    weights are compared on its two real input channels (f, mask)."""
     import torch
     from oracle import unet_ref
     p = _params(7)
@@ -54,6 +76,7 @@ def test_unet_forward_and_gradient(gpu, dims):
                            torch.as_tensor(inp, dtype=torch.float64)).detach().numpy()
     assert out.shape == ref.shape
     assert _rel(out, ref) < 1e-2
+    _close(out, ref, 2e-2, 1e-2, "output")
     loss, grad = gpu.unet_grad(pt, it, tt)
     lref, gref = unet_ref.loss_and_grad(p.astype(np.float64), inp, target)
     assert abs(loss - lref) <= 1e-2 * lref
@@ -61,11 +84,17 @@ def test_unet_forward_and_gradient(gpu, dims):
     o = 0
     for i, (ci, co) in enumerate(unet_ref.LAYERS):
         n = 27 * ci * co
-        if i > 0:  # layer 0's padded input channels carry no signal
-            assert _rel(grad[o:o + n], gref[o:o + n]) < 5e-2, ("weights", i)
-        assert _rel(grad[o + n:o + n + co], gref[o + n:o + n + co]) < 5e-2, ("bias", i)
+        w, wr = grad[o:o + n].reshape(27, co, ci), gref[o:o + n].reshape(27, co, ci)
+        if i == 0:  # channels 2..7 of the first layer are zero padding
+            w, wr = w[:, :, :2], wr[:, :, :2]
+        assert _rel(w, wr) < 5e-2, ("weights", i)
+        _close(w, wr, 1e-1, 3e-2, ("weights", i))
+        b, br = grad[o + n:o + n + co], gref[o + n:o + n + co]
+        assert _rel(b, br) < 5e-2, ("bias", i)
+        _close(b, br, 1e-1, 3e-2, ("bias", i))
         o += n + co
     assert _rel(grad[o:], gref[o:]) < 2e-2
+    _close(grad[o:], gref[o:], 5e-2, 1e-2, "head")
 
 
 def test_unet_adam_step(gpu):
