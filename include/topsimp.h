@@ -297,6 +297,23 @@ int ts_assign_auction(int64_t n_pts, const double* pb, const double* pd, int64_t
                       const double* qb, const double* qd, double rel_precision, int32_t* match,
                       double* cost);
 
+/* Vertex order (as ts_order) for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It needs no context and allocates nothing: its temporaries
+ * (sort keys and values with their ping-pong buffers, digit histograms, scan
+ * sums, a flag) live in one static device array of 2^21 * 16 bytes + 1 MiB
+ * (33 MiB), which every device that runs this call holds until the process
+ * ends.  Calls that overlap on one device share that array and race: order
+ * them on one stream.
+ *   f:      n floats, device pointer on the current device
+ *   n:      1 .. 2^21 (2,097,152); larger sizes return TS_ERR_ARG
+ *   order, rank: n int32 each, device pointers; no two of f, order, rank
+ *           may overlap
+ *   hip_stream: the hipStream_t to run on (NULL: the null stream); the call
+ *           waits for it before returning (it reads back the non-finite flag)
+ * Returns TS_OK, TS_ERR_ARG, TS_ERR_NONFINITE (NaN or Inf in f), TS_ERR_HIP. */
+int ts_order_noalloc(const float* f, int64_t n, int32_t* order, int32_t* rank, void* hip_stream);
+
 /* Per-kernel device time (ms) of the last ts_diagram / ts_simplify call,
  * measured with HIP events on the context's stream: stage_ms[i] for the
  * stage named stage_names[i] (NULL-terminated list).  Returns the count. */

@@ -73,7 +73,7 @@ EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram
            "ts_simplify", "ts_simplify_batch", "ts_unet_param_count", "ts_unet_forward",
            "ts_unet_backward", "ts_unet_adam",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
-           "ts_stage_times", "ts_signal_mask"]
+           "ts_stage_times", "ts_signal_mask", "ts_order_noalloc"]
 
 
 def lib():
@@ -93,6 +93,7 @@ def lib():
         L.ts_simplify.argtypes = [P, P, P, P, P, P, P]
         L.ts_simplify_batch.argtypes = [P, i32, P, P, P, P, P, P]
         L.ts_signal_mask.argtypes = [P, P, P, P, i32, P, P]
+        L.ts_order_noalloc.argtypes = [P, i64, P, P, P]
         L.ts_unet_param_count.argtypes = [P]
         L.ts_unet_forward.argtypes = [P, P, P, P, P]
         L.ts_unet_backward.argtypes = [P, P, P, P, P, P, P]

@@ -569,6 +569,23 @@ int ts_assign_auction(int64_t n_pts, const double* pb, const double* pd, int64_t
   }
 }
 
+int ts_order_noalloc(const float* f, int64_t n, int32_t* order, int32_t* rank,
+                     void* hip_stream) {
+  try {
+    if (!f || !order || !rank || n < 1) return TS_ERR_ARG;
+    const float* fo = reinterpret_cast<const float*>(order);
+    const float* fr = reinterpret_cast<const float*>(rank);
+    if (overlaps(f, n, fo, n) || overlaps(f, n, fr, n) || overlaps(fo, n, fr, n))
+      return TS_ERR_ARG;
+    order_noalloc(f, n, order, rank, static_cast<hipStream_t>(hip_stream));
+    return TS_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return TS_ERR_INTERNAL;
+  }
+}
+
 int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** ms) {
   if (!ctx || !names || !ms) return TS_ERR_ARG;
   *names = ctx->stage_names.empty() ? nullptr : ctx->stage_names.data();

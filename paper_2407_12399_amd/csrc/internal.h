@@ -95,6 +95,21 @@ struct Grid {
   int n;
 };
 
+// Slices of one device area handed out in order (256-byte aligned), for
+// code that must not allocate; running past the area is an argument error.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  template <class T>
+  T* get(const std::string&, size_t count) {
+    const size_t at = (used + 255) & ~size_t(255);
+    const size_t bytes = count * sizeof(T) + 16;
+    if (at + bytes > cap) throw Error(TS_ERR_ARG, "scratch area too small for this size");
+    used = at + bytes;
+    return reinterpret_cast<T*>(base + at);
+  }
+};
+
 // Sorting and scanning primitives (sort.hip).
 void scan_exclusive_u32(Workspace& ws, const uint32_t* in, uint32_t* out, size_t n,
                         hipStream_t s);
@@ -103,6 +118,9 @@ void scan_exclusive_u32(Workspace& ws, const uint32_t* in, uint32_t* out, size_t
 void radix_sort_u64(Workspace& ws, uint64_t* keys, uint32_t* vals, size_t n, int begin_bit,
                     int end_bit, hipStream_t s);
 void radix_sort_u32(Workspace& ws, uint32_t* keys, uint32_t* vals, size_t n, int begin_bit,
+                    int end_bit, hipStream_t s);
+// The same sort with its temporary buffers taken from an arena.
+void radix_sort_u32(Arena& arena, uint32_t* keys, uint32_t* vals, size_t n, int begin_bit,
                     int end_bit, hipStream_t s);
 
 }  // namespace ts

@@ -54,6 +54,9 @@ struct PersistenceResult {
 
 // Vertex order only (K1 + K2).
 void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* rank);
+// The vertex order with no device allocation: temporaries in a static device
+// array (at most 2^21 vertices); f, order, rank are device pointers.
+void order_noalloc(const float* f, int64_t n, int32_t* order, int32_t* rank, hipStream_t s);
 
 // The whole persistence map (K1..K8) of a device field.  With `changed`
 // (device, n bytes, nonzero where the value differs from the field of the

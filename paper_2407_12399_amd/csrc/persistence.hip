@@ -24,6 +24,7 @@
 //          parallel Z2 reduction (every column whose pivot is not its own
 //          adds the column of the lowest owner of that pivot, in rounds).
 //   K8     diagram: v_birth != v_death filter, diagram-order sort.
+#include <mutex>
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -2294,6 +2295,57 @@ void compute_order(ts_ctx* ctx, const float* f, int n, int32_t* order, int32_t* 
   ctx->timer.start("K2 rank");
   k_rank_scatter<<<blocks_for(n), 256, 0, s>>>(vals, n, rank, order);
   ctx->timer.stop();
+  TS_HIP(hipGetLastError());
+  if (read_scalar(bad, s)) throw Error(TS_ERR_NONFINITE, "field contains NaN or Inf");
+}
+
+// ---------------------------------------------------------------- vertex
+// order without allocation.  Its temporaries (sort keys and values, their
+// ping-pong buffers, digit histograms, scan sums, the non-finite flag) live
+// in one static device array, sized for kNoAllocMaxN vertices: 16 bytes per
+// vertex plus 1 MiB.  Every device that runs it holds its own copy of the
+// array until the process ends; its address is taken once per device with
+// hipGetSymbolAddress (the array's name is not a device address in host
+// code).  Calls that overlap on one device share the array and race.
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 21;
+constexpr size_t kNoAllocScratchBytes = size_t(kNoAllocMaxN) * 16 + (size_t(1) << 20);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+__global__ void k_clear_flag(int* flag) { *flag = 0; }
+
+// The array's device address on the current device (taken on the first call there).
+char* scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  TS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(TS_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    TS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(TS_ERR_HIP, "no device address for the scratch array");
+    addr[dev] = p;
+  }
+  return static_cast<char*>(addr[dev]);
+}
+
+void order_noalloc(const float* f, int64_t n, int32_t* order, int32_t* rank, hipStream_t s) {
+  if (!f || !order || !rank || n < 1) throw Error(TS_ERR_ARG, "bad arguments");
+  if (n > kNoAllocMaxN)
+    throw Error(TS_ERR_ARG, "more than 2^21 vertices: beyond the no-allocation scratch");
+  Arena a;
+  a.base = scratch_address();
+  a.cap = kNoAllocScratchBytes;
+  uint32_t* keys = a.get<uint32_t>("keys", size_t(n));
+  uint32_t* vals = a.get<uint32_t>("vals", size_t(n));
+  int* bad = a.get<int>("bad", 1);
+  k_clear_flag<<<1, 1, 0, s>>>(bad);
+  k_order_keys<<<blocks_for(int(n)), 256, 0, s>>>(f, int(n), keys, vals, bad);
+  TS_HIP(hipGetLastError());
+  radix_sort_u32(a, keys, vals, size_t(n), 0, 32, s);
+  k_rank_scatter<<<blocks_for(int(n)), 256, 0, s>>>(vals, int(n), rank, order);
   TS_HIP(hipGetLastError());
   if (read_scalar(bad, s)) throw Error(TS_ERR_NONFINITE, "field contains NaN or Inf");
 }

@@ -192,22 +192,38 @@ __global__ void copy_u64(const uint64_t* a, uint64_t* b, size_t n) {
   if (i < n) b[i] = a[i];
 }
 
-template <class K>
-void radix_sort_impl(Workspace& ws, K* keys, uint32_t* vals, size_t n, int begin_bit,
+template <class A>
+void scan_impl(A& ws, const uint32_t* in, uint32_t* out, size_t n, hipStream_t s, int depth) {
+  if (n == 0) return;
+  const size_t nblocks = (n + kTile - 1) / kTile;
+  if (nblocks == 1) {
+    scan_apply<<<1, kThreads, 0, s>>>(in, out, n, nullptr);
+    TS_HIP(hipGetLastError());
+    return;
+  }
+  uint32_t* sums = ws.template get<uint32_t>("scan.sums" + std::to_string(depth), nblocks);
+  scan_block_sums<<<unsigned(nblocks), kThreads, 0, s>>>(in, n, sums);
+  scan_impl(ws, sums, sums, nblocks, s, depth + 1);
+  scan_apply<<<unsigned(nblocks), kThreads, 0, s>>>(in, out, n, sums);
+  TS_HIP(hipGetLastError());
+}
+
+template <class K, class A>
+void radix_sort_impl(A& ws, K* keys, uint32_t* vals, size_t n, int begin_bit,
                      int end_bit, hipStream_t s, const char* tag) {
   if (n <= 1 || end_bit <= begin_bit) return;
   const int nblocks = int((n + rs_tile<K>() - 1) / rs_tile<K>());
   std::string t(tag);
-  K* ktmp = ws.get<K>(t + ".k", n);
-  uint32_t* vtmp = ws.get<uint32_t>(t + ".v", n);
-  uint32_t* hist = ws.get<uint32_t>(t + ".h", size_t(256) * nblocks);
+  K* ktmp = ws.template get<K>(t + ".k", n);
+  uint32_t* vtmp = ws.template get<uint32_t>(t + ".v", n);
+  uint32_t* hist = ws.template get<uint32_t>(t + ".h", size_t(256) * nblocks);
   K* kin = keys;
   uint32_t* vin = vals;
   K* kout = ktmp;
   uint32_t* vout = vtmp;
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
     rs_hist<K><<<nblocks, kThreads, 0, s>>>(kin, n, shift, hist, nblocks);
-    scan_exclusive_u32(ws, hist, hist, size_t(256) * nblocks, s);
+    scan_impl(ws, hist, hist, size_t(256) * nblocks, s, 0);
     rs_scatter<K><<<nblocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, nblocks);
     std::swap(kin, kout);
     std::swap(vin, vout);
@@ -229,23 +245,7 @@ void radix_sort_impl(Workspace& ws, K* keys, uint32_t* vals, size_t n, int begin
 
 void scan_exclusive_u32(Workspace& ws, const uint32_t* in, uint32_t* out, size_t n,
                         hipStream_t s) {
-  if (n == 0) return;
-  const size_t nblocks = (n + kTile - 1) / kTile;
-  if (nblocks == 1) {
-    scan_apply<<<1, kThreads, 0, s>>>(in, out, n, nullptr);
-    TS_HIP(hipGetLastError());
-    return;
-  }
-  // one level of block sums, scanned recursively
-  static int depth = 0;
-  std::string tag = "scan.sums" + std::to_string(depth);
-  uint32_t* sums = ws.get<uint32_t>(tag, nblocks);
-  scan_block_sums<<<unsigned(nblocks), kThreads, 0, s>>>(in, n, sums);
-  ++depth;
-  scan_exclusive_u32(ws, sums, sums, nblocks, s);
-  --depth;
-  scan_apply<<<unsigned(nblocks), kThreads, 0, s>>>(in, out, n, sums);
-  TS_HIP(hipGetLastError());
+  scan_impl(ws, in, out, n, s, 0);
 }
 
 void radix_sort_u64(Workspace& ws, uint64_t* keys, uint32_t* vals, size_t n, int begin_bit,
@@ -256,6 +256,11 @@ void radix_sort_u64(Workspace& ws, uint64_t* keys, uint32_t* vals, size_t n, int
 void radix_sort_u32(Workspace& ws, uint32_t* keys, uint32_t* vals, size_t n, int begin_bit,
                     int end_bit, hipStream_t s) {
   radix_sort_impl<uint32_t>(ws, keys, vals, n, begin_bit, end_bit, s, "rs32");
+}
+
+void radix_sort_u32(Arena& arena, uint32_t* keys, uint32_t* vals, size_t n, int begin_bit,
+                    int end_bit, hipStream_t s) {
+  radix_sort_impl<uint32_t>(arena, keys, vals, n, begin_bit, end_bit, s, "rs32");
 }
 
 }  // namespace ts
