@@ -175,8 +175,12 @@ def _pairs_call(fn, field):
     nv = int(np.prod(dims))
     # a capacity that usually fits, so that the map is not computed twice
     cap = max(4096, _cap_hint.get((fn.__name__, nv), nv // 4 + 16))
+    torch = _torch()
     while True:
-        out = np.empty(cap, PAIR_DTYPE)
+        # the records land in pinned host memory (a full-speed copy); the
+        # returned array is a view that keeps that memory alive
+        buf = torch.empty(cap * PAIR_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+        out = buf.numpy().view(PAIR_DTYPE)
         n = np.zeros(1, np.int64)
         rc = fn(ctx, fp, _ptr(dims), on_dev, _ptr(out), cap, _ptr(n))
         if rc == -5:
@@ -184,7 +188,7 @@ def _pairs_call(fn, field):
             continue
         _check(ctx, rc)
         _cap_hint[(fn.__name__, int(np.prod(dims)))] = int(n[0]) + int(n[0]) // 8 + 16
-        return out[: int(n[0])].copy()
+        return out[: int(n[0])]
 
 
 def diagram(field) -> np.ndarray:
@@ -224,7 +228,7 @@ def diagram_batch(fields) -> list:
         _check(ctx, rc)
         _cap_hint[("batch", nv)] = int(counts.sum()) * 9 // 8 + 16
         ends = np.cumsum(counts)
-        return [out[e - c: e].copy() for c, e in zip(counts, ends)]
+        return [out[e - c: e] for c, e in zip(counts, ends)]
 
 
 def pairs(field) -> np.ndarray:

@@ -32,10 +32,34 @@ void* Workspace::get(const std::string& name, size_t bytes) {
   return b.p;
 }
 
+void* Workspace::host(const std::string& name, size_t bytes) {
+  Buf& b = host_bufs[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) {
+    TS_HIP(hipDeviceSynchronize());
+    TS_HIP(hipHostFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  want += want / 8;  // room to grow a little without a new allocation
+  hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    throw Error(TS_ERR_OOM, "hipHostMalloc(" + std::to_string(want) + ") for " + name + ": " +
+                                hipGetErrorString(e));
+  }
+  b.bytes = want;
+  return b.p;
+}
+
 void Workspace::release() {
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   bufs.clear();
+  for (auto& kv : host_bufs)
+    if (kv.second.p) (void)hipHostFree(kv.second.p);
+  host_bufs.clear();
 }
 
 size_t Workspace::total_bytes() const {
@@ -124,21 +148,33 @@ void finish_timing(ts_ctx* ctx) {
 
 // Host records of the pairs (all, or the diagram subset in diagram order),
 // assembled on the device.
-void pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev, bool diagram_only,
-                   std::vector<ts_pair>* out) {
+// The records are copied straight into the caller's array (at full link
+// speed when it is pinned memory); returns the count, and copies nothing when
+// it exceeds the capacity.
+int64_t pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev,
+                      bool diagram_only, ts_pair* dst, int64_t capacity) {
   hipStream_t s = ctx->stream;
   const int64_t n = diagram_only ? R.ndiag : R.npairs;
+  if (n > capacity) return n;
+  if (n > 0 && !dst) throw Error(TS_ERR_ARG, "out is NULL");
   ts_pair* d = ctx->ws.get<ts_pair>("api.records", n + 1);
   pair_records(ctx, R, f_dev, diagram_only, d);
-  out->resize(n);
-  if (n) TS_HIP(hipMemcpyAsync(out->data(), d, n * sizeof(ts_pair), hipMemcpyDeviceToHost, s));
+  if (n) TS_HIP(hipMemcpyAsync(dst, d, n * sizeof(ts_pair), hipMemcpyDeviceToHost, s));
   TS_HIP(hipStreamSynchronize(s));
   if (!diagram_only)
-    std::sort(out->begin(), out->end(), [](const ts_pair& a, const ts_pair& b) {
+    std::sort(dst, dst + n, [](const ts_pair& a, const ts_pair& b) {
       if (a.dim != b.dim) return a.dim < b.dim;
       if (a.birth_cell != b.birth_cell) return a.birth_cell < b.birth_cell;
       return a.death_cell < b.death_cell;
     });
+  return n;
+}
+
+void pairs_to_host(ts_ctx* ctx, const PersistenceResult& R, const float* f_dev, bool diagram_only,
+                   std::vector<ts_pair>* out) {
+  const int64_t n = diagram_only ? R.ndiag : R.npairs;
+  out->resize(n);
+  pairs_to_host(ctx, R, f_dev, diagram_only, out->data(), n);
 }
 
 // Layout of a batch of fields stored one after another.
@@ -347,16 +383,13 @@ int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_devi
     const float* fd = device_field(ctx, f, g.n, on_device);
     PersistenceResult R;
     compute_persistence(ctx, fd, g, &R);
-    std::vector<ts_pair> P;
-    pairs_to_host(ctx, R, fd, false, &P);
+    const int64_t n = pairs_to_host(ctx, R, fd, false, out, capacity);
     finish_timing(ctx);
-    *n_out = int64_t(P.size());
-    if (int64_t(P.size()) > capacity) {
+    *n_out = n;
+    if (n > capacity) {
       ctx->err = "capacity too small";
       return int(TS_ERR_CAPACITY);
     }
-    if (!out && !P.empty()) throw Error(TS_ERR_ARG, "out is NULL");
-    std::copy(P.begin(), P.end(), out);
     return int(TS_OK);
   });
 }
@@ -370,16 +403,13 @@ int ts_diagram(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_de
     const float* fd = device_field(ctx, f, g.n, on_device);
     PersistenceResult R;
     compute_persistence(ctx, fd, g, &R);
-    std::vector<ts_pair> P;
-    pairs_to_host(ctx, R, fd, true, &P);
+    const int64_t n = pairs_to_host(ctx, R, fd, true, out, capacity);
     finish_timing(ctx);
-    *n_out = int64_t(P.size());
-    if (int64_t(P.size()) > capacity) {
+    *n_out = n;
+    if (n > capacity) {
       ctx->err = "capacity too small";
       return int(TS_ERR_CAPACITY);
     }
-    if (!out && !P.empty()) throw Error(TS_ERR_ARG, "out is NULL");
-    std::copy(P.begin(), P.end(), out);
     return int(TS_OK);
   });
 }
@@ -394,26 +424,27 @@ int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64
     Grid g{0, 0, 0, int(B.base[nf])};
     PersistenceResult R;
     compute_persistence(ctx, fd, g, &R, nullptr, &B);
-    std::vector<ts_pair> P;
-    pairs_to_host(ctx, R, fd, true, &P);
+    // the batch diagram lands in pinned staging, then each record goes to its
+    // field's segment of out with field-local ids (diagram order restricted to
+    // a field is that field's own diagram order)
+    const int64_t total = R.ndiag;
+    ts_pair* P = ctx->ws.host<ts_pair>("api.batch_records", size_t(total) + 1);
+    pairs_to_host(ctx, R, fd, true, P, total);
     finish_timing(ctx);
-    // diagram order restricted to a field is that field's own diagram order
-    std::vector<std::vector<ts_pair>> per(nf);
-    for (const ts_pair& r : P) {
-      const int i = field_of(B, r.v_birth);
-      per[i].push_back(local_record(r, B.base[i]));
-    }
-    int64_t total = 0;
-    for (int i = 0; i < nf; ++i) {
-      counts[i] = int64_t(per[i].size());
-      total += counts[i];
+    std::vector<int32_t> fld(total);
+    std::fill(counts, counts + nf, int64_t(0));
+    for (int64_t r = 0; r < total; ++r) {
+      fld[r] = field_of(B, P[r].v_birth);
+      ++counts[fld[r]];
     }
     if (total > capacity) {
       ctx->err = "capacity too small";
       return int(TS_ERR_CAPACITY);
     }
     if (!out && total > 0) throw Error(TS_ERR_ARG, "out is NULL");
-    for (int i = 0; i < nf; ++i) out = std::copy(per[i].begin(), per[i].end(), out);
+    std::vector<int64_t> at(nf + 1, 0);
+    for (int i = 0; i < nf; ++i) at[i + 1] = at[i] + counts[i];
+    for (int64_t r = 0; r < total; ++r) out[at[fld[r]]++] = local_record(P[r], B.base[fld[r]]);
     return int(TS_OK);
   });
 }

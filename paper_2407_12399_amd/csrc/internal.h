@@ -35,10 +35,17 @@ struct Workspace {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
+  std::map<std::string, Buf> host_bufs;  // pinned host staging (hipHostMalloc)
   void* get(const std::string& name, size_t bytes);
   template <class T>
   T* get(const std::string& name, size_t count) {
     return static_cast<T*>(get(name, count * sizeof(T) + 16));
+  }
+  // Pinned host memory for device-to-host copies at full link speed.
+  void* host(const std::string& name, size_t bytes);
+  template <class T>
+  T* host(const std::string& name, size_t count) {
+    return static_cast<T*>(host(name, count * sizeof(T) + 16));
   }
   void release();
   size_t total_bytes() const;

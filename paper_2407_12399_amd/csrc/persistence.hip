@@ -2256,19 +2256,26 @@ int union_find_rounds(ts_ctx* ctx, int64_t nedges, int64_t nnodes, int32_t* ca, 
   uint32_t* nxt = listB;
   unsigned int* ncur = cnt;
   unsigned int* nnxt = cnt + 1;
+  // The active count is read back every kUfCheck rounds only: a round's list
+  // is a subset of the previous one, so grids sized by the last count read
+  // cover the rounds launched before the next read, and a round over an empty
+  // list changes nothing (it reads the count on the device).
+  const int kUfCheck = env_int("TS_UF_CHECK", 4, 1, 64);
   while (h_n > 0) {
-    ++rounds;
-    TS_HIP(hipMemsetAsync(nnxt, 0, sizeof(unsigned int), s));
-    k_uf_hook<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, dual, nedges);
-    k_uf_link<<<blocks_for(h_n), 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, nxt, nnxt,
-                                              dual, nedges, cell_id, cell_key, node_id, node_key,
-                                              po);
-    k_uf_reset<<<blocks_for(nnodes), 256, 0, s>>>(parent, best, nnodes);
+    const unsigned grid = blocks_for(h_n);
+    for (int it = 0; it < kUfCheck; ++it) {
+      ++rounds;
+      k_fill_u32<<<1, 1, 0, s>>>(nnxt, 1, 0u);
+      k_uf_hook<<<grid, 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, dual, nedges);
+      k_uf_link<<<grid, 256, 0, s>>>(cur, ncur, ca, cb, parent, best, state, nxt, nnxt, dual,
+                                     nedges, cell_id, cell_key, node_id, node_key, po);
+      k_uf_reset<<<blocks_for(nnodes), 256, 0, s>>>(parent, best, nnodes);
+      std::swap(cur, nxt);
+      std::swap(ncur, nnxt);
+    }
     TS_HIP(hipGetLastError());
-    h_n = read_scalar(nnxt, s);
-    std::swap(cur, nxt);
-    std::swap(ncur, nnxt);
-    if (rounds > nedges + 2) throw Error(TS_ERR_INTERNAL, "union-find did not converge");
+    h_n = read_scalar(ncur, s);
+    if (rounds > nedges + 2 + kUfCheck) throw Error(TS_ERR_INTERNAL, "union-find did not converge");
   }
   return rounds;
 }
