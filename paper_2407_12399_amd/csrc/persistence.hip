@@ -451,8 +451,8 @@ __global__ void __launch_bounds__(kGradThreads)
 k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
            int32_t* __restrict__ down_out, CritOut co, const uint32_t* __restrict__ vlist,
            int64_t nlist) {
-  __shared__ uint8_t s_slot_cell[kSlotBytes * kGradThreads];
-  __shared__ uint8_t s_cell_slot[kCellBytes * kGradThreads];
+  __shared__ __align__(16) uint8_t s_slot_cell[kSlotBytes * kGradThreads];
+  __shared__ __align__(16) uint8_t s_cell_slot[kCellBytes * kGradThreads];
   __shared__ unsigned int s_cnt[4];
   __shared__ unsigned long long s_base[4];
   __shared__ HotTables T;
@@ -475,8 +475,52 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
 #define CELL_SLOT(i) cell_slot[(i) * kGradThreads]
 
   const int64_t lane = int64_t(blockIdx.x) * kGradThreads + tid;
-  const bool active = kList ? lane < nlist : lane < G.total();
-  const int v = kList ? (active ? int(vlist[lane]) : 0) : int(lane);
+  // The lower-star loops run as often as the slowest lane of a wave needs, and
+  // their trip counts grow with the number of lower neighbours.  The block's
+  // vertices are therefore first sorted by that number (a counting sort in
+  // LDS, in the space the slot tables use later), so that each wave holds
+  // vertices of similar work.  Every output is indexed by vertex, so the
+  // processing order does not change any result.
+  int v;
+  bool active;
+  {
+    const bool act0 = kList ? lane < nlist : lane < G.total();
+    const int v0 = kList ? (act0 ? int(vlist[lane]) : 0) : int(lane);
+    int key = 15;  // inactive lanes last
+    if (act0) {
+      const auto S0 = G.site(v0);
+      int x, y, z;
+      S0.xyz(v0, &x, &y, &z);
+      const uint32_t valid = S0.valid_at(x, y, z);
+      const int r0 = rank[v0];
+      int c = 0;
+#pragma unroll
+      for (int k = 0; k < 14; ++k)
+        if ((valid >> k) & 1u) c += rank[v0 + S0.nb(k)] < r0 ? 1 : 0;
+      key = c;
+    }
+    unsigned int* s_hist = reinterpret_cast<unsigned int*>(s_cell_slot);  // 16 counters
+    int* s_sorted = reinterpret_cast<int*>(s_slot_cell);                 // kGradThreads vertices
+    if (tid < 16) s_hist[tid] = 0;
+    __syncthreads();
+    const unsigned int within = atomicAdd(&s_hist[key], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned int acc = 0;
+      for (int b = 0; b < 16; ++b) {
+        const unsigned int t = s_hist[b];
+        s_hist[b] = acc;
+        acc += t;
+      }
+    }
+    __syncthreads();
+    s_sorted[s_hist[key] + within] = act0 ? v0 : -1;
+    __syncthreads();
+    const int mine = s_sorted[tid];
+    __syncthreads();  // the slot tables reuse this space below
+    active = mine >= 0;
+    v = active ? mine : 0;
+  }
   const auto S = G.site(active ? v : 0);
   int rx = 0;
   uint32_t low = 0;
