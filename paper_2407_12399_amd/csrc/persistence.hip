@@ -445,19 +445,17 @@ struct HotTables {
   uint8_t pair_tri[14][14];
 };
 
-// kList: lane i processes vertex vlist[i] (i < nlist) instead of vertex i.
-template <bool kList, class Geo>
-__global__ void __launch_bounds__(kGradThreads)
-k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
-           int32_t* __restrict__ down_out, CritOut co, const uint32_t* __restrict__ vlist,
-           int64_t nlist) {
-  __shared__ __align__(16) uint8_t s_slot_cell[kSlotBytes * kGradThreads];
-  __shared__ __align__(16) uint8_t s_cell_slot[kCellBytes * kGradThreads];
-  __shared__ unsigned int s_cnt[4];
-  __shared__ unsigned long long s_base[4];
-  __shared__ HotTables T;
+// LDS of the lower-star kernel: per-lane slot tables and the block's
+// emission counters.
+struct K3Shared {
+  __align__(16) uint8_t slot_cell[kSlotBytes * kGradThreads];
+  __align__(16) uint8_t cell_slot[kCellBytes * kGradThreads];
+  unsigned int cnt[4];
+  unsigned long long base[4];
+};
+
+__device__ __forceinline__ void load_hot_tables(HotTables& T) {
   const int tid = threadIdx.x;
-  if (tid < 4) s_cnt[tid] = 0;
   if (tid < 24) T.tet_trim[tid] = c_st.tet_trim[tid];
   if (tid < 14) T.edge_trim[tid] = c_st.edge_trim[tid];
   if (tid < 36) {
@@ -468,13 +466,26 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
   }
   if (tid < 24) T.tet_nbm[tid] = c_st.tet_nbm[tid];
   if (tid < 196) T.pair_tri[tid / 14][tid % 14] = c_st.pair_tri[tid / 14][tid % 14];
-  __syncthreads();
+}
+
+// One block's worth of lower stars: lane tid brings vertex v0 (act0: a vertex
+// to process).  Called by every thread of the block (it holds barriers).
+template <class Geo>
+__device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const Geo& G,
+                                         uint4* __restrict__ code_out,
+                                         int32_t* __restrict__ down_out, const CritOut& co,
+                                         const HotTables& T, K3Shared& sh, bool act0, int v0) {
+  const int tid = threadIdx.x;
+  uint8_t* s_slot_cell = sh.slot_cell;
+  uint8_t* s_cell_slot = sh.cell_slot;
+  unsigned int* s_cnt = sh.cnt;
+  unsigned long long* s_base = sh.base;
+  if (tid < 4) s_cnt[tid] = 0;
   uint8_t* slot_cell = s_slot_cell + tid;  // element i at [i * kGradThreads]
   uint8_t* cell_slot = s_cell_slot + tid;
 #define SLOT_CELL(i) slot_cell[(i) * kGradThreads]
 #define CELL_SLOT(i) cell_slot[(i) * kGradThreads]
 
-  const int64_t lane = int64_t(blockIdx.x) * kGradThreads + tid;
   // The lower-star loops run as often as the slowest lane of a wave needs, and
   // their trip counts grow with the number of lower neighbours.  The block's
   // vertices are therefore first sorted by that number (a counting sort in
@@ -484,8 +495,6 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
   int v;
   bool active;
   {
-    const bool act0 = kList ? lane < nlist : lane < G.total();
-    const int v0 = kList ? (act0 ? int(vlist[lane]) : 0) : int(lane);
     int key = 15;  // inactive lanes last
     if (act0) {
       const auto S0 = G.site(v0);
@@ -807,6 +816,66 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
       }
       ++p;
     }
+  }
+}
+
+// kList: lane i processes vertex vlist[i] (i < nlist) instead of vertex i.
+template <bool kList, class Geo>
+__global__ void __launch_bounds__(kGradThreads)
+k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
+           int32_t* __restrict__ down_out, CritOut co, const uint32_t* __restrict__ vlist,
+           int64_t nlist) {
+  __shared__ K3Shared sh;
+  __shared__ HotTables T;
+  load_hot_tables(T);
+  __syncthreads();
+  const int64_t lane = int64_t(blockIdx.x) * kGradThreads + threadIdx.x;
+  const bool act0 = kList ? lane < nlist : lane < G.total();
+  const int v0 = kList ? (act0 ? int(vlist[lane]) : 0) : int(lane);
+  k3_block(rank, G, code_out, down_out, co, T, sh, act0, v0);
+}
+
+// Work queue of 3D tiles for the persistent form of the lower-star kernel: the
+// tiles of field f are items tile_base[f] .. tile_base[f + 1] - 1, numbered x
+// fastest within the field; a tile holds tx * ty * tz = kGradThreads vertices.
+struct TileQueue {
+  const int4* field;          // per field: (base vertex, Lx, Ly, Lz)
+  const int64_t* tile_base;   // nf + 1 prefix counts of tiles
+  int nf;
+  int tx, ty, tz;
+  unsigned int* head;         // next item (cleared before the launch)
+  int64_t nitems;
+};
+
+// The lower-star kernel as persistent workgroups that take tiles from a
+// queue until it is empty: the hot tables are staged once per workgroup, and a
+// tile keeps the 14-neighbour stencil of its vertices within a small box.
+template <class Geo>
+__global__ void __launch_bounds__(kGradThreads)
+k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
+                 int32_t* __restrict__ down_out, CritOut co, TileQueue q) {
+  __shared__ K3Shared sh;
+  __shared__ HotTables T;
+  __shared__ int64_t s_item;
+  load_hot_tables(T);
+  const int tid = threadIdx.x;
+  const int lx = tid % q.tx, ly = (tid / q.tx) % q.ty, lz = tid / (q.tx * q.ty);
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_item = int64_t(atomicAdd(q.head, 1u));
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= q.nitems) break;  // the whole workgroup leaves together
+    int f = 0;
+    while (f + 1 < q.nf && item >= q.tile_base[f + 1]) ++f;
+    const int4 fd = q.field[f];
+    const int nbx = (fd.y + q.tx - 1) / q.tx, nby = (fd.z + q.ty - 1) / q.ty;
+    const int64_t t = item - q.tile_base[f];
+    const int bx = int(t % nbx), by = int((t / nbx) % nby), bz = int(t / (int64_t(nbx) * nby));
+    const int x = bx * q.tx + lx, y = by * q.ty + ly, z = bz * q.tz + lz;
+    const bool act0 = x < fd.y && y < fd.z && z < fd.w;
+    const int v0 = act0 ? fd.x + x + fd.y * (y + fd.z * z) : 0;
+    k3_block(rank, G, code_out, down_out, co, T, sh, act0, v0);
   }
 }
 
@@ -2547,12 +2616,71 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         ctx->timer.stop();
       }
     } else {
+      // persistent workgroups over a queue of 3D tiles; the tile shape is
+      // picked by the launch tuner per size class (every shape gives the same
+      // gradient), or fixed by TS_K3_TILE (index into the candidates)
+      static const int kTiles[6][3] = {{256, 1, 1}, {64, 4, 1}, {32, 8, 1},
+                                       {32, 4, 2}, {16, 4, 4}, {8, 8, 4}};
+      const std::string tkey = std::string(batch ? "k3.tiles.batch." : "k3.tiles.") +
+                               std::to_string(64 - __builtin_clzll(uint64_t(n) | 1));
+      int tidx = -1, shape = 0;
+      if (std::getenv("TS_K3_TILE")) {
+        shape = env_int("TS_K3_TILE", 0, 0, 5);
+      } else {
+        tidx = ctx->tuner.pick(tkey, 6);
+        shape = tidx;
+      }
+      const int tx = kTiles[shape][0], ty = kTiles[shape][1], tz = kTiles[shape][2];
+      std::vector<int4> hf;
+      std::vector<int64_t> htb(1, 0);
+      auto add_field = [&](int base, int Lx, int Ly, int Lz) {
+        hf.push_back(make_int4(base, Lx, Ly, Lz));
+        htb.push_back(htb.back() + int64_t((Lx + tx - 1) / tx) * ((Ly + ty - 1) / ty) *
+                                      ((Lz + tz - 1) / tz));
+      };
+      if (batch) {
+        for (int i = 0; i < nf; ++i)
+          add_field(int(batch->base[i]), batch->grids[i].Lx, batch->grids[i].Ly,
+                    batch->grids[i].Lz);
+      } else {
+        add_field(0, g.Lx, g.Ly, g.Lz);
+      }
+      int4* dfield = ws.get<int4>("pm.k3.fields", hf.size());
+      int64_t* dtb = ws.get<int64_t>("pm.k3.tile_base", htb.size());
+      unsigned int* dhead = ws.get<unsigned int>("pm.k3.head", 1);
+      TS_HIP(hipMemcpyAsync(dfield, hf.data(), hf.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      TS_HIP(hipMemcpyAsync(dtb, htb.data(), htb.size() * 8, hipMemcpyHostToDevice, s));
+      k_fill_u32<<<1, 1, 0, s>>>(dhead, 1, 0u);
+      TileQueue q{dfield, dtb, int(hf.size()), tx, ty, tz, dhead, htb.back()};
+      static int n_cu = 0;
+      if (!n_cu) {
+        TS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        n_cu = std::max(n_cu, 1);
+      }
+      // workgroups resident at once (the kernel's LDS allows 4 per CU)
+      const unsigned grid = unsigned(std::min<int64_t>(q.nitems, int64_t(4) * n_cu));
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (tidx >= 0) {
+        TS_HIP(hipEventCreate(&e0));
+        TS_HIP(hipEventCreate(&e1));
+        TS_HIP(hipEventRecord(e0, s));
+      }
       ctx->timer.start("K3 gradient");
-      with_geo([&](auto G) {
-        k_gradient<false><<<blocks_for(n, kGradThreads), kGradThreads, 0, s>>>(
-            R->rank, G, R->code, R->down, co, nullptr, 0);
-      });
+      if (grid > 0)
+        with_geo([&](auto G) {
+          k_gradient_tiles<<<grid, kGradThreads, 0, s>>>(R->rank, G, R->code, R->down, co, q);
+        });
       ctx->timer.stop();
+      TS_HIP(hipGetLastError());
+      if (tidx >= 0) {
+        TS_HIP(hipEventRecord(e1, s));
+        TS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ctx->tuner.report(tkey, tidx, double(ms) * 1e-3);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+      }
     }
     TS_HIP(hipGetLastError());
     unsigned long long h[4];
