@@ -219,8 +219,11 @@ def diagram_batch(fields) -> list:
     counts = np.zeros(nf, np.int64)
     nv = int(np.prod(dims.reshape(-1, 3), axis=1).sum())
     cap = max(4096, _cap_hint.get(("batch", nv), nv // 4 + 16))
+    torch = _torch()
     while True:
-        out = np.empty(cap, PAIR_DTYPE)
+        # pinned host memory: the records arrive in one full-speed copy
+        buf = torch.empty(cap * PAIR_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+        out = buf.numpy().view(PAIR_DTYPE)
         rc = lib().ts_diagram_batch(ctx, nf, ptrs, _ptr(dims), on_dev, _ptr(out), cap, _ptr(counts))
         if rc == -5:
             cap = int(counts.sum()) + 1

@@ -206,23 +206,6 @@ float* batch_field(ts_ctx* ctx, const Batch& B, const float* const* f, int on_de
   return d;
 }
 
-// Field of batch vertex v.
-int field_of(const Batch& B, int64_t v) {
-  return int(std::upper_bound(B.base.begin(), B.base.end(), v) - B.base.begin()) - 1;
-}
-
-// Batch records to field-local ids: a cell id of dimension d is a multiple of
-// the vertex id space (1, 7, 12, 6 cells per anchor vertex for d = 0..3).
-ts_pair local_record(const ts_pair& r, int64_t base) {
-  static const int64_t per[4] = {1, 7, 12, 6};
-  ts_pair q = r;
-  q.v_birth -= base;
-  q.v_death -= base;
-  q.birth_cell -= per[r.dim] * base;
-  if (q.death_cell >= 0) q.death_cell -= per[r.dim + 1] * base;
-  return q;
-}
-
 // Whether [a, a + na) and [b, b + nb) (float counts) share memory.
 bool overlaps(const float* a, int64_t na, const float* b, int64_t nb) {
   const uintptr_t a0 = uintptr_t(a), a1 = a0 + uintptr_t(na) * sizeof(float);
@@ -424,27 +407,21 @@ int ts_diagram_batch(ts_ctx* ctx, int32_t nf, const float* const* f, const int64
     Grid g{0, 0, 0, int(B.base[nf])};
     PersistenceResult R;
     compute_persistence(ctx, fd, g, &R, nullptr, &B);
-    // the batch diagram lands in pinned staging, then each record goes to its
-    // field's segment of out with field-local ids (diagram order restricted to
-    // a field is that field's own diagram order)
+    // split by field on the device (diagram order restricted to a field is
+    // that field's own diagram order), then one copy into the caller's array
     const int64_t total = R.ndiag;
-    ts_pair* P = ctx->ws.host<ts_pair>("api.batch_records", size_t(total) + 1);
-    pairs_to_host(ctx, R, fd, true, P, total);
+    ts_pair* d = ctx->ws.get<ts_pair>("api.batch_records", size_t(total) + 1);
+    batch_diagram_records(ctx, R, fd, B, d, counts);
     finish_timing(ctx);
-    std::vector<int32_t> fld(total);
-    std::fill(counts, counts + nf, int64_t(0));
-    for (int64_t r = 0; r < total; ++r) {
-      fld[r] = field_of(B, P[r].v_birth);
-      ++counts[fld[r]];
-    }
     if (total > capacity) {
       ctx->err = "capacity too small";
       return int(TS_ERR_CAPACITY);
     }
     if (!out && total > 0) throw Error(TS_ERR_ARG, "out is NULL");
-    std::vector<int64_t> at(nf + 1, 0);
-    for (int i = 0; i < nf; ++i) at[i + 1] = at[i] + counts[i];
-    for (int64_t r = 0; r < total; ++r) out[at[fld[r]]++] = local_record(P[r], B.base[fld[r]]);
+    if (total > 0)
+      TS_HIP(hipMemcpyAsync(out, d, size_t(total) * sizeof(ts_pair), hipMemcpyDeviceToHost,
+                            ctx->stream));
+    TS_HIP(hipStreamSynchronize(ctx->stream));
     return int(TS_OK);
   });
 }

@@ -74,6 +74,12 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
 void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool diagram_only,
                   ts_pair* out_dev);
 
+// The diagram of a batch split by field on the device: out_dev holds field
+// 0's records, then field 1's, ..., each in its field's diagram order and with
+// field-local ids; counts (host, nf entries) receives the sizes.
+void batch_diagram_records(ts_ctx* ctx, const PersistenceResult& R, const float* f,
+                           const Batch& B, ts_pair* out_dev, int64_t* counts);
+
 // Dense gradient partner arrays (device outputs of sizes n, 7n, 12n).
 void decode_gradient(ts_ctx* ctx, const PersistenceResult& R, int32_t* vup, int32_t* eup,
                      int32_t* tup);

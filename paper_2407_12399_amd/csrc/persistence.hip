@@ -3151,6 +3151,85 @@ void pair_records(ts_ctx* ctx, const PersistenceResult& R, const float* f, bool 
   TS_HIP(hipGetLastError());
 }
 
+namespace {
+
+// field of each record (by its birth vertex) as a sort key, the record index
+// as the payload
+__global__ void k_record_fields(const ts_pair* __restrict__ rec, int64_t n,
+                                const int64_t* __restrict__ base, int nf,
+                                uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = rec[i].v_birth;
+  int lo = 0, hi = nf - 1;  // the last field whose base is <= v
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  key[i] = uint32_t(lo);
+  val[i] = uint32_t(i);
+}
+
+// first position of each field in the sorted keys
+__global__ void k_field_starts(const uint32_t* __restrict__ key, int64_t n,
+                               int64_t* __restrict__ start) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i == 0 || key[i] != key[i - 1]) start[key[i]] = i;
+}
+
+// records in field order with field-local ids (a cell id of dimension d is
+// a multiple of the vertex id space: 1, 7, 12, 6 cells per anchor vertex)
+__global__ void k_local_records(const ts_pair* __restrict__ rec, const uint32_t* __restrict__ key,
+                                const uint32_t* __restrict__ val, int64_t n,
+                                const int64_t* __restrict__ base, ts_pair* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ts_pair r = rec[val[i]];
+  const int64_t b = base[key[i]];
+  const int64_t per[4] = {1, 7, 12, 6};
+  r.v_birth -= b;
+  r.v_death -= b;
+  r.birth_cell -= per[r.dim] * b;
+  if (r.death_cell >= 0) r.death_cell -= per[r.dim + 1] * b;
+  out[i] = r;
+}
+
+}  // namespace
+
+void batch_diagram_records(ts_ctx* ctx, const PersistenceResult& R, const float* f,
+                           const Batch& B, ts_pair* out_dev, int64_t* counts) {
+  hipStream_t s = ctx->stream;
+  Workspace& ws = ctx->ws;
+  const int nf = int(B.grids.size());
+  const int64_t n = R.ndiag;
+  ts_pair* rec = ws.get<ts_pair>("bd.records", n + 1);
+  pair_records(ctx, R, f, true, rec);
+  int64_t* dbase = ws.get<int64_t>("bd.base", nf + 1);
+  uint32_t* key = ws.get<uint32_t>("bd.key", n + 1);
+  uint32_t* val = ws.get<uint32_t>("bd.val", n + 1);
+  int64_t* start = ws.get<int64_t>("bd.start", nf + 1);
+  TS_HIP(hipMemcpyAsync(dbase, B.base.data(), size_t(nf) * 8, hipMemcpyHostToDevice, s));
+  k_fill_u64<<<blocks_for(nf + 1), 256, 0, s>>>(reinterpret_cast<uint64_t*>(start), nf + 1,
+                                               uint64_t(n));
+  if (n > 0) {
+    k_record_fields<<<blocks_for(n), 256, 0, s>>>(rec, n, dbase, nf, key, val);
+    int bits = 0;
+    while ((int64_t(1) << bits) < nf) ++bits;
+    radix_sort_u32(ws, key, val, size_t(n), 0, std::max(bits, 1), s);  // stable
+    k_field_starts<<<blocks_for(n), 256, 0, s>>>(key, n, start);
+    k_local_records<<<blocks_for(n), 256, 0, s>>>(rec, key, val, n, dbase, out_dev);
+  }
+  TS_HIP(hipGetLastError());
+  std::vector<int64_t> h(nf + 1);
+  TS_HIP(hipMemcpyAsync(h.data(), start, size_t(nf + 1) * 8, hipMemcpyDeviceToHost, s));
+  TS_HIP(hipStreamSynchronize(s));
+  h[nf] = n;
+  // every field has at least its essential class, so every start is written
+  for (int i = 0; i < nf; ++i) counts[i] = h[i + 1] - h[i];
+}
+
 void decode_gradient(ts_ctx* ctx, const PersistenceResult& R, int32_t* vup, int32_t* eup,
                      int32_t* tup) {
   hipStream_t s = ctx->stream;
