@@ -54,32 +54,35 @@ K3_BYTES_PER_VERTEX = 20
 ORDER_STAGES = ("K1 order keys", "K1 radix sort", "K2 rank")
 
 
-# HBM traffic of one k_gradient launch at 256^3, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes (KiB per dispatch), each scaled by what the same counter
-# reads for a plain 256 MiB device copy (fetch x2.0, write x1.0).  It belongs
-# to the kernel source it was measured on: a changed kernel reports null.
-K3_COUNTERS = {"source_sha1": "bc8c6567d936d94f39c2c5d8425661550676767c",
-               "dims": (256, 256, 256), "fetch_kib": 98221.3, "write_kib": 404298.2,
+# HBM traffic of one lower-star gradient launch (k_gradient_tiles) at 256^3
+# with 8x8x4 tiles, from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (KiB per
+# dispatch), each scaled by what the same counter reads for a plain 256 MiB
+# device copy (fetch x2.0, write x1.0).  It belongs to the kernel source and
+# tile shape it was measured on: another source or shape reports null.
+K3_COUNTERS = {"source_sha1": "f83154d3ec9f48f48af65411848e08902dacf49d", "tiles": (8, 8, 4),
+               "dims": (256, 256, 256), "fetch_kib": 180608.0, "write_kib": 436630.0,
                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-# SQ_INSTS_VALU / SQ_WAVES of K3 from the instruction-mix pass recorded in
-# profiles/k3_gradient_filament256_instruction_mix.md (same kernel source)
-K3_VALU_PER_WAVE = {"source_sha1": "bc8c6567d936d94f39c2c5d8425661550676767c", "valu": 19138.0}
-# untimed persistence maps before timing: the launch tuner tries 5 D1 block sizes
-WARM_MAPS = 6
+# SQ_INSTS_VALU of the same launch divided by the vertex count / 64 (wave-level
+# VALU instructions per 64 vertices; the waves are persistent, so SQ_WAVES
+# counts workgroups, not vertices)
+K3_VALU_PER_64 = {"source_sha1": "f83154d3ec9f48f48af65411848e08902dacf49d", "tiles": (8, 8, 4), "valu": 10750.6}
+# untimed persistence maps before timing: the launch tuner tries 7 K3 tile
+# shapes and 5 D1 block sizes, one per map
+WARM_MAPS = 7
 # one wave64 VALU instruction per CU per cycle (4 SIMDs x 16 lanes), 256 CUs at 2.4 GHz
 VALU_ISSUE_PEAK_G = 256 * 2.4
 
 
-def kernel_source_sha1(name="k_gradient"):
-    """sha1 of a kernel's definition text in persistence.hip."""
+def k3_source_sha1():
+    """sha1 of the lower-star gradient kernel's source in persistence.hip: its
+    LDS struct, per-block body and the persistent tile kernel."""
     import hashlib
     path = os.path.join(ROOT, "paper_2407_12399_amd", "csrc", "persistence.hip")
     s = open(path).read()
-    i = s.index("\n" + name + "(")
-    i = s.rindex("\n", 0, i - 1) + 1
-    j = s.index("\n}\n", i) + 3
+    i = s.index("struct K3Shared {")
+    j = s.index("\n}\n", s.index("\nk_gradient_tiles(")) + 3
     return hashlib.sha1(s[i:j].encode()).hexdigest()
 
 
@@ -255,7 +258,8 @@ def batch_run(ts, fields, torch, args):
             "diagram_one_by_one_wall_s": seq,
             "solver_steps": steps,
             "simplify_batch_wall_s": tb, "simplify_one_by_one_wall_s": tsq,
-            "solver_mverts_s": nv * steps / tb / 1e6}
+            "solver_mverts_s": nv * steps / tb / 1e6,
+            "launch_choices": ts.launch_choices()}
 
 
 def unet_run(ts, torch, reps=10):
@@ -372,7 +376,8 @@ def main():
         for _ in range(args.diag_reps + WARM_MAPS):
             ts.diagram_batch(fb)
         torch.cuda.synchronize()
-        print(json.dumps({"batch_maps": args.diag_reps + WARM_MAPS}))
+        print(json.dumps({"batch_maps": args.diag_reps + WARM_MAPS,
+                          "launch_choices": ts.launch_choices()}))
         return
     w = fields.WORKLOADS[WORKLOAD]
     dims = tuple(args.dims) if args.dims else w["dims"]
@@ -388,7 +393,8 @@ def main():
     # persistence map alone (device time of the persistence stages per map)
     print("[bench] persistence map", file=sys.stderr, flush=True)
     # warm-up: workspace allocation, table upload, and the launch tuner's trial
-    # maps (it tries each D1 block size once, then keeps the fastest)
+    # maps (it tries each K3 tile shape and D1 block size once, then keeps the
+    # fastest)
     for _ in range(WARM_MAPS):
         ts.diagram(ft)
     diag_stage = {}
@@ -404,7 +410,8 @@ def main():
     stage_ms = {k: float(np.median(v)) for k, v in diag_stage.items()}
     if args.diagram_only:
         print(json.dumps({"persistence_map_ms": sum(stage_ms.values()), "stage_ms": stage_ms,
-                          "wall_ms": float(np.median(wall)) * 1e3, "pairs": len(D)}))
+                          "wall_ms": float(np.median(wall)) * 1e3, "pairs": len(D),
+                          "launch_choices": ts.launch_choices()}))
         return
     pm_ms = sum(stage_ms.values())
     n_pairs = [int((D["dim"] == d).sum() - (D["essential"] if d == 0 else 0).sum())
@@ -428,14 +435,19 @@ def main():
     k3_ms = stage_ms["K3 gradient"]
     algo_bytes = K3_BYTES_PER_VERTEX * n
     achieved = algo_bytes / (k3_ms * 1e-3) / 1e9
+    k3_key = "k3.tiles.%d" % n.bit_length()
+    k3_choice = ts.launch_choices().get(k3_key, -1)
+    k3_tiles = ts.K3_TILE_SHAPES[k3_choice] if k3_choice >= 0 else None
+    k3_sha = k3_source_sha1()
     traffic = None
     c = K3_COUNTERS
-    if tuple(dims) == c["dims"] and kernel_source_sha1() == c["source_sha1"]:
+    if tuple(dims) == c["dims"] and k3_sha == c["source_sha1"] and k3_tiles == c["tiles"]:
         traffic = (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024
-    roofline = {"bound": "hbm", "kernel": "K3 gradient (k_gradient)", "achieved": achieved,
+    roofline = {"bound": "hbm", "kernel": "K3 gradient (k_gradient_tiles)", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic, "algo_bytes_per_vertex": K3_BYTES_PER_VERTEX,
-                "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": k3_ms}
+                "algo_bytes_per_launch": algo_bytes, "avg_launch_ms": k3_ms,
+                "tiles": list(k3_tiles) if k3_tiles else None}
     order_ms = sum(stage_ms.get(k, 0.0) for k in ORDER_STAGES)
     order_gbs = ORDER_BYTES_PER_VERTEX * n / (order_ms * 1e-3) / 1e9
     stage_hbm = {
@@ -445,11 +457,11 @@ def main():
         "K3 gradient": {"algo_bytes_per_vertex": K3_BYTES_PER_VERTEX, "ms": k3_ms,
                         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS}}
     k3_issue = None
-    if kernel_source_sha1() == K3_VALU_PER_WAVE["source_sha1"]:
-        rate = n / 64 * K3_VALU_PER_WAVE["valu"] / (k3_ms * 1e-3) / 1e9
+    if k3_sha == K3_VALU_PER_64["source_sha1"] and k3_tiles == K3_VALU_PER_64["tiles"]:
+        rate = n / 64 * K3_VALU_PER_64["valu"] / (k3_ms * 1e-3) / 1e9
         k3_issue = {"bound": "alu", "kernel": "K3 gradient", "achieved": rate,
                     "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-level VALU instructions/s",
-                    "frac": rate / VALU_ISSUE_PEAK_G, "valu_per_wave": K3_VALU_PER_WAVE["valu"]}
+                    "frac": rate / VALU_ISSUE_PEAK_G, "valu_per_64_vertices": K3_VALU_PER_64["valu"]}
     out = {
         "metric": "time to full non-signal cancellation (s) + persistence-map Mverts/s at 256^3",
         "value": value, "unit": "Mverts/s", "n_gpus": 1, "steps": steps,

@@ -279,10 +279,11 @@ int ts_pairs(ts_ctx* ctx, const float* f, const int64_t dims[3], int32_t on_devi
  * A point and a target with c(p,q) >= diag(p) + diag(q) are never matched.
  * The result is the exact optimum: after exact reductions, a problem of at
  * most 1000 points + targets is solved by successive shortest paths; a
- * larger one by an epsilon-scaled auction (final eps 1e-10 * W, W = max
- * diag(p) + max diag(q)) whose result is then proved optimal by
- * complementary slackness with exact duals, trading along cost-reducing
- * cycles where it is not.  TS_ERR_INTERNAL if no certificate is reached.
+ * larger one by an epsilon-scaled forward/reverse auction (final eps
+ * 1e-10 * W, W = max diag(p) + max diag(q)) whose result is then proved
+ * optimal by complementary slackness with exact duals (up to 4 ulps of the
+ * terms compared), trading along cost-reducing cycles where it is not.
+ * TS_ERR_INTERNAL if no certificate is reached.
  * Needs no context and no GPU. */
 int ts_assign(int64_t n_pts, const double* pb, const double* pd, int64_t n_tgt, const double* qb,
               const double* qd, int32_t* match, double* cost);
@@ -318,6 +319,21 @@ int ts_order_noalloc(const float* f, int64_t n, int32_t* order, int32_t* rank, v
  * measured with HIP events on the context's stream: stage_ms[i] for the
  * stage named stage_names[i] (NULL-terminated list).  Returns the count. */
 int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** ms);
+
+/* The launch tuner's choices so far.  Some launch shapes are picked by timing
+ * each candidate once on the first calls of a size class (the results do not
+ * depend on the choice); keys[i] names the launch and its size class
+ * (floor(log2 size) + 1), choices[i] is the index of the candidate in use,
+ * or -1 while candidates are still being tried:
+ *   "k3.tiles.<c>", "k3.tiles.batch.<c>" (c from the vertex count): tile
+ *       shape of the lower-star gradient, 0..5 = 256x1x1, 64x4x1, 32x8x1,
+ *       32x4x2, 16x4x4, 8x8x4 vertices, 6 = runs of 256 consecutive vertex
+ *       ids;
+ *   "d1.block.<c>" (c from the column count): block of the saddle-saddle
+ *       reduction, 0..4 = 2^16, 2^17, 2^18, 2^20, 2^24 columns.
+ * The arrays stay valid until the next call on ctx; keys is NULL-terminated.
+ * Returns the count, or TS_ERR_ARG. */
+int ts_launch_choices(ts_ctx* ctx, const char* const** keys, const int** choices);
 
 #ifdef __cplusplus
 }

@@ -73,7 +73,7 @@ EXPORTS = ["ts_create", "ts_destroy", "ts_last_error", "ts_diagram", "ts_diagram
            "ts_simplify", "ts_simplify_batch", "ts_unet_param_count", "ts_unet_forward",
            "ts_unet_backward", "ts_unet_adam",
            "ts_order", "ts_gradient", "ts_critical", "ts_pairs", "ts_assign", "ts_assign_auction",
-           "ts_stage_times", "ts_signal_mask", "ts_order_noalloc"]
+           "ts_stage_times", "ts_signal_mask", "ts_order_noalloc", "ts_launch_choices"]
 
 
 def lib():
@@ -107,6 +107,8 @@ def lib():
         L.ts_assign_auction.argtypes = [i64, P, P, i64, P, P, ctypes.c_double, P, P]
         L.ts_stage_times.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_char_p)),
                                      ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+        L.ts_launch_choices.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_char_p)),
+                                        ctypes.POINTER(ctypes.POINTER(ctypes.c_int))]
         for fn in EXPORTS:
             if fn != "ts_last_error":
                 getattr(L, fn).restype = ctypes.c_int
@@ -321,6 +323,24 @@ def stage_times():
     ms = ctypes.POINTER(ctypes.c_double)()
     k = lib().ts_stage_times(ctx, ctypes.byref(names), ctypes.byref(ms))
     return {names[i].decode(): ms[i] for i in range(max(k, 0))}
+
+
+# candidates of the tuned launches, in the library's index order ("runs":
+# runs of 256 consecutive vertex ids instead of 3D tiles)
+K3_TILE_SHAPES = ((256, 1, 1), (64, 4, 1), (32, 8, 1), (32, 4, 2), (16, 4, 4), (8, 8, 4), "runs")
+D1_BLOCK_BITS = (16, 17, 18, 20, 24)
+
+
+def launch_choices():
+    """{launch key: candidate index in use, -1 while still trying} of the
+    current context's launch tuner (keys "k3.tiles.<c>", "d1.block.<c>", ...)."""
+    ctx = context()
+    keys = ctypes.POINTER(ctypes.c_char_p)()
+    ch = ctypes.POINTER(ctypes.c_int)()
+    k = lib().ts_launch_choices(ctx, ctypes.byref(keys), ctypes.byref(ch))
+    if k < 0:
+        raise TopsimpError(k, "ts_launch_choices failed")
+    return {keys[i].decode(): ch[i] for i in range(k)}
 
 
 @dataclass

@@ -601,4 +601,20 @@ int ts_stage_times(const ts_ctx* ctx, const char* const** names, const double** 
   return int(ctx->stage_ms.size());
 }
 
+int ts_launch_choices(ts_ctx* ctx, const char* const** keys, const int** choices) {
+  if (!ctx || !keys || !choices) return TS_ERR_ARG;
+  ctx->tuner_keys_store.clear();
+  ctx->tuner_choices.clear();
+  for (const auto& kv : ctx->tuner.entries) {
+    ctx->tuner_keys_store.push_back(kv.first);
+    ctx->tuner_choices.push_back(kv.second.best);
+  }
+  ctx->tuner_keys.clear();
+  for (const auto& k : ctx->tuner_keys_store) ctx->tuner_keys.push_back(k.c_str());
+  ctx->tuner_keys.push_back(nullptr);
+  *keys = ctx->tuner_keys.data();
+  *choices = ctx->tuner_choices.data();
+  return int(ctx->tuner_choices.size());
+}
+
 }  // extern "C"

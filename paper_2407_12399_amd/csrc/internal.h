@@ -142,4 +142,7 @@ struct ts_ctx {
   std::vector<std::string> stage_names_store;
   std::vector<const char*> stage_names;
   std::vector<double> stage_ms;
+  std::vector<std::string> tuner_keys_store;
+  std::vector<const char*> tuner_keys;
+  std::vector<int> tuner_choices;
 };

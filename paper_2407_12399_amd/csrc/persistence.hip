@@ -838,6 +838,8 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
 // Work queue of 3D tiles for the persistent form of the lower-star kernel: the
 // tiles of field f are items tile_base[f] .. tile_base[f + 1] - 1, numbered x
 // fastest within the field; a tile holds tx * ty * tz = kGradThreads vertices.
+// tx == 0 instead makes item i the run of vertex ids i * kGradThreads ..
+// (i + 1) * kGradThreads - 1 over all fields (no idle lanes at field edges).
 struct TileQueue {
   const int4* field;          // per field: (base vertex, Lx, Ly, Lz)
   const int64_t* tile_base;   // nf + 1 prefix counts of tiles
@@ -859,13 +861,21 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
   __shared__ int64_t s_item;
   load_hot_tables(T);
   const int tid = threadIdx.x;
-  const int lx = tid % q.tx, ly = (tid / q.tx) % q.ty, lz = tid / (q.tx * q.ty);
+  const bool runs = q.tx == 0;
+  const int tx = runs ? 1 : q.tx, ty = runs ? 1 : q.ty;
+  const int lx = tid % tx, ly = (tid / tx) % ty, lz = tid / (tx * ty);
   for (;;) {
     __syncthreads();
     if (tid == 0) s_item = int64_t(atomicAdd(q.head, 1u));
     __syncthreads();
     const int64_t item = s_item;
     if (item >= q.nitems) break;  // the whole workgroup leaves together
+    if (runs) {
+      const int64_t v = item * kGradThreads + tid;
+      const bool act = v < G.total();
+      k3_block(rank, G, code_out, down_out, co, T, sh, act, act ? int(v) : 0);
+      continue;
+    }
     int f = 0;
     while (f + 1 < q.nf && item >= q.tile_base[f + 1]) ++f;
     const int4 fd = q.field[f];
@@ -2616,18 +2626,19 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         ctx->timer.stop();
       }
     } else {
-      // persistent workgroups over a queue of 3D tiles; the tile shape is
-      // picked by the launch tuner per size class (every shape gives the same
+      // persistent workgroups over a queue of 3D tiles (or of runs of
+      // consecutive vertex ids, the last candidate); the shape is picked by
+      // the launch tuner per size class (every shape gives the same
       // gradient), or fixed by TS_K3_TILE (index into the candidates)
-      static const int kTiles[6][3] = {{256, 1, 1}, {64, 4, 1}, {32, 8, 1},
-                                       {32, 4, 2}, {16, 4, 4}, {8, 8, 4}};
+      static const int kTiles[7][3] = {{256, 1, 1}, {64, 4, 1}, {32, 8, 1}, {32, 4, 2},
+                                       {16, 4, 4},  {8, 8, 4},  {0, 0, 0}};
       const std::string tkey = std::string(batch ? "k3.tiles.batch." : "k3.tiles.") +
                                std::to_string(64 - __builtin_clzll(uint64_t(n) | 1));
       int tidx = -1, shape = 0;
       if (std::getenv("TS_K3_TILE")) {
-        shape = env_int("TS_K3_TILE", 0, 0, 5);
+        shape = env_int("TS_K3_TILE", 0, 0, 6);
       } else {
-        tidx = ctx->tuner.pick(tkey, 6);
+        tidx = ctx->tuner.pick(tkey, 7);
         shape = tidx;
       }
       const int tx = kTiles[shape][0], ty = kTiles[shape][1], tz = kTiles[shape][2];
@@ -2638,7 +2649,10 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         htb.push_back(htb.back() + int64_t((Lx + tx - 1) / tx) * ((Ly + ty - 1) / ty) *
                                       ((Lz + tz - 1) / tz));
       };
-      if (batch) {
+      if (tx == 0) {
+        hf.push_back(make_int4(0, 0, 0, 0));
+        htb.push_back((n + kGradThreads - 1) / kGradThreads);
+      } else if (batch) {
         for (int i = 0; i < nf; ++i)
           add_field(int(batch->base[i]), batch->grids[i].Lx, batch->grids[i].Ly,
                     batch->grids[i].Lz);

@@ -743,46 +743,6 @@ struct KDTree {
   }
 };
 
-// Prices that only rise, with the lowest price (the lowest id among equal
-// ones) and the second lowest price at hand: a binary heap ordered by
-// (price, id) that knows where every id sits, so that a raised price sinks
-// from its own slot (a raised minimum, the common case in an auction, stops
-// as soon as it passes the next cheapest prices).
-struct RisingMinHeap {
-  std::vector<double> p;     // slot -> price
-  std::vector<int> id, pos;  // slot -> id, id -> slot
-  int n = 0;
-  void build(int count) {  // every price 0: the id order is a valid heap
-    n = count;
-    p.assign(n, 0.0);
-    id.resize(n);
-    pos.resize(n);
-    for (int i = 0; i < n; ++i) id[i] = pos[i] = i;
-  }
-  bool before(int a, int b) const { return p[a] < p[b] || (p[a] == p[b] && id[a] < id[b]); }
-  void raise(int i, double v) {  // v is at least the current price of i
-    int sl = pos[i];
-    p[sl] = v;
-    for (;;) {
-      int c = 2 * sl + 1;
-      if (c >= n) break;
-      if (c + 1 < n && before(c + 1, c)) ++c;
-      if (!before(c, sl)) break;
-      std::swap(p[sl], p[c]);
-      std::swap(id[sl], id[c]);
-      pos[id[sl]] = sl;
-      pos[id[c]] = c;
-      sl = c;
-    }
-  }
-  int min_id() const { return n > 0 ? id[0] : -1; }
-  double min_price() const { return n > 0 ? p[0] : std::numeric_limits<double>::infinity(); }
-  double second_price() const {  // the second smallest sits below the root
-    if (n < 2) return std::numeric_limits<double>::infinity();
-    return n > 2 ? std::min(p[1], p[2]) : p[1];
-  }
-};
-
 // Optimality certificate for an assignment of the square augmented problem
 // (min-cost form).  Persons are the points 0..m-1 and one diagonal copy per
 // target (m + j); objects are the targets 0..k-1 and one diagonal copy per
@@ -802,7 +762,10 @@ struct RisingMinHeap {
 // that set the new price, and a cycle among those records has negative total
 // cost (Bellman-Ford predecessor graphs), so the persons on it trade along
 // it, which lowers the total cost, and the checks go on.  A person counts as
-// above its minimum by more than 4 ulps of the values compared only.
+// above its minimum only by more than 4 ulps of the terms of the two values
+// compared (|cost| + |price| of its object and of the minimising one), the
+// size of their rounding: with prices of either sign a sum can cancel far
+// below its terms.
 struct Certificate {
   int64_t lowerings = 0, trades = 0;
   bool ok = false;
@@ -826,9 +789,10 @@ Certificate certify_assignment(const std::vector<double>& pb, const std::vector<
     const int j = x - m;
     return o < k ? (o == j ? dq[j] : INF) : 0.0;
   };
-  auto slack_tol = [](double a, double b) {
-    return 4.0 * std::numeric_limits<double>::epsilon() * std::max(std::fabs(a), std::fabs(b)) +
-           1e-300;
+  auto slack_tol = [&](int x, int o, int arg) {
+    const double a = std::fabs(cost(x, o)) + std::fabs(price[o]);
+    const double b = arg >= 0 ? std::fabs(cost(x, arg)) + std::fabs(price[arg]) : 0.0;
+    return 4.0 * std::numeric_limits<double>::epsilon() * std::max(a, b) + 1e-300;
   };
   std::vector<double> lam(NP);
   for (int x = 0; x < NP; ++x) lam[x] = cost(x, holds[x]) + price[holds[x]];
@@ -950,8 +914,8 @@ Certificate certify_assignment(const std::vector<double>& pb, const std::vector<
     int arg;
     const double mu = minimum(x, &arg);
     if (x >= m) tcl.push({lam[x], x});  // keep it findable by lam
-    if (!(mu < lam[x] - slack_tol(mu, lam[x]))) continue;
     const int o = holds[x];
+    if (!(mu < lam[x] - slack_tol(x, o, arg))) continue;
     if (arg == o) continue;  // cannot happen with exact minima; be safe
     price[o] = mu - cost(x, o);
     from[o] = arg;
@@ -1001,15 +965,26 @@ Certificate certify_assignment(const std::vector<double>& pb, const std::vector<
 
 }  // namespace
 
-// Forward auction with epsilon scaling (Bertsekas) on the square augmented
-// problem: persons are the points and one diagonal copy per target, objects
-// are the targets and one diagonal copy per point; a point values target j
-// at -c(p,q_j) and its own diagonal copy at -diag(p); the diagonal copy of
-// target j values target j at -diag(q_j) and every point's diagonal copy at
-// 0.  Bids use the KD-tree (best and second-best target) and a rising-price
-// heap of the diagonal copies' prices.  The final assignment is within
-// (m + k) * eps_final of the optimum; in exact mode (gap_rel == 0) it is then
-// certified optimal (certify_assignment).
+// Auction on the rectangular form of the problem.  Sending every target to
+// the diagonal costs sum diag(q); from there, point p pays
+// c'(p,q) = c(p,q) - diag(q) for taking target q (at most one point per
+// target) or diag(p) for its own diagonal.  Persons are the points, objects
+// the targets (prices pi_q >= 0) and each point's private diagonal (no
+// price).  Complementary slackness asks every point to hold a cheapest
+// option (cost plus price) and every target nobody holds to have price 0.
+// Forward bids (Bertsekas) raise the price of a point's best target by the gap
+// to its second best option plus eps.  Prices carry over between the phases of
+// epsilon scaling, so a target may end a phase with no holder and a positive
+// price: it then makes reverse bids, offering itself to the point that gains
+// most from it at the price the second such point would pay (less eps), or
+// dropping to price 0 when no point gains more than eps.  Forward bids end
+// with every point within eps of its cheapest option, reverse bids keep that
+// and end with every unheld target at price 0.  Bids use KD-trees over the
+// targets (score diag(q) - pi_q) and over the points (score: what each pays).
+// In exact mode (gap_rel == 0) the final state, written as one of the square
+// augmented problem, is then certified optimal (certify_assignment); with
+// gap_rel > 0 the phases stop once the assignment's total is within
+// (1 + gap_rel)^2 of the dual lower bound, with no certificate.
 double assign_auction(const std::vector<double>& pb, const std::vector<double>& pd,
                       const std::vector<double>& qb, const std::vector<double>& qd,
                       std::vector<int>* match, double eps_rel, double gap_rel) {
@@ -1020,124 +995,138 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
   for (int i = 0; i < m; ++i) maxdp = std::max(maxdp, dp[i] = diag_cost(pb[i], pd[i]));
   for (int j = 0; j < k; ++j) maxdq = std::max(maxdq, dq[j] = diag_cost(qb[j], qd[j]));
   const double W = std::max(maxdp + maxdq, 1e-300);
-  const int NP = m + k;  // persons: points 0..m-1, target copies m..m+k-1
-  // objects: targets 0..k-1, point copies k..k+m-1
-  std::vector<double> price(k + m, 0.0);
-  std::vector<int> owner(k + m, -1), holds(NP, -1);
-  KDTree tree;
-  tree.build(qb.data(), qd.data(), k);
-  {
-    std::vector<double> sc(k, 0.0);
-    tree.set_all(sc);  // s_j = -price_j
-  }
-  RisingMinHeap copies;  // prices of the points' diagonal copies
-  copies.build(m);
-  auto two_cheapest = [&](int* i1, double* p1, double* p2) {
-    *i1 = copies.min_id();
-    *p1 = copies.min_price();
-    *p2 = copies.second_price();
+  const bool trace = std::getenv("TS_TRACE") != nullptr;
+  std::vector<double> pi(dq);     // target prices, started at diag(q)
+  std::vector<int> owner(k, -1);  // target -> point
+  std::vector<int> holds(m, -1);  // point -> target, or k for its diagonal
+  std::vector<double> pay(m, 0.0);  // what each point pays for its holding
+  KDTree tt;
+  tt.build(qb.data(), qd.data(), k);
+  tt.set_all(std::vector<double>(k, 0.0));  // diag(q) - pi_q
+  KDTree pt;
+  pt.build(pb.data(), pd.data(), m);
+  std::vector<int> hints(2 * size_t(std::max(m, 1)), -1), rhints(2 * size_t(std::max(k, 1)), -1);
+  auto cprime = [&](int i, int j) { return pair_cost(pb[i], pd[i], qb[j], qd[j]) - dq[j]; };
+  auto set_price = [&](int j, double v) {
+    pi[j] = v;
+    tt.update(j, dq[j] - v, false);
   };
-  std::vector<int> hints(2 * size_t(m), -1);  // each point's last best and second-best targets
   double eps = W / 4.0;
   const double eps_final = W * eps_rel;
-  std::vector<int> queue;
-  queue.reserve(NP);
+  const int64_t bid_cap = int64_t(400) * (m + k) + 1000000;
+  std::vector<int> queue, rqueue;
   for (int phase = 0;; ++phase) {
     std::fill(owner.begin(), owner.end(), -1);
     std::fill(holds.begin(), holds.end(), -1);
     queue.clear();
-    for (int x = 0; x < NP; ++x) queue.push_back(x);
-    size_t head = 0;
-    int64_t bids = 0;
-    while (head < queue.size()) {
-      const int x = queue[head++];
-      if (holds[x] >= 0) continue;
-      double v1, v2;  // best and second-best values
-      int o1;
-      if (x < m) {
-        double c1, c2;
-        const int j = tree.best2(pb[x], pd[x], &c1, &c2, &hints[2 * size_t(x)]);  // c = |p-q|^2 + price
-        const double vd = -dp[x] - price[k + x];
-        v1 = vd;
-        o1 = k + x;
-        v2 = -std::numeric_limits<double>::infinity();
-        if (j >= 0) {
-          if (-c1 > vd || (-c1 == vd && j < k + x)) {
-            v1 = -c1;
-            o1 = j;
-            v2 = std::max(vd, -c2);
-          } else {
-            v2 = -c1;
-          }
-        }
-      } else {
-        const int j = x - m;
-        int i1;
-        double p1, p2;
-        two_cheapest(&i1, &p1, &p2);
-        const double vt = -dq[j] - price[j];
-        if (i1 >= 0 && -p1 > vt) {
-          v1 = -p1;
-          o1 = k + i1;
-          v2 = std::max(vt, -p2);
-        } else {
-          v1 = vt;
-          o1 = j;
-          v2 = i1 >= 0 ? -p1 : -std::numeric_limits<double>::infinity();
-        }
+    for (int i = 0; i < m; ++i) queue.push_back(i);
+    int64_t fbids = 0, rbids = 0;
+    for (size_t head = 0; head < queue.size(); ++head) {
+      const int i = queue[head];
+      double c1, c2;  // the two smallest c' + pi over the targets
+      const int j = tt.best2(pb[i], pd[i], &c1, &c2, &hints[2 * size_t(i)]);
+      if (++fbids > bid_cap) throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
+      if (j < 0 || dp[i] <= c1) {  // its diagonal (ties go to the diagonal)
+        holds[i] = k;
+        pay[i] = dp[i];
+        continue;
       }
-      if (v2 == -std::numeric_limits<double>::infinity()) v2 = v1 - W;
-      const double inc = (v1 - v2) + eps;
-      price[o1] += inc;
-      if (o1 < k) tree.update(o1, -price[o1], false);
-      else copies.raise(o1 - k, price[o1]);
-      const int prev = owner[o1];
-      owner[o1] = x;
-      holds[x] = o1;
+      set_price(j, pi[j] + (std::min(c2, dp[i]) - c1) + eps);
+      const int prev = owner[j];
+      owner[j] = i;
+      holds[i] = j;
+      pay[i] = cprime(i, j) + pi[j];
       if (prev >= 0) {
         holds[prev] = -1;
         queue.push_back(prev);
       }
-      if (++bids > int64_t(400) * NP + 1000000)
-        throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
     }
-    if (std::getenv("TS_TRACE"))
-      std::fprintf(stderr, "[topsimp] auction phase %d eps %.3g bids %lld\n", phase, eps,
-                   (long long)bids);
+    rqueue.clear();
+    for (int j = 0; j < k; ++j)
+      if (owner[j] < 0 && pi[j] > 0) rqueue.push_back(j);
+    if (!rqueue.empty()) {
+      pt.set_all(pay);
+      for (size_t head = 0; head < rqueue.size(); ++head) {
+        const int j = rqueue[head];
+        if (owner[j] >= 0 || !(pi[j] > 0)) continue;
+        if (++rbids > bid_cap) throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
+        double v1, v2;  // the two smallest |p - q|^2 - pay_p over the points
+        const int i1 = pt.best2(qb[j], qd[j], &v1, &v2, &rhints[2 * size_t(j)]);
+        const double g1 = dq[j] - v1, g2 = dq[j] - v2;  // pay_p - c'(p, q)
+        if (i1 < 0 || g1 <= eps) {
+          set_price(j, 0.0);
+          continue;
+        }
+        set_price(j, std::max(0.0, std::min(pi[j], g2 - eps)));
+        const int old = holds[i1];
+        owner[j] = i1;
+        holds[i1] = j;
+        pay[i1] = cprime(i1, j) + pi[j];
+        pt.update(i1, pay[i1], false);
+        if (old < k) {
+          owner[old] = -1;
+          if (pi[old] > 0) rqueue.push_back(old);
+        }
+      }
+    }
+    if (trace)
+      std::fprintf(stderr, "[topsimp] auction phase %d eps %.3g bids %lld forward, %lld reverse\n",
+                   phase, eps, (long long)fbids, (long long)rbids);
     if (eps <= eps_final) break;
     if (gap_rel > 0) {
-      // Dual bound of the square problem (benefits a = -cost, prices p):
-      // optimum <= sum of profits + sum of prices, so cost >= -(that).
-      double dual = 0, primal = 0, dmin = std::numeric_limits<double>::infinity();
-      for (int i = 0; i < m; ++i) dmin = std::min(dmin, price[k + i]);
-      for (int o = 0; o < k + m; ++o) dual += price[o];
+      // dual bound: for prices pi >= 0 and u_p = the cheapest option of p,
+      // every assignment costs at least sum diag(q) + sum u_p - sum pi_q
+      double primal = 0, lower = 0;
+      for (int j = 0; j < k; ++j) {
+        lower += dq[j] - pi[j];
+        if (owner[j] < 0) primal += dq[j];
+      }
       for (int i = 0; i < m; ++i) {
         double val;
-        const int j = tree.best(pb[i], pd[i], &val, hints[2 * size_t(i)]);  // min_j c_ij + p_j
-        double prof = -dp[i] - price[k + i];
-        if (j >= 0) prof = std::max(prof, -val);
-        dual += prof;
-        const int o = holds[i];
-        primal += o < k ? pair_cost(pb[i], pd[i], qb[o], qd[o]) : dp[i];
+        const int j = tt.best(pb[i], pd[i], &val, hints[2 * size_t(i)]);
+        lower += j >= 0 ? std::min(dp[i], val) : dp[i];
+        primal += holds[i] < k ? pair_cost(pb[i], pd[i], qb[holds[i]], qd[holds[i]]) : dp[i];
       }
-      for (int j = 0; j < k; ++j) {
-        dual += std::max(-dq[j] - price[j], m > 0 ? -dmin : -std::numeric_limits<double>::infinity());
-        if (holds[m + j] == j) primal += dq[j];
-      }
-      const double lower = -dual;
-      if (std::getenv("TS_TRACE"))
+      if (trace)
         std::fprintf(stderr, "[topsimp] auction phase %d total %.9g lower bound %.9g\n", phase,
                      primal, lower);
       if (lower > 0 && primal <= (1 + gap_rel) * (1 + gap_rel) * lower) break;
     }
     eps = std::max(eps / 4.0, eps_final);  // a factor of 4 needs the fewest bids on noisy diagrams
   }
+  // the state as one of the square problem: target j at price pi_j - diag(q_j)
+  // and the point copies at 0, except that a point on its diagonal may pay up
+  // to its margin for its own copy (that headroom keeps the certificate's
+  // lowerings local); a target copy holds its target when no point does,
+  // else the copy of a point that holds a target
+  std::vector<int> sholds(m + k, -1);
+  std::vector<double> price(k + m, 0.0);
+  for (int j = 0; j < k; ++j) price[j] = pi[j] - dq[j];
+  std::vector<int> spare;
+  for (int i = 0; i < m; ++i) {
+    if (holds[i] < k) {
+      sholds[i] = holds[i];
+      spare.push_back(k + i);
+    } else {
+      sholds[i] = k + i;
+    }
+  }
+  for (int j = 0, s = 0; j < k; ++j) sholds[m + j] = owner[j] < 0 ? j : spare[s++];
   if (gap_rel == 0) {
-    // exact mode: prove the assignment optimal, trading along cycles where
-    // it is not (the auction alone is only within (m + k) * eps)
+    tt.set_all([&] {
+      std::vector<double> sc(k);
+      for (int j = 0; j < k; ++j) sc[j] = -price[j];
+      return sc;
+    }());
+    for (int i = 0; i < m; ++i) {
+      if (holds[i] < k) continue;
+      double v1, v2;
+      int h[2] = {-1, -1};
+      if (tt.best2(pb[i], pd[i], &v1, &v2, h) >= 0 && v1 - dp[i] > 0) price[k + i] = v1 - dp[i];
+    }
     const double tc = now_s();
-    const Certificate c = certify_assignment(pb, pd, qb, qd, dp, dq, &price, &holds);
-    if (std::getenv("TS_TRACE"))
+    const Certificate c = certify_assignment(pb, pd, qb, qd, dp, dq, &price, &sholds);
+    if (trace)
       std::fprintf(stderr, "[topsimp] certificate %s: %lld lowerings, %lld trades, %.3f s\n",
                    c.ok ? "ok" : "not reached", (long long)c.lowerings, (long long)c.trades,
                    now_s() - tc);
@@ -1146,7 +1135,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
   double total = 0;
   std::vector<char> used(k, 0);
   for (int i = 0; i < m; ++i) {
-    const int o = holds[i];
+    const int o = sholds[i];
     if (o < k && pair_cost(pb[i], pd[i], qb[o], qd[o]) < dp[i] + dq[o]) {
       (*match)[i] = o;
       used[o] = 1;
@@ -1404,12 +1393,16 @@ double assign_reduced(const std::vector<double>& pb, const std::vector<double>& 
     for (size_t t = 0; t < keep.size(); ++t) kept[t] = mine[keep[t]];
     mine.swap(kept);
   };
+  const double t_red = now_s();
   prune(0);
   prune(1);
   if (!cols.empty() && int64_t(rows.size()) > 4 * int64_t(cols.size()))
     top_k(0);  // few targets
   else if (!rows.empty() && int64_t(cols.size()) > 4 * int64_t(rows.size()))
     top_k(1);  // few points
+  if (std::getenv("TS_TRACE"))
+    std::fprintf(stderr, "[topsimp] assignment reductions: %d x %d -> %zu x %zu, %.3f s\n", m, k,
+                 rows.size(), cols.size(), now_s() - t_red);
 
   const std::vector<double> rb = gather(pb, rows), rd = gather(pd, rows);
   const std::vector<double> cb = gather(qb, cols), cd = gather(qd, cols);

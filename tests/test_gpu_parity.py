@@ -73,6 +73,21 @@ def test_gradient_bit_exact(gpu, orc, dims, seed, kind):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("shape", range(7))
+def test_gradient_every_tile_shape(gpu, orc, monkeypatch, shape):
+    """Every candidate launch shape of the lower-star kernel (3D tiles and
+    runs of consecutive ids) gives the oracle's gradient, alone and in a
+    batch of uneven fields whose edges cut the tiles."""
+    monkeypatch.setenv("TS_K3_TILE", str(shape))
+    for dims, seed in [((23, 19, 17), 6), ((33, 2, 9), 7), ((70, 9, 13), 8)]:
+        f = _rand(dims, seed, "ties")
+        for a, b in zip(gpu.gradient(_t(f)), orc.gradient(f)):
+            assert np.array_equal(a, b)
+    fs = _uneven_batch(5, 2, 21, shape)
+    for d, f in zip(gpu.diagram_batch([_t(f) for f in fs]), fs):
+        _same_pairs(d, orc.diagram(f))
+
+
 def test_gradient_2x2x2_orders(gpu, orc):
     rng = np.random.default_rng(0)
     perms = list(itertools.permutations(range(8)))
@@ -402,12 +417,17 @@ def test_batch_edges(gpu, orc):
 
 
 def test_autotuned_launches_same_result(gpu, orc):
-    """The first maps of a size class try each D1 block size in turn, later
-    ones use the fastest: every map gives the oracle's diagram."""
+    """The first maps of a size class try each K3 tile shape and D1 block size
+    in turn, later ones use the fastest: every map gives the oracle's diagram."""
     f = fields.gaussian_mixture((50, 47, 45), 64, 0.1, 13)
     want = orc.diagram(f)
-    for _ in range(6):
+    k3_key = "k3.tiles.%d" % f.size.bit_length()
+    for _ in range(len(gpu.K3_TILE_SHAPES)):
         _same_pairs(gpu.diagram(_t(f)), want)
+    # every K3 candidate tried once: the choice is made by now
+    ch = gpu.launch_choices()
+    assert 0 <= ch[k3_key] < len(gpu.K3_TILE_SHAPES)
+    assert all(-1 <= v < len(gpu.K3_TILE_SHAPES) for v in ch.values())
 
 
 def test_deterministic(gpu):
