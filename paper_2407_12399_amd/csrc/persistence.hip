@@ -1383,6 +1383,11 @@ struct LaneHeap {
   uint32_t* ref;
   int64_t stride;
   int len, cap;
+  __device__ static bool leader() { return true; }
+  __device__ void clear() { len = 0; }
+  __device__ int size() const { return len; }
+  __device__ uint64_t top_key() const { return key[0]; }
+  __device__ uint32_t top_ref() const { return ref[0]; }
   __device__ uint64_t k(int j) const { return key[int64_t(j) * stride]; }
   __device__ bool push(uint64_t kk, uint32_t rr) {
     if (len >= cap) return false;
@@ -1433,13 +1438,14 @@ struct LaneHeap {
 
 // toggle r in the ascending row list rows[0..*len) (interleaved); false on overflow
 __device__ __forceinline__ bool toggle_row(uint32_t* rows, int64_t stride, int* len, int cap,
-                                           uint32_t r) {
+                                           uint32_t r, int* moved) {
   int lo = 0, hi = *len;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (rows[int64_t(mid) * stride] < r) lo = mid + 1;
     else hi = mid;
   }
+  *moved += *len - lo;
   if (lo < *len && rows[int64_t(lo) * stride] == r) {
     for (int i = lo; i + 1 < *len; ++i) rows[int64_t(i) * stride] = rows[int64_t(i + 1) * stride];
     --*len;
@@ -1477,6 +1483,7 @@ struct BoundaryCommon {
   int* err;
   unsigned long long* stats;
   int max_steps;
+  int wave_cap;  // queue capacity of the wave kernel (<= 256)
 };
 
 template <class Geo>
@@ -1492,9 +1499,143 @@ struct BoundaryArgs : BoundaryCommon {
 // with h the higher vertex and k the star index of o.  A column whose heap or
 // row list overflows, or that needs more than max_steps pops, is appended to
 // the retry list and left unwritten.
-template <class Geo>
-__device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap& H, uint32_t* Rows,
-                                int64_t rstride, int rcap) {
+// Cross-lane moves of the wave queue: DPP wave shifts (lane i takes lane
+// i + 1, or i - 1) with the lane that has no source taking `in`, and reads of
+// one lane's value.
+__device__ __forceinline__ uint32_t wave_down(uint32_t v, uint32_t in) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(in), int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t wave_up(uint32_t v, uint32_t in) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(in), int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
+  return uint32_t(__builtin_amdgcn_readlane(int(v), lane));
+}
+
+// A max-priority queue of up to 256 (key, ref) entries held by one wave in
+// registers, sorted descending over the index i = 64 j + lane (4 entries a
+// lane; empty entries have key 0, below every edge key).  Every lane makes
+// every call, and the values returned are the same in all lanes.  A pop
+// shifts the whole list down by one place and a push finds its place with
+// four ballots and shifts the tail up: a few dozen VALU instructions instead
+// of a chain of dependent LDS accesses per heap level.
+struct WaveList {
+  static constexpr int kCap = 256;
+  uint32_t khi[4], klo[4], r[4];
+  int n;
+  int lane;
+  int cap = kCap;  // may be set lower (tests of the fallback)
+  __device__ static bool leader() { return (threadIdx.x & 63) == 0; }
+  __device__ static uint64_t join(uint32_t hi, uint32_t lo) { return (uint64_t(hi) << 32) | lo; }
+  __device__ void clear() {
+    lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) khi[j] = klo[j] = r[j] = 0;
+    n = 0;
+  }
+  __device__ int size() const { return n; }
+  __device__ uint64_t top_key() const { return join(lane_value(khi[0], 0), lane_value(klo[0], 0)); }
+  __device__ uint32_t top_ref() const { return lane_value(r[0], 0); }
+  __device__ void pop(uint64_t* kk, uint32_t* rr) {
+    *kk = top_key();
+    *rr = top_ref();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // entry i takes entry i + 1
+      const uint32_t ch = j < 3 ? lane_value(khi[j + 1], 0) : 0u;
+      const uint32_t cl = j < 3 ? lane_value(klo[j + 1], 0) : 0u;
+      const uint32_t cr = j < 3 ? lane_value(r[j + 1], 0) : 0u;
+      khi[j] = wave_down(khi[j], ch);
+      klo[j] = wave_down(klo[j], cl);
+      r[j] = wave_down(r[j], cr);
+    }
+    --n;
+  }
+  __device__ bool push(uint64_t kk, uint32_t rr) {
+    if (n >= cap) return false;
+    int p = 0;  // entries above the new one
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p += __popcll(__ballot(join(khi[j], klo[j]) > kk));
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {  // entry i > p takes entry i - 1
+      const uint32_t ch = j > 0 ? lane_value(khi[j - 1], 63) : 0u;
+      const uint32_t cl = j > 0 ? lane_value(klo[j - 1], 63) : 0u;
+      const uint32_t cr = j > 0 ? lane_value(r[j - 1], 63) : 0u;
+      const uint32_t uh = wave_up(khi[j], ch), ul = wave_up(klo[j], cl), ur = wave_up(r[j], cr);
+      const int i = 64 * j + lane;
+      if (i > p) {
+        khi[j] = uh;
+        klo[j] = ul;
+        r[j] = ur;
+      } else if (i == p) {
+        khi[j] = uint32_t(kk >> 32);
+        klo[j] = uint32_t(kk);
+        r[j] = rr;
+      }
+    }
+    ++n;
+    return true;
+  }
+};
+
+// Neighbour ranks of a vertex group's higher vertex h, as the expansion of
+// an edge (h, o) needs the rank of its third vertex, a lower neighbour of h.
+// RanksDirect loads each when needed.  RanksWave loads the gradient code and
+// the 14 neighbour ranks of a vertex in one round trip (lane j holds
+// neighbour j; indices are clamped into the rank array and only the lower
+// neighbours' ranks, which are in the grid, are used), and loads the next
+// group's ahead (hint) while the current group is expanded.
+template <class Site>
+struct RanksDirect {
+  const int32_t* rank;
+  const uint4* code;
+  Site S;
+  int h = -1;
+  __device__ RanksDirect(const int32_t* r, const uint4* c, const Site& s, int) : rank(r), code(c), S(s) {}
+  __device__ uint4 start(int v) {
+    h = v;
+    return code[v];
+  }
+  __device__ uint32_t get(int k2) const { return uint32_t(rank[h + S.nb(k2)]); }
+  __device__ void hint(int) {}
+};
+
+template <class Site>
+struct RanksWave {
+  const int32_t* rank;
+  const uint4* code;
+  Site S;
+  int last;       // last index of the rank array
+  uint32_t cur;   // this lane's neighbour rank of the current vertex
+  int pf_v = -1;  // vertex loaded ahead
+  uint4 pf_code;
+  uint32_t pf_r;
+  __device__ RanksWave(const int32_t* r, const uint4* c, const Site& s, int l)
+      : rank(r), code(c), S(s), last(l) {}
+  __device__ void load(int v) {
+    const int lane = threadIdx.x & 63;
+    int off = 0;
+#pragma unroll
+    for (int j = 0; j < 14; ++j)
+      if (lane == j) off = S.nb(j);
+    pf_v = v;
+    pf_code = code[v];
+    pf_r = uint32_t(rank[min(max(v + off, 0), last)]);
+  }
+  __device__ uint4 start(int v) {
+    if (pf_v != v) load(v);
+    cur = pf_r;
+    pf_v = -1;
+    return pf_code;
+  }
+  __device__ uint32_t get(int k2) const { return __shfl(cur, k2); }
+  __device__ void hint(int v) {
+    if (v != pf_v) load(v);
+  }
+};
+
+template <bool kWave, class Q, class Geo>
+__device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, Q& H,
+                                                uint32_t* Rows, int64_t rstride, int rcap) {
   const uint32_t ti = A.cols[c];
   const int id = A.tri_ids[ti];
   const int y = A.order[A.tri_keys[ti] >> 12];
@@ -1507,7 +1648,7 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
   const int p = mask == 0 ? 0 : (mask == c_st.tri_chain[type][1] ? 1 : 2);
   const int lt = c_st.tri_local[type][p];
   const int ka = c_st.tri_nb[lt][0], kb = c_st.tri_nb[lt][1];
-  H.len = 0;
+  H.clear();
   int rl = 0;
   // the three edges of the triangle (y is its highest vertex)
   const uint32_t ry = uint32_t(A.rank[y]);
@@ -1520,22 +1661,27 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
     const int kk = c_st.nb_diff[a_hi ? ka : kb][a_hi ? kb : ka];
     ok = H.push((uint64_t(a_hi ? ra : rb) << 32) | (a_hi ? rb : ra), (uint32_t(hv) << 4) | uint32_t(kk));
   }
-  int steps = 0, maxlen = H.len;
+  int steps = 0, maxlen = H.size();
+  int toggles = 0, moved = 0, groups = 0, expands = 0;  // diagnostics
   // edges leave the heap grouped by their higher vertex (it is the high part
   // of the key): the vertex's gradient code is loaded once per group
   int code_v = -1;
   uint4 code_h = make_uint4(0, 0, 0, 0);
-  while (ok && H.len > 0) {
+  using Site = decltype(S);
+  typename std::conditional<kWave, RanksWave<Site>, RanksDirect<Site>>::type N(
+      A.rank, A.code, S, A.G.total() - 1);
+  const bool lead = Q::leader();
+  while (ok && H.size() > 0) {
     if (++steps > A.max_steps) {
       ok = false;
       break;
     }
-    maxlen = max(maxlen, H.len);
+    maxlen = max(maxlen, H.size());
     uint64_t key;
     uint32_t ref;
     H.pop(&key, &ref);
     int copies = 1;
-    while (H.len > 0 && H.k(0) == key) {
+    while (H.size() > 0 && H.top_key() == key) {
       uint64_t k2;
       uint32_t r2;
       H.pop(&k2, &r2);
@@ -1545,7 +1691,12 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
     const int h = int(ref >> 4), k = int(ref & 15u);
     if (h != code_v) {
       code_v = h;
-      code_h = A.code[h];
+      ++groups;
+      code_h = N.start(h);
+    }
+    if (H.size() > 0) {
+      const int nh = int(H.top_ref() >> 4);
+      if (nh != h) N.hint(nh);
     }
     const uint32_t ec = edge_code(code_h, k);
     if (ec == 7u) continue;  // paired with its vertex: the path ends
@@ -1554,12 +1705,13 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
       const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
       const int64_t f = crit_pos(A.edge_pos_of, A.edge_ids, A.nedges, eid);
       if (f < 0) {
-        atomicOr(A.err, 16);
+        if (lead) atomicOr(A.err, 16);
         continue;
       }
       const uint32_t row = uint32_t(f);
       if (A.edge_state[row] != 1) continue;  // dies in dimension 0: dropped
-      if (!toggle_row(Rows, rstride, &rl, rcap, row)) {
+      ++toggles;
+      if (!toggle_row(Rows, rstride, &rl, rcap, row, &moved)) {
         ok = false;
         break;
       }
@@ -1569,14 +1721,15 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
     uint64_t m = c_st.edge_trim[k];
     for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
     if (m == 0) {
-      atomicOr(A.err, 128);
+      if (lead) atomicOr(A.err, 128);
       ok = false;
       break;
     }
     const int t = ffs64(m);
     const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
+    ++expands;
     const uint32_t rh = uint32_t(key >> 32), ro = uint32_t(key);
-    const uint32_t rn = uint32_t(A.rank[h + S.nb(k2)]);
+    const uint32_t rn = N.get(k2);
     // edges (h, n2) and (o, n2)
     ok = H.push((uint64_t(rh) << 32) | rn, (uint32_t(h) << 4) | uint32_t(k2));
     if (ok) {
@@ -1589,6 +1742,7 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
       }
     }
   }
+  if (!lead) return;  // the rest is done once per column
   if (A.stats) {  // expansion statistics (diagnostics)
     atomicAdd(&A.stats[0], (unsigned long long)steps);
     atomicMax(&A.stats[1], (unsigned long long)steps);
@@ -1596,6 +1750,18 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
     if (steps > 1000) atomicAdd(&A.stats[3], 1ull);
     if (!ok) atomicAdd(&A.stats[4], 1ull);
     atomicAdd(&A.stats[5 + min(31 - __clz(steps | 1), 20)], 1ull);
+    // largest heap: <= 8, 16, 32, 64, 128, more
+    atomicAdd(&A.stats[26 + min(max(31 - __clz(max(maxlen - 1, 1)) - 2, 0), 5)], 1ull);
+    atomicAdd(&A.stats[32], (unsigned long long)toggles);
+    atomicAdd(&A.stats[33], (unsigned long long)moved);
+    atomicAdd(&A.stats[34], (unsigned long long)groups);
+    atomicAdd(&A.stats[35], (unsigned long long)expands);
+    if (steps > 2000) {  // the long columns
+      atomicAdd(&A.stats[36], (unsigned long long)steps);
+      atomicAdd(&A.stats[37], (unsigned long long)toggles);
+      atomicAdd(&A.stats[38], (unsigned long long)moved);
+      atomicAdd(&A.stats[39], (unsigned long long)groups);
+    }
   }
   if (!ok) {
     A.retry[atomicAdd(A.nretry, 1u)] = c;
@@ -1616,25 +1782,48 @@ __device__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, LaneHeap
   A.col_desc[c] = (uint64_t(at) << 24) | uint64_t(rl);
 }
 
-// Many short columns: one lane per column, heap and rows in global scratch
-// (interleaved, sized for exactly nthreads lanes).
+// First pass over every column: one lane per column, heap (16 entries) and
+// rows (16) in LDS, interleaved by lane; a column that needs more is retried.
+constexpr int kLaneHeap = 16, kLaneRows = 16, kLaneThreads = 256;
 template <class Geo>
-__global__ void k_d1_boundary(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo,
-                              uint64_t* __restrict__ hkeys, uint32_t* __restrict__ hrefs,
-                              uint32_t* __restrict__ hrows, int hcap, int rcap, int64_t nthreads) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (tid >= nthreads) return;
+__global__ void __launch_bounds__(kLaneThreads)
+k_d1_boundary_lanes(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo) {
+  __shared__ uint64_t s_key[kLaneHeap * kLaneThreads];
+  __shared__ uint32_t s_ref[kLaneHeap * kLaneThreads];
+  __shared__ uint32_t s_rows[kLaneRows * kLaneThreads];
   LaneHeap H;
-  H.key = hkeys + tid;
-  H.ref = hrefs + tid;
-  H.stride = nthreads;
-  H.cap = hcap;
-  for (int64_t w = tid; w < ntodo; w += nthreads)
-    boundary_column(A, todo ? todo[w] : uint32_t(w), H, hrows + tid, nthreads, rcap);
+  H.key = s_key + threadIdx.x;
+  H.ref = s_ref + threadIdx.x;
+  H.stride = kLaneThreads;
+  H.cap = kLaneHeap;
+  for (int64_t w = int64_t(blockIdx.x) * kLaneThreads + threadIdx.x; w < ntodo;
+       w += int64_t(gridDim.x) * kLaneThreads)
+    boundary_column<false>(A, todo ? todo[w] : uint32_t(w), H, s_rows + threadIdx.x, kLaneThreads,
+                           kLaneRows);
 }
 
-// Long columns: one column per workgroup of one wave, heap and rows in LDS,
-// expanded by the first lane (the chain of pops is sequential).
+// Long columns: one column per wave, the queue in the wave's registers (up to
+// 256 edges), rows in LDS; the pops are sequential, each a few cross-lane
+// moves, with the next vertex group's code and neighbour ranks loaded ahead.
+constexpr int kWaveRows = 1024;
+template <class Geo>
+__global__ void __launch_bounds__(64)
+k_d1_boundary_wave(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo,
+                   unsigned int* __restrict__ next) {
+  __shared__ uint32_t s_rows[kWaveRows];
+  WaveList H;
+  H.cap = A.wave_cap;
+  for (;;) {  // columns are taken from a shared counter, so long ones do not queue up
+    unsigned int w = 0;
+    if (threadIdx.x == 0) w = atomicAdd(next, 1u);
+    w = lane_value(w, 0);
+    if (int64_t(w) >= ntodo) break;
+    boundary_column<true>(A, todo[w], H, s_rows, 1, kWaveRows);
+  }
+}
+
+// Columns whose queue outgrows the wave's registers: one column per
+// workgroup of one wave, heap and rows in LDS, expanded by the first lane.
 constexpr int kLdsHeap = 2048, kLdsRows = 1024;
 template <class Geo>
 __global__ void __launch_bounds__(64)
@@ -1649,7 +1838,7 @@ k_d1_boundary_lds(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_
   H.stride = 1;
   H.cap = kLdsHeap;
   for (int64_t w = blockIdx.x; w < ntodo; w += gridDim.x)
-    boundary_column(A, todo[w], H, s_rows, 1, kLdsRows);
+    boundary_column<false>(A, todo[w], H, s_rows, 1, kLdsRows);
 }
 
 // Parallel Z2 reduction.  owner[p] is the lowest column whose current pivot
@@ -2851,36 +3040,34 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     BA.err = err;
     BA.stats = nullptr;
     // launch parameters, overridable for tuning (TS_D1_*); results do not depend on them
-    const int hcap = env_int("TS_D1_HCAP", 64, 8, 1024), rcap = env_int("TS_D1_RCAP", 32, 8, 1024);
     const int pass0_steps = env_int("TS_D1_STEPS", 512, 16, 1 << 20);
+    BA.wave_cap = env_int("TS_D1_WAVE_CAP", WaveList::kCap, 4, WaveList::kCap);
     int64_t ntodo = ncols;
     const uint32_t* list = nullptr;  // first pass: every column
-    for (int pass = 0;; ++pass) {
-      // pass 0: one lane per column with a bounded number of pops; later
-      // passes: the rest, one column per wave with the heap in LDS
-      const bool lds = pass > 0;
-      const int64_t nthreads = lds ? 0 : std::min<int64_t>(ntodo, int64_t(1) << 20);
+    for (int pass = 0, kind = 0;; ++pass) {
+      // kind 0 (every column): one lane per column, a small heap in LDS and
+      // a bounded number of pops; kind 1: the rest, one column per wave, the
+      // queue in the wave's registers; kind 2: columns whose queue outgrows
+      // that, one column per wave with a large heap in LDS
+      const bool lds = kind >= 1;
       uint32_t* out = todo[pass & 1];
       TS_HIP(hipMemsetAsync(nretry, 0, sizeof(unsigned int), s));
       TS_HIP(hipMemsetAsync(bfull, 0, sizeof(int), s));
       if (std::getenv("TS_TRACE")) {
-        BA.stats = ws.get<unsigned long long>("d1.bstats", 32);
-        k_fill_u64<<<1, 32, 0, s>>>(reinterpret_cast<uint64_t*>(BA.stats), 32, 0);
+        BA.stats = ws.get<unsigned long long>("d1.bstats", 40);
+        k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<uint64_t*>(BA.stats), 40, 0);
       }
       BA.pool = pool;
       BA.col_desc = col_desc;
       BA.retry = out;
       BA.max_steps = lds ? 64 * g.n : pass0_steps;
-      if (!lds) {
-        uint64_t* hk = ws.get<uint64_t>("d1.hk", nthreads * hcap);
-        uint32_t* hr = ws.get<uint32_t>("d1.hr", nthreads * hcap);
-        uint32_t* rr = ws.get<uint32_t>("d1.rr", nthreads * rcap);
+      if (kind == 0) {
+        const unsigned nb = unsigned(std::min<int64_t>((ntodo + kLaneThreads - 1) / kLaneThreads, 8192));
         with_geo([&](auto G) {
           BoundaryArgs<decltype(G)> A;
           static_cast<BoundaryCommon&>(A) = BA;
           A.G = G;
-          k_d1_boundary<<<blocks_for(nthreads), 256, 0, s>>>(A, list, ntodo, hk, hr, rr, hcap,
-                                                             rcap, nthreads);
+          k_d1_boundary_lanes<<<nb, kLaneThreads, 0, s>>>(A, list, ntodo);
         });
       } else {
         const unsigned nb = unsigned(std::min<int64_t>(ntodo, 8192));
@@ -2888,25 +3075,40 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
           BoundaryArgs<decltype(G)> A;
           static_cast<BoundaryCommon&>(A) = BA;
           A.G = G;
-          k_d1_boundary_lds<<<nb, 64, 0, s>>>(A, list, ntodo);
+          if (kind == 1) {
+            unsigned int* next = ws.get<unsigned int>("d1.bnext", 1);
+            k_fill_u32<<<1, 1, 0, s>>>(next, 1, 0u);
+            k_d1_boundary_wave<<<nb, 64, 0, s>>>(A, list, ntodo, next);
+          } else {
+            k_d1_boundary_lds<<<nb, 64, 0, s>>>(A, list, ntodo);
+          }
         });
       }
       TS_HIP(hipGetLastError());
       if (BA.stats) {
-        unsigned long long h[32];
+        unsigned long long h[40];
         TS_HIP(hipMemcpyAsync(h, BA.stats, sizeof(h), hipMemcpyDeviceToHost, s));
         TS_HIP(hipStreamSynchronize(s));
         std::fprintf(stderr,
                      "[topsimp] d1 boundary pass %d: columns %lld %s steps %llu max %llu max heap "
                      "%llu long %llu retried %llu; log2 histogram:",
-                     pass, (long long)ntodo, lds ? "lds" : "lanes", h[0], h[1], h[2], h[3], h[4]);
+                     pass, (long long)ntodo,
+                     kind == 0 ? "lanes" : (kind == 1 ? "wave" : "lds"),
+                     h[0], h[1], h[2], h[3], h[4]);
         for (int b = 0; b < 21; ++b) std::fprintf(stderr, " %llu", h[5 + b]);
-        std::fprintf(stderr, "\n");
+        std::fprintf(stderr, "; largest heap <= 8, 16, 32, 64, 128, more:");
+        for (int b = 0; b < 6; ++b) std::fprintf(stderr, " %llu", h[26 + b]);
+        std::fprintf(stderr,
+                     "; toggles %llu rows moved %llu vertex groups %llu expansions %llu; columns "
+                     "over 2000 pops: pops %llu toggles %llu moved %llu groups %llu\n",
+                     h[32], h[33], h[34], h[35], h[36], h[37], h[38], h[39]);
       }
       ntodo = read_scalar(nretry, s);
       if (ntodo == 0) break;
       if (pass > 12) throw Error(TS_ERR_INTERNAL, "boundary extraction did not finish");
       list = out;
+      const int done_kind = kind;
+      kind = std::min(kind + 1, 2);
       if (read_scalar(bfull, s)) {
         // grow the pool keeping its contents
         // (failed reservations past the old capacity were never written)
@@ -2920,7 +3122,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         pool.cap = ncap;
         k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(keep));
         TS_HIP(hipGetLastError());
-      } else if (pass > 0) {
+      } else if (done_kind == 2) {
         throw Error(TS_ERR_CAPACITY, "saddle-saddle boundary exceeds the LDS heap");
       }
     }

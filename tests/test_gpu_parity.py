@@ -191,6 +191,17 @@ def test_column_pool_growth(gpu, orc, monkeypatch):
     _same_pairs(gpu.diagram(_t(f)), ref)
 
 
+@pytest.mark.parametrize("steps,cap", [(16, 256), (16, 4)])
+def test_boundary_fallback_kinds(gpu, orc, monkeypatch, steps, cap):
+    """Saddle-saddle boundaries: with a first pass cut at 16 pops, the columns
+    go on to the wave-queue kernel, and with that queue cut to 4 edges, on to
+    the LDS-heap kernel; every route gives the oracle's diagram."""
+    monkeypatch.setenv("TS_D1_STEPS", str(steps))
+    monkeypatch.setenv("TS_D1_WAVE_CAP", str(cap))
+    f = fields.workload("filament_256", seed=3, dims=(48, 40, 36))
+    _same_pairs(gpu.diagram(_t(f)), orc.diagram(f))
+
+
 def test_critical_list_retry(gpu, orc, monkeypatch):
     """Critical-cell lists that start too small are sized from the counts
     and the gradient kernel is run again: same critical cells."""
