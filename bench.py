@@ -59,8 +59,8 @@ ORDER_STAGES = ("K1 order keys", "K1 radix sort", "K2 rank")
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (fetch x2.0, write x1.0).  It belongs to the kernel source and
 # tile shape it was measured on: another source or shape reports null.
-K3_COUNTERS = {"source_sha1": "536042b358ef564dbe7ca5b80fa78fcab68a264c", "tiles": (8, 8, 4),
-               "dims": (256, 256, 256), "fetch_kib": 180548.0, "write_kib": 436826.0,
+K3_COUNTERS = {"source_sha1": "a8402324a5cb7ec1b58fc813f1ded1d63a52a545", "tiles": (8, 8, 4),
+               "dims": (256, 256, 256), "fetch_kib": 53713.0, "write_kib": 423103.0,
                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
