@@ -1890,12 +1890,14 @@ __device__ __forceinline__ void d1_claim_one(uint32_t c, const uint64_t* __restr
 // are displaced), cnt[1] = size of the next list, cnt[2] = size of the
 // current list when the round began.
 // cnt[3]: long columns deferred to the workgroup kernel this round;
-// cnt[4]: the lowest active column (every column below it is final).
+// cnt[4]: the lowest active column (every column below it is final);
+// cnt[5]: columns deferred from the lane kernel to the wave kernel.
 __global__ void k_d1_round_begin(unsigned int* __restrict__ cnt) {
   cnt[2] = cnt[0];
   cnt[1] = 0;
   cnt[3] = 0;
   cnt[4] = 0xFFFFFFFFu;
+  cnt[5] = 0;
 }
 
 // end of a round: the next list becomes current, the round advances and the
@@ -1907,6 +1909,7 @@ __global__ void k_d1_round_next(unsigned int* __restrict__ cnt, unsigned int* __
   cnt[1] = 0;
   cnt[3] = 0;
   cnt[4] = 0xFFFFFFFFu;
+  cnt[5] = 0;
 }
 
 // pdesc[p] = the column of p's owner (after the claims of a round, the owner
@@ -2305,6 +2308,144 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
 }
 
 // Reduce phase with one wave per active column.
+// ---- lane reduction of short columns -------------------------------------
+// Most columns are a few rows long: one lane per column, the working column,
+// the next one and the owner's column in LDS (interleaved by lane).  Same
+// steps and results as the wave form; a column (or owner) longer than
+// kLaneCol is deferred to the wave kernel of the same round.
+constexpr int kLaneCol = 16, kRedLanes = 128;
+
+__device__ __forceinline__ void load_col(const uint32_t* __restrict__ src, uint32_t n, uint32_t* dst) {
+  uint32_t v[kLaneCol];
+#pragma unroll
+  for (int i = 0; i < kLaneCol; ++i) v[i] = uint32_t(i) < n ? src[i] : 0u;
+#pragma unroll
+  for (int i = 0; i < kLaneCol; ++i)
+    if (uint32_t(i) < n) dst[i * kRedLanes] = v[i];
+}
+
+// returns as d1_reduce_wave: 0 owner, 1 again next round, 2 pool full, -1 deferred
+__device__ int d1_reduce_lane(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
+                              const ColPool& pc, const unsigned int* __restrict__ owner,
+                              const uint64_t* __restrict__ pdesc, int* __restrict__ err, uint32_t fin,
+                              uint32_t* cur, uint32_t* nxt, uint32_t* own, int* adds) {
+  const uint64_t d = col_desc[c];
+  uint32_t len = uint32_t(d & 0xFFFFFFu);
+  *adds = 0;
+  if (len == 0) return 0;
+  if (len > uint32_t(kLaneCol)) return -1;
+  load_col(pool + (d >> 24), len, cur);
+  bool changed = false;
+  int result = 1;
+  for (;;) {
+    const uint32_t piv = cur[0];
+    const unsigned int o = owner[piv];
+    const uint64_t od = pdesc[piv];
+    if (o == c) {
+      result = 0;
+      break;
+    }
+    if (o > c) break;  // unowned or owned by a later column: claim next round
+    const uint32_t olen = uint32_t(od & 0xFFFFFFu);
+    if (olen > uint32_t(kLaneCol) || len + olen > uint32_t(2 * kLaneCol)) {
+      if (!changed) return -1;
+      break;  // write back what we have; the next round hands it on
+    }
+    load_col(pool + (od >> 24), olen, own);
+    // symmetric difference of the two descending lists
+    uint32_t i = 0, j = 0, w = 0;
+    while (i < len && j < olen) {
+      const uint32_t x = cur[i * kRedLanes], y = own[j * kRedLanes];
+      if (x == y) {
+        ++i;
+        ++j;
+      } else if (x > y) {
+        nxt[(w++) * kRedLanes] = x;
+        ++i;
+      } else {
+        nxt[(w++) * kRedLanes] = y;
+        ++j;
+      }
+    }
+    for (; i < len; ++i) nxt[(w++) * kRedLanes] = cur[i * kRedLanes];
+    for (; j < olen; ++j) nxt[(w++) * kRedLanes] = own[j * kRedLanes];
+    changed = true;
+    ++*adds;
+    if (w == 0) {
+      atomicOr(err, 64);
+      len = 0;
+      break;
+    }
+    uint32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    len = w;
+    if (o >= fin || len > uint32_t(kLaneCol)) break;  // owner not final: one step per round
+  }
+  if (!changed) return result;
+  const unsigned long long at = atomicAdd(pc.top, (unsigned long long)len);
+  if ((int64_t)(at + len) > pc.cap) return 2;  // column unchanged; retried after growth
+  for (uint32_t i = 0; i < len; ++i) pool[at + i] = cur[i * kRedLanes];
+  __threadfence();
+  col_desc[c] = (uint64_t(at) << 24) | uint64_t(len);
+  return result;
+}
+
+// append v to list (counter *n) for the lanes whose flag is set, with one
+// atomic per wave
+__device__ __forceinline__ void wave_append(bool flag, uint32_t v, uint32_t* __restrict__ list,
+                                            unsigned int* __restrict__ n) {
+  const uint64_t m = __ballot(flag);
+  if (m == 0) return;
+  const unsigned lane = threadIdx.x & 63u;
+  const int first = __ffsll((unsigned long long)m) - 1;
+  unsigned int base = 0;
+  if (int(lane) == first) base = atomicAdd(n, unsigned(__popcll(m)));
+  base = __shfl(base, first);
+  if (flag) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
+}
+
+__global__ void __launch_bounds__(kRedLanes)
+k_d1_reduce_lanes(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
+                  const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
+                  unsigned int* __restrict__ mark, unsigned int* __restrict__ round_ptr,
+                  const uint32_t* __restrict__ list, uint32_t* __restrict__ next,
+                  unsigned int* __restrict__ cnt, int* __restrict__ err, int* __restrict__ pool_full,
+                  uint32_t* __restrict__ wave_list, unsigned long long* __restrict__ stats) {
+  __shared__ uint32_t s_buf[(5 * kLaneCol) * kRedLanes];
+  uint32_t* cur = s_buf + threadIdx.x;
+  uint32_t* nxt = cur + 2 * kLaneCol * kRedLanes;
+  uint32_t* own = nxt + 2 * kLaneCol * kRedLanes;
+  const unsigned int n1 = cnt[0];
+  const uint32_t fin = cnt[4];  // owners below it are final
+  const unsigned int round = *round_ptr;
+  // every lane of a wave runs the same number of iterations (ballots below)
+  const unsigned int stride = gridDim.x * kRedLanes;
+  const unsigned int begin = blockIdx.x * kRedLanes + (threadIdx.x & ~63u);
+  for (unsigned int jb = begin; jb < n1; jb += stride) {
+    const unsigned int j = jb + (threadIdx.x & 63u);
+    const bool live = j < n1;
+    const uint32_t c = live ? list[j] : 0u;
+    int adds = 0;
+    const int r = live ? d1_reduce_lane(c, col_desc, pool, pc, owner, pdesc, err, fin, cur, nxt, own,
+                                        &adds)
+                       : 0;
+    if (r == 2) atomicOr(pool_full, 1);
+    if (live && r > 0) mark[c] = round + 1;
+    wave_append(live && r > 0, c, next, &cnt[1]);
+    wave_append(live && r < 0, c, wave_list, &cnt[5]);
+    if (stats) {
+      const uint64_t m = __ballot(live && r >= 0);
+      int a = adds;
+      for (int sh = 32; sh >= 1; sh >>= 1) a += __shfl_xor(a, sh, 64);
+      if ((threadIdx.x & 63u) == 0) {
+        atomicAdd(&stats[6], (unsigned long long)__popcll(m));
+        atomicAdd(&stats[7], (unsigned long long)a);
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64 * kRedWaves)
 k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
                  const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
@@ -2316,7 +2457,7 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   __shared__ uint32_t s_buf[kRedWaves][3][2 * kWaveCap];
   const unsigned wave = threadIdx.x >> 6;
   const unsigned lane = lane_id();
-  const unsigned int n1 = cnt[0];
+  const unsigned int n1 = cnt[5];  // the columns the lane kernel deferred
   const uint32_t fin = cnt[4];  // owners below it are final
   const unsigned int round = *round_ptr;
   const unsigned gw = blockIdx.x * kRedWaves + wave;
@@ -3169,7 +3310,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     unsigned int* mark = ws.get<unsigned int>("d1.mark", ncols + 1);
     uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
     uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
-    unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 5);
+    unsigned int* cnt = ws.get<unsigned int>("d1.cnt", 6);
+    uint32_t* wave_list = ws.get<uint32_t>("d1.wave", ncols + 1);
     uint32_t* long_list = ws.get<uint32_t>("d1.long", ncols + 1);
     int* pool_full = ws.get<int>("d1.full", 1);
     k_fill_u32<<<blocks_for(ne), 256, 0, s>>>(owner, ne, 0xFFFFFFFFu);
@@ -3236,16 +3378,20 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         // grids sized by the last known active count (the kernels stride over
         // the device-side count, so a later, larger list is still covered)
         const unsigned grid = std::min<unsigned>(std::max<unsigned>(blocks_for(h_n), 8u), 1024u);
-        const unsigned wgrid =
-            std::min<unsigned>(std::max<unsigned>((2 * h_n + kRedWaves - 1) / kRedWaves, 64u), 4096u);
+        const unsigned lgrid =
+            std::min<unsigned>(std::max<unsigned>((h_n + kRedLanes - 1) / kRedLanes, 8u), 8192u);
+        const unsigned wgrid = 512u;  // the deferred columns are few (counted on the device)
         TS_HIP(hipMemsetAsync(pool_full, 0, sizeof(int), s));
         for (int it = 0; it < kCheckEvery; ++it) {
           ++rounds;
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
           k_d1_publish<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, A, cnt, 0, pdesc);
+          k_d1_reduce_lanes<<<lgrid, kRedLanes, 0, s>>>(col_desc, pool.data, pool, owner, pdesc, mark,
+                                                          round_d, A, B, cnt, err, pool_full,
+                                                          wave_list, rstats);
           k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
                                                             mark,
-                                                            round_d, A, B, cnt, err, pool_full,
+                                                            round_d, wave_list, B, cnt, err, pool_full,
                                                             long_list, rstats);
           k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
                                                        mark,
@@ -3277,9 +3423,9 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       unsigned long long h[8];
       TS_HIP(hipMemcpy(h, rstats, sizeof(h), hipMemcpyDeviceToHost));
       std::fprintf(stderr,
-                   "[topsimp] d1 reduction work: wave columns %llu additions %llu max chain %llu; "
-                   "long columns %llu additions %llu max chain %llu\n",
-                   h[0], h[1], h[2], h[3], h[4], h[5]);
+                   "[topsimp] d1 reduction work: lane columns %llu additions %llu; wave columns %llu "
+                   "additions %llu max chain %llu; long columns %llu additions %llu max chain %llu\n",
+                   h[6], h[7], h[0], h[1], h[2], h[3], h[4], h[5]);
     }
     length_stats("reduced");
     if (std::getenv("TS_TRACE"))
