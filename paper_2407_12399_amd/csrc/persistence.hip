@@ -2033,14 +2033,16 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
   int steps_done = 0;
   uint32_t* cur = bufA;
   uint32_t* nxt = bufO;
+  // the owner of the current pivot and its column; after the first step they
+  // are loaded during the previous addition (the next pivot, the largest
+  // row left after cancelling, is known from the two columns' heads)
+  unsigned int o = owner[cur[0]];
+  uint64_t od = pdesc[cur[0]];
   for (int steps = 0;; ++steps) {
     if (steps > (1 << 20)) {  // pivots strictly decrease: cannot happen
       if (lane == 0) atomicOr(err, 512);
       break;
     }
-    const uint32_t piv = cur[0];
-    const unsigned int o = owner[piv];
-    const uint64_t od = pdesc[piv];  // the owner's column, loaded with the owner
     if (o == c) {
       result = 0;
       break;
@@ -2054,6 +2056,17 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     const uint64_t ooff = od >> 24;
     for (uint32_t i = lane; i < olen; i += 64) bufB[i] = pool[ooff + i];
     wave_sync();
+    const unsigned int o_step = o;  // the owner added in this step
+    uint32_t hi = 1, hj = 1;  // both heads are the pivot
+    while (hi < len && hj < olen && cur[hi] == bufB[hj]) {
+      ++hi;
+      ++hj;
+    }
+    if (hi < len || hj < olen) {
+      const uint32_t np = hi < len && (hj >= olen || cur[hi] > bufB[hj]) ? cur[hi] : bufB[hj];
+      o = owner[np];
+      od = pdesc[np];
+    }
     const uint32_t w = wave_xor(cur, len, bufB, olen, nxt);
     changed = true;
     ++steps_done;
@@ -2066,7 +2079,7 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     cur = nxt;
     nxt = t;
     len = w;
-    if (o >= fin || len > kWaveCap) break;  // owner not final: one step per round
+    if (o_step >= fin || len > kWaveCap) break;  // owner not final: one step per round
   }
   if (stats && lane == 0) {  // diagnostics: columns, additions, longest chain
     atomicAdd(&stats[0], 1ull);
@@ -2180,6 +2193,11 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   __shared__ int s_state;  // -1 continue, 0 owner, 1 next round, 2 pool full, 3 stop (error)
   __shared__ int s_lds;    // the working column lives in s_col[cur]
   __shared__ int s_spill;  // it must move to global memory before the next addition
+  // the owner of the next pivot and its column, loaded during the addition
+  // before (the next pivot is known from the two columns' heads)
+  __shared__ int s_pf;
+  __shared__ unsigned int s_po;
+  __shared__ uint64_t s_pod;
   const unsigned int nlong = cnt[3];
   const unsigned int round = *round_ptr;
   const uint32_t fin = cnt[4];  // owners below it are final
@@ -2191,6 +2209,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       s_off = d >> 24;
       s_lds = s_len <= kLongCap ? 1 : 0;
       s_state = -1;
+      s_pf = 0;
     }
     __syncthreads();
     int cur = 0, nsteps = 0;
@@ -2206,9 +2225,17 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           s_state = 3;
           atomicOr(err, 1024);
         } else {
-          const uint32_t piv = s_lds ? s_col[cur][0] : pool[s_off];
-          const unsigned int o = owner[piv];
-          const uint64_t od = pdesc[piv];  // the owner's column, loaded with the owner
+          unsigned int o;
+          uint64_t od;  // the owner's column, loaded with the owner
+          if (s_pf) {
+            o = s_po;
+            od = s_pod;
+          } else {
+            const uint32_t piv = s_lds ? s_col[cur][0] : pool[s_off];
+            o = owner[piv];
+            od = pdesc[piv];
+          }
+          s_pf = 0;
           if (o == c) {
             s_state = 0;
           } else if (o > c || (steps > 0 && o >= fin)) {
@@ -2246,12 +2273,34 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       if (s_lds) {
         for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
         __syncthreads();
+        unsigned int po = 0;
+        uint64_t pod = 0;
+        bool pf = false;
+        if (threadIdx.x == 0) {
+          const uint32_t* X = s_col[cur];
+          uint32_t hi = 1, hj = 1;  // both heads are the pivot
+          while (hi < s_len && hj < s_olen && X[hi] == s_own[hj]) {
+            ++hi;
+            ++hj;
+          }
+          if (hi < s_len || hj < s_olen) {
+            const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > s_own[hj]) ? X[hi] : s_own[hj];
+            po = owner[np];
+            pod = pdesc[np];
+            pf = true;
+          }
+        }
         const uint32_t w = block_xor(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_wave);
         cur ^= 1;
         dirty = true;
         if (threadIdx.x == 0) {
           if (w == 0) atomicOr(err, 64);  // a negative column cannot vanish
           s_len = w;
+          if (pf) {
+            s_po = po;
+            s_pod = pod;
+            s_pf = 1;
+          }
         }
         __syncthreads();
       } else {
