@@ -63,6 +63,10 @@ struct StarTables {
   uint8_t tri_chain[12][3];  // corner masks of the canonical chains
   uint16_t negx, posx, negy, posy, negz, posz;  // neighbours leaving the box side
   int8_t nb_diff[14][14];    // star index of offset nb[b] - nb[a], -1 if not a neighbour
+  // expansion step of the Morse boundary: edge (centre, k) paired with its
+  // j-th star triangle (centre, k, k2): bit 31 valid, bits 0..3 k2, 4..7
+  // nb_diff[k][k2], 8..11 nb_diff[k2][k]
+  uint32_t edge_step[14][6];
 };
 
 __constant__ StarTables c_st;
@@ -211,6 +215,20 @@ StarTables build_tables() {
   for (int k = 0; k < 14; ++k)  // edge codes 0..5 name one of at most 6 triangles
     if (__builtin_popcountll(T.edge_trim[k]) > 6)
       throw Error(TS_ERR_INTERNAL, "star tables: edge of degree > 6");
+  for (int k = 0; k < 14; ++k) {
+    uint64_t m = T.edge_trim[k];
+    for (int j = 0; j < 6; ++j) {
+      T.edge_step[k][j] = 0;
+      if (m == 0) continue;
+      const int t = __builtin_ctzll(m);
+      m &= m - 1;
+      const int k2 = __builtin_ctz(uint32_t(T.tri_nbm[t]) & ~(1u << k));
+      if (T.nb_diff[k][k2] < 0 || T.nb_diff[k2][k] < 0)
+        throw Error(TS_ERR_INTERNAL, "star tables: triangle edge is not a neighbour offset");
+      T.edge_step[k][j] = (1u << 31) | uint32_t(k2) | (uint32_t(T.nb_diff[k][k2]) << 4) |
+                          (uint32_t(T.nb_diff[k2][k]) << 8);
+    }
+  }
   // canonical cell -> star index at each of its vertices
   for (int type = 0; type < 12; ++type) {
     for (int k = 0; k < 3; ++k) T.tri_chain[type][k] = uint8_t(kTriChains[type][k]);
@@ -1559,6 +1577,7 @@ struct WaveList {
     *rr = top_ref();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {  // entry i takes entry i + 1
+      if (64 * j >= n) break;  // registers past the last entry hold zeros
       const uint32_t ch = j < 3 ? lane_value(khi[j + 1], 0) : 0u;
       const uint32_t cl = j < 3 ? lane_value(klo[j + 1], 0) : 0u;
       const uint32_t cr = j < 3 ? lane_value(r[j + 1], 0) : 0u;
@@ -1575,6 +1594,7 @@ struct WaveList {
     for (int j = 0; j < 4; ++j) p += __popcll(__ballot(join(khi[j], klo[j]) > kk));
 #pragma unroll
     for (int j = 3; j >= 0; --j) {  // entry i > p takes entry i - 1
+      if (64 * j > n) continue;  // registers past the new last entry stay zero
       const uint32_t ch = j > 0 ? lane_value(khi[j - 1], 63) : 0u;
       const uint32_t cl = j > 0 ? lane_value(klo[j - 1], 63) : 0u;
       const uint32_t cr = j > 0 ? lane_value(r[j - 1], 63) : 0u;
@@ -1736,15 +1756,13 @@ __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint
       continue;
     }
     // paired with the ec-th star triangle (h, o, n2) containing the edge
-    uint64_t m = c_st.edge_trim[k];
-    for (uint32_t s = 0; s < ec; ++s) m &= m - 1;
-    if (m == 0) {
+    const uint32_t stp = c_st.edge_step[k][ec];
+    if (!(stp >> 31)) {
       if (lead) atomicOr(A.err, 128);
       ok = false;
       break;
     }
-    const int t = ffs64(m);
-    const int k2 = ffs32(uint32_t(c_st.tri_nbm[t]) & ~(1u << k));
+    const int k2 = int(stp & 15u);
     ++expands;
     const uint32_t rh = uint32_t(key >> 32), ro = uint32_t(key);
     const uint32_t rn = N.get(k2);
@@ -1753,10 +1771,10 @@ __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint
     if (ok) {
       const int o = h + S.nb(k);
       if (ro > rn) {
-        ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(o) << 4) | uint32_t(c_st.nb_diff[k][k2]));
+        ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(o) << 4) | ((stp >> 4) & 15u));
       } else {
         const int n2 = h + S.nb(k2);
-        ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(n2) << 4) | uint32_t(c_st.nb_diff[k2][k]));
+        ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(n2) << 4) | ((stp >> 8) & 15u));
       }
     }
   }
