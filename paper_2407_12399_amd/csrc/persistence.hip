@@ -2190,6 +2190,80 @@ __device__ uint32_t block_xor(const uint32_t* A, uint32_t a, const uint32_t* B, 
   return keptA + keptB;
 }
 
+// Exclusive prefix sum over the workgroup of small per-thread counts;
+// *total receives the sum.
+__device__ __forceinline__ uint32_t block_scan_counts(uint32_t v, uint32_t* s_wave,
+                                                      uint32_t* total) {
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const unsigned nw = blockDim.x / 64;
+  uint32_t x = v;  // inclusive scan within the wave
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = uint32_t(__shfl_up(int(x), d, 64));
+    if (int(lane) >= d) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t c = lane < nw ? s_wave[lane] : 0u;
+    uint32_t z = c;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = uint32_t(__shfl_up(int(z), d, 64));
+      if (int(lane) >= d) z += y;
+    }
+    if (lane < nw) s_wave[lane] = z - c;
+    if (lane == nw - 1) s_wave[nw] = z;
+  }
+  __syncthreads();
+  const uint32_t r = s_wave[wave] + x - v;
+  *total = s_wave[nw];
+  __syncthreads();
+  return r;
+}
+
+// Symmetric difference of the descending lists A (a) and B (b), both in LDS,
+// by the whole workgroup: a merge-path merge into tmp (thread t writes the
+// merged positions [t K, (t + 1) K), K = ceil((a + b) / threads), starting
+// from the split found by one binary search on its diagonal; on equal values
+// A's comes first), then the equal pairs, which are neighbours in the merged
+// list, are dropped while the rest is compacted into out.  Two passes over
+// short per-thread runs instead of one binary search per element.
+__device__ uint32_t block_xor_merge(const uint32_t* A, uint32_t a, const uint32_t* B, uint32_t b,
+                                    uint32_t* tmp, uint32_t* out, uint32_t* s_wave) {
+  const uint32_t total = a + b;
+  const uint32_t K = (total + kLongThreads - 1) / kLongThreads;
+  const uint32_t d0 = min(threadIdx.x * K, total), d1 = min(d0 + K, total);
+  // i = number of A elements among the first d0 merged ones: the first i in
+  // [max(0, d0 - b), min(d0, a)] with A[i] after B[d0 - 1 - i]
+  uint32_t lo = d0 > b ? d0 - b : 0u, hi = d0 < a ? d0 : a;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] >= B[d0 - 1 - mid]) lo = mid + 1;  // A[mid] comes first
+    else hi = mid;
+  }
+  uint32_t i = lo, j = d0 - lo;
+  for (uint32_t p = d0; p < d1; ++p) {
+    if (i < a && (j >= b || A[i] >= B[j])) tmp[p] = A[i++];
+    else tmp[p] = B[j++];
+  }
+  __syncthreads();
+  uint64_t keep = 0;  // K <= kLongCap / kLongThreads <= 64
+  uint32_t cnt = 0;
+  for (uint32_t p = d0; p < d1; ++p) {
+    const uint32_t x = tmp[p];
+    const bool gone = (p + 1 < total && tmp[p + 1] == x) || (p > 0 && tmp[p - 1] == x);
+    if (!gone) {
+      keep |= 1ull << (p - d0);
+      ++cnt;
+    }
+  }
+  uint32_t kept;
+  uint32_t at = block_scan_counts(cnt, s_wave, &kept);
+  for (uint32_t p = d0; p < d1; ++p)
+    if ((keep >> (p - d0)) & 1ull) out[at++] = tmp[p];
+  __syncthreads();
+  return kept;
+}
+
 // Reduce phase for long columns, one workgroup per column.  The working
 // column stays in LDS across the additions of a round (chained through
 // final owners) and is written back once; a column or owner too long for
@@ -2231,6 +2305,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
     }
     __syncthreads();
     int cur = 0, nsteps = 0;
+    uint64_t tph[4] = {0, 0, 0, 0};  // diagnostics: decision, owner load, merge, update
+    uint64_t tmark = wall_clock64();
     bool dirty = false;  // the LDS column is newer than col_desc[c]
     if (s_lds)
       for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) s_col[0][i] = pool[s_off + i];
@@ -2266,6 +2342,11 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         }
       }
       __syncthreads();
+      if (stats) {
+        const uint64_t t = wall_clock64();
+        tph[0] += t - tmark;
+        tmark = t;
+      }
       if (s_state >= 0) break;
       ++nsteps;
       if (s_spill) {
@@ -2291,6 +2372,11 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       if (s_lds) {
         for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
         __syncthreads();
+        if (stats) {
+          const uint64_t t = wall_clock64();
+          tph[1] += t - tmark;
+          tmark = t;
+        }
         unsigned int po = 0;
         uint64_t pod = 0;
         bool pf = false;
@@ -2308,8 +2394,14 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
             pf = true;
           }
         }
-        const uint32_t w = block_xor(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_wave);
-        cur ^= 1;
+        // merged into s_col[cur ^ 1], compacted back into s_col[cur]
+        const uint32_t w =
+            block_xor_merge(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_col[cur], s_wave);
+        if (stats) {
+          const uint64_t t = wall_clock64();
+          tph[2] += t - tmark;
+          tmark = t;
+        }
         dirty = true;
         if (threadIdx.x == 0) {
           if (w == 0) atomicOr(err, 64);  // a negative column cannot vanish
@@ -2321,6 +2413,11 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           }
         }
         __syncthreads();
+        if (stats) {
+          const uint64_t t = wall_clock64();
+          tph[3] += t - tmark;
+          tmark = t;
+        }
       } else {
         if (threadIdx.x == 0) {
           s_at = atomicAdd(pc.top, (unsigned long long)(s_len + s_olen));
@@ -2361,6 +2458,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         atomicAdd(&stats[3], 1ull);
         atomicAdd(&stats[4], (unsigned long long)nsteps);
         atomicMax(&stats[5], (unsigned long long)nsteps);
+        for (int q = 0; q < 4; ++q) atomicAdd(&stats[8 + q], (unsigned long long)tph[q]);
       }
       int st = s_state;
       if (st == 0 && dirty) st = 1;  // the pivot changed this round: claim it next round
@@ -3431,8 +3529,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     uint32_t* B = listB;
     unsigned long long* rstats = nullptr;
     if (std::getenv("TS_TRACE")) {
-      rstats = ws.get<unsigned long long>("d1.rstats", 8);
-      k_fill_u64<<<1, 8, 0, s>>>(reinterpret_cast<uint64_t*>(rstats), 8, 0);
+      rstats = ws.get<unsigned long long>("d1.rstats", 16);
+      k_fill_u64<<<1, 16, 0, s>>>(reinterpret_cast<uint64_t*>(rstats), 16, 0);
     }
     for (int64_t lo = 0; lo < ncols; lo += kBlock) {
       const int64_t hi = std::min<int64_t>(ncols, lo + kBlock);
@@ -3487,8 +3585,15 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     ctx->tuner.report(tune_key, tune_idx,
                       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_reduce).count());
     if (rstats) {
-      unsigned long long h[8];
+      unsigned long long h[16];
       TS_HIP(hipMemcpy(h, rstats, sizeof(h), hipMemcpyDeviceToHost));
+      int wclk = 0;  // kHz
+      TS_HIP(hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, ctx->device));
+      const double us = wclk > 0 ? 1e3 / wclk : 0.0;
+      std::fprintf(stderr,
+                   "[topsimp] d1 workgroup reduction phases (us, all long columns): decision %.0f, "
+                   "owner load %.0f, merge %.0f, update %.0f\n",
+                   h[8] * us, h[9] * us, h[10] * us, h[11] * us);
       std::fprintf(stderr,
                    "[topsimp] d1 reduction work: lane columns %llu additions %llu; wave columns %llu "
                    "additions %llu max chain %llu; long columns %llu additions %llu max chain %llu\n",
