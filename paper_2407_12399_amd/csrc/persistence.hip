@@ -487,8 +487,12 @@ __device__ __forceinline__ void load_hot_tables(HotTables& T) {
 }
 
 // One block's worth of lower stars: lane tid brings vertex v0 (act0: a vertex
-// to process).  Called by every thread of the block (it holds barriers).
-template <class Geo>
+// to process).  kWaveMode false: called by every thread of the block (it holds
+// barriers: the block's vertices are sorted by work first, and the critical
+// cells are emitted with one atomic per block).  kWaveMode true: the lane's
+// vertex is processed as given and the cells are emitted with one atomic per
+// wave, with no barrier, so that the waves of a block run independently.
+template <bool kWaveMode = false, class Geo>
 __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const Geo& G,
                                          uint4* __restrict__ code_out,
                                          int32_t* __restrict__ down_out, const CritOut& co,
@@ -498,7 +502,7 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
   uint8_t* s_cell_slot = sh.cell_slot;
   unsigned int* s_cnt = sh.cnt;
   unsigned long long* s_base = sh.base;
-  if (tid < 4) s_cnt[tid] = 0;
+  if (!kWaveMode && tid < 4) s_cnt[tid] = 0;
   uint8_t* slot_cell = s_slot_cell + tid;  // element i at [i * kGradThreads]
   uint8_t* cell_slot = s_cell_slot + tid;
 #define SLOT_CELL(i) slot_cell[(i) * kGradThreads]
@@ -510,9 +514,9 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
   // LDS, in the space the slot tables use later), so that each wave holds
   // vertices of similar work.  Every output is indexed by vertex, so the
   // processing order does not change any result.
-  int v;
-  bool active;
-  {
+  int v = v0;
+  bool active = act0;
+  if constexpr (!kWaveMode) {
     int key = 15;  // inactive lanes last
     if (act0) {
       const auto S0 = G.site(v0);
@@ -767,26 +771,52 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
   // ---- emit critical cells (block-aggregated) ----
   const unsigned int nv = (active && low == 0) ? 1u : 0u;
   const unsigned int ne = __popc(critE), nt = __popcll(critT), nq = __popc(critQ);
-  __syncthreads();
-  unsigned int o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-  if (nv) o0 = atomicAdd(&s_cnt[0], nv);
-  if (ne) o1 = atomicAdd(&s_cnt[1], ne);
-  if (nt) o2 = atomicAdd(&s_cnt[2], nt);
-  if (nq) o3 = atomicAdd(&s_cnt[3], nq);
-  __syncthreads();
-  if (tid < 4) s_base[tid] = s_cnt[tid] ? atomicAdd(&co.count[tid], (unsigned long long)s_cnt[tid]) : 0ull;
-  __syncthreads();
+  unsigned long long p0, p1, p2, p3;  // first output slot of each kind
+  if constexpr (kWaveMode) {
+    // exclusive prefix of each kind's count over the wave, one atomic a kind
+    const unsigned lane = threadIdx.x & 63u;
+    auto reserve = [&](unsigned int c, unsigned long long* counter) {
+      unsigned int incl = c;
+      for (int d = 1; d < 64; d <<= 1) {
+        const unsigned int y = unsigned(__shfl_up(int(incl), d, 64));
+        if (int(lane) >= d) incl += y;
+      }
+      const unsigned int tot = unsigned(__shfl(int(incl), 63, 64));
+      unsigned long long b = 0;
+      if (lane == 63 && tot) b = atomicAdd(counter, (unsigned long long)tot);
+      b = __shfl(b, 63, 64);
+      return b + (incl - c);
+    };
+    p0 = reserve(nv, &co.count[0]);
+    p1 = reserve(ne, &co.count[1]);
+    p2 = reserve(nt, &co.count[2]);
+    p3 = reserve(nq, &co.count[3]);
+  } else {
+    __syncthreads();
+    unsigned int o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+    if (nv) o0 = atomicAdd(&s_cnt[0], nv);
+    if (ne) o1 = atomicAdd(&s_cnt[1], ne);
+    if (nt) o2 = atomicAdd(&s_cnt[2], nt);
+    if (nq) o3 = atomicAdd(&s_cnt[3], nq);
+    __syncthreads();
+    if (tid < 4) s_base[tid] = s_cnt[tid] ? atomicAdd(&co.count[tid], (unsigned long long)s_cnt[tid]) : 0ull;
+    __syncthreads();
+    p0 = s_base[0] + o0;
+    p1 = s_base[1] + o1;
+    p2 = s_base[2] + o2;
+    p3 = s_base[3] + o3;
+  }
   if (!active) return;
   const uint64_t rk = uint64_t(rx) << 12;
   if (nv) {
-    const unsigned long long p = s_base[0] + o0;
+    const unsigned long long p = p0;
     if ((int64_t)p < co.cap[0]) {
       co.key[0][p] = rk;
       co.id[0][p] = v;
     }
   }
   if (ne) {
-    unsigned long long p = s_base[1] + o1;
+    unsigned long long p = p1;
     uint32_t m = critE;
     while (m) {
       const int k = ffs32(m);
@@ -800,7 +830,7 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
     }
   }
   if (nt) {
-    unsigned long long p = s_base[2] + o2;
+    unsigned long long p = p2;
     uint64_t m = critT;
     while (m) {
       const int t = ffs64(m);
@@ -816,7 +846,7 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
     }
   }
   if (nq) {
-    unsigned long long p = s_base[3] + o3;
+    unsigned long long p = p3;
     uint32_t m = critQ;
     while (m) {
       const int q = ffs32(m);
@@ -877,40 +907,39 @@ struct TileQueue {
 // The lower-star kernel as persistent workgroups that take tiles from a
 // queue until it is empty: the hot tables are staged once per workgroup, and a
 // tile keeps the 14-neighbour stencil of its vertices within a small box.
+// A workgroup takes two tiles at a time (512 vertices), sorts them by their
+// number of lower neighbours (the lower-star loops run as often as a wave's
+// slowest lane needs, and their trip counts grow with that number), and its
+// waves then take the eight groups of 64 sorted vertices from a shared
+// counter, the heaviest first, each emitting its own critical cells: a wave
+// that drew light groups takes more of them instead of waiting at a barrier
+// for the wave with the heaviest one.
+constexpr int kK3Batch = 2;  // tiles per workgroup round
 template <class Geo>
 __global__ void __launch_bounds__(kGradThreads)
 k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out,
                  int32_t* __restrict__ down_out, CritOut co, TileQueue q) {
   __shared__ K3Shared sh;
   __shared__ HotTables T;
-  __shared__ int64_t s_item;
+  __shared__ int64_t s_item[kK3Batch];
+  __shared__ uint16_t s_order[kK3Batch * kGradThreads];  // batch slots sorted by work
+  __shared__ unsigned int s_hist[16];
+  __shared__ int s_next;
   load_hot_tables(T);
   const int tid = threadIdx.x;
+  const unsigned lane = threadIdx.x & 63u;
   const bool runs = q.tx == 0;
   const int tx = runs ? 1 : q.tx, ty = runs ? 1 : q.ty;
-  const int lx = tid % tx, ly = (tid / tx) % ty, lz = tid / (tx * ty);
-  int probe = 0;  // queues tried so far (uniform over the workgroup)
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) {
-      s_item = -1;
-      for (; probe < kTileQueues; ++probe) {
-        const int qi = int((blockIdx.x + probe) % kTileQueues);
-        const int64_t i = q.begin(qi) + int64_t(atomicAdd(q.head + qi, 1u));
-        if (i < q.begin(qi + 1)) {
-          s_item = i;
-          break;
-        }
-      }
+  // vertex of lane position `pos` of item `item` (act: inside its field)
+  auto vertex = [&](int64_t item, int pos, bool* act) -> int {
+    if (item < 0) {
+      *act = false;
+      return 0;
     }
-    __syncthreads();
-    const int64_t item = s_item;
-    if (item < 0) break;  // the whole workgroup leaves together
     if (runs) {
-      const int64_t v = item * kGradThreads + tid;
-      const bool act = v < G.total();
-      k3_block(rank, G, code_out, down_out, co, T, sh, act, act ? int(v) : 0);
-      continue;
+      const int64_t v = item * kGradThreads + pos;
+      *act = v < G.total();
+      return *act ? int(v) : 0;
     }
     int f = 0;
     while (f + 1 < q.nf && item >= q.tile_base[f + 1]) ++f;
@@ -918,10 +947,81 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
     const int nbx = (fd.y + q.tx - 1) / q.tx, nby = (fd.z + q.ty - 1) / q.ty;
     const int64_t t = item - q.tile_base[f];
     const int bx = int(t % nbx), by = int((t / nbx) % nby), bz = int(t / (int64_t(nbx) * nby));
+    const int lx = pos % tx, ly = (pos / tx) % ty, lz = pos / (tx * ty);
     const int x = bx * q.tx + lx, y = by * q.ty + ly, z = bz * q.tz + lz;
-    const bool act0 = x < fd.y && y < fd.z && z < fd.w;
-    const int v0 = act0 ? fd.x + x + fd.y * (y + fd.z * z) : 0;
-    k3_block(rank, G, code_out, down_out, co, T, sh, act0, v0);
+    *act = x < fd.y && y < fd.z && z < fd.w;
+    return *act ? fd.x + x + fd.y * (y + fd.z * z) : 0;
+  };
+  int probe = 0;  // queues tried so far (uniform over the workgroup)
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      for (int b = 0; b < kK3Batch; ++b) {
+        s_item[b] = -1;
+        for (; probe < kTileQueues; ++probe) {
+          const int qi = int((blockIdx.x + probe) % kTileQueues);
+          const int64_t i = q.begin(qi) + int64_t(atomicAdd(q.head + qi, 1u));
+          if (i < q.begin(qi + 1)) {
+            s_item[b] = i;
+            break;
+          }
+        }
+      }
+      s_next = 0;
+    }
+    if (tid < 16) s_hist[tid] = 0;
+    __syncthreads();
+    if (s_item[0] < 0) break;  // the whole workgroup leaves together
+    // sort the batch's vertices by their number of lower neighbours (vertices
+    // outside the grid count as 0, with the cheapest)
+    int key[kK3Batch];
+    unsigned int within[kK3Batch];
+#pragma unroll
+    for (int b = 0; b < kK3Batch; ++b) {
+      bool act;
+      const int v = vertex(s_item[b], tid, &act);
+      int c = 0;
+      if (act) {
+        const auto S0 = G.site(v);
+        int x, y, z;
+        S0.xyz(v, &x, &y, &z);
+        const uint32_t valid = S0.valid_at(x, y, z);
+        const int r0 = rank[v];
+#pragma unroll
+        for (int k = 0; k < 14; ++k)
+          if ((valid >> k) & 1u) c += rank[v + S0.nb(k)] < r0 ? 1 : 0;
+      }
+      key[b] = c;
+      within[b] = atomicAdd(&s_hist[c], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned int acc = 0;
+      for (int b = 0; b < 16; ++b) {
+        const unsigned int t = s_hist[b];
+        s_hist[b] = acc;
+        acc += t;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kK3Batch; ++b)
+      s_order[s_hist[key[b]] + within[b]] = uint16_t(b * kGradThreads + tid);
+    __syncthreads();
+    constexpr int kGroups = kK3Batch * kGradThreads / 64;
+    for (;;) {
+      // keep the LDS table reads inside the loop (hoisted, they would hold
+      // a hundred registers and cost a wave per SIMD)
+      asm volatile("" ::: "memory");
+      int g = 0;
+      if (lane == 0) g = atomicAdd(&s_next, 1);
+      g = __shfl(g, 0, 64);
+      if (g >= kGroups) break;
+      const int slot = s_order[(kGroups - 1 - g) * 64 + int(lane)];  // heaviest first
+      bool act;
+      const int v = vertex(s_item[slot / kGradThreads], slot % kGradThreads, &act);
+      k3_block<true>(rank, G, code_out, down_out, co, T, sh, act, v);
+    }
   }
 }
 
