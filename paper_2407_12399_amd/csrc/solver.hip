@@ -21,7 +21,9 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <queue>
+#include <sched.h>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -480,6 +482,41 @@ void fetch_points(ts_ctx* ctx, const PersistenceResult& R, const float* x, std::
 
 namespace {
 
+// Values |p - q_u|^2 - s_u of one KD-tree leaf's members (coordinates and
+// scores contiguous; a masked member has score -inf and value +inf), and the
+// bit mask of the members whose value is <= thr.  Built
+// for AVX-512, AVX2 and baseline x86-64, picked at load time by the CPU; the
+// same IEEE operations in the same order in every variant (no contraction),
+// so all give the same values bit for bit.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TS_HOST_CLONES
+#else
+#define TS_HOST_CLONES __attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+TS_HOST_CLONES uint64_t leaf_values(const double* __restrict__ x, const double* __restrict__ y,
+                                    const double* __restrict__ s, int cnt, double px, double py,
+                                    double thr, double* __restrict__ out) {
+  for (int u = 0; u < cnt; ++u) {
+    const double dx = x[u] - px, dy = y[u] - py;
+    out[u] = (dx * dx + dy * dy) - s[u];
+  }
+  uint64_t m = 0;
+  for (int u = 0; u < cnt; ++u) m |= uint64_t(out[u] <= thr) << u;
+  return m;
+}
+
+// Largest of a leaf's scores (-inf if all are masked): max is exact, so the
+// four running maxima of the vector form give the scalar loop's result.
+TS_HOST_CLONES double leaf_max(const double* __restrict__ s, int cnt) {
+  double m[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  int u = 0;
+  for (; u + 4 <= cnt; u += 4)
+    for (int l = 0; l < 4; ++l) m[l] = m[l] < s[u + l] ? s[u + l] : m[l];
+  for (; u < cnt; ++u) m[0] = m[0] < s[u] ? s[u] : m[0];
+  const double a = m[0] < m[1] ? m[1] : m[0], b = m[2] < m[3] ? m[3] : m[2];
+  return a < b ? b : a;
+}
+
 // 2D KD-tree over the targets (birth, death).  Every target j carries a
 // score s_j (or "masked"); a node keeps the largest unmasked score below it.
 // best(p) returns the unmasked target minimising |p - q_j|^2 - s_j.  Leaf
@@ -494,8 +531,7 @@ struct KDTree {
   std::vector<int> idx, leaf_of, pos_of;
   std::vector<double> s;     // score by target id
   std::vector<char> masked;  // mask by target id
-  std::vector<double> lx, ly, ls;  // coordinates and score in tree order
-  std::vector<char> lm;            // mask in tree order
+  std::vector<double> lx, ly, ls;  // coordinates and score (-inf if masked) in tree order
   const double* X = nullptr;
   const double* Y = nullptr;
   static constexpr double NEG = -std::numeric_limits<double>::infinity();
@@ -504,7 +540,7 @@ struct KDTree {
   // point too, since every step of both is monotone), so this only sets the
   // balance between node visits and leaf scans: on the auction's problems 32
   // is about 12 % faster than 8, and 16 or 64 are no faster than 32.
-  static constexpr int kLeaf = 32;
+  static constexpr int kLeaf = 64;
 
   void build(const double* x, const double* y, int k) {
     X = x;
@@ -520,7 +556,6 @@ struct KDTree {
     lx.resize(k);
     ly.resize(k);
     ls.assign(k, 0.0);
-    lm.assign(k, 0);
     for (int t = 0; t < k; ++t) {
       pos_of[idx[t]] = t;
       lx[t] = X[idx[t]];
@@ -563,17 +598,13 @@ struct KDTree {
   void set_all(const std::vector<double>& sc) {
     s = sc;
     std::fill(masked.begin(), masked.end(), 0);
-    std::fill(lm.begin(), lm.end(), 0);
     for (size_t t = 0; t < idx.size(); ++t) ls[t] = s[idx[t]];
     for (int i = int(nodes.size()) - 1; i >= 0; --i) refresh(i);
   }
   void refresh(int id) {
     Node& nd = nodes[id];
     if (nd.left < 0) {
-      double m = NEG;
-      for (int t = nd.begin; t < nd.end; ++t)
-        if (!lm[t]) m = std::max(m, ls[t]);
-      nd.smax = m;
+      nd.smax = leaf_max(&ls[nd.begin], nd.end - nd.begin);
     } else {
       nd.smax = std::max(nodes[nd.left].smax, nodes[nd.right].smax);
     }
@@ -584,8 +615,7 @@ struct KDTree {
     const double now = mask ? NEG : sj;
     s[j] = sj;
     masked[j] = mask;
-    ls[pos_of[j]] = sj;
-    lm[pos_of[j]] = mask;
+    ls[pos_of[j]] = now;
     const int leaf = leaf_of[j];
     if (now >= old) {  // the maxima on the path can only rise, to `now`
       for (int id = leaf; id >= 0 && nodes[id].smax < now; id = nodes[id].parent) nodes[id].smax = now;
@@ -647,18 +677,17 @@ struct KDTree {
       if (top.first > *v2) continue;
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
-        // values of the whole leaf first (a straight loop the compiler
-        // vectorises), then the running two smallest
+        // values of the whole leaf first (vector code), then the running
+        // two smallest among those not above the second smallest so far
+        // (which only falls during the scan)
         double vals[kLeaf];
         const int cnt = nd.end - nd.begin;
-        for (int u = 0; u < cnt; ++u) {
-          const int t = nd.begin + u;
-          const double dx = lx[t] - px, dy = ly[t] - py;
-          vals[u] = lm[t] ? INFINITY : (dx * dx + dy * dy) - ls[t];
-        }
-        for (int u = 0; u < cnt; ++u) {
+        uint64_t m = leaf_values(&lx[nd.begin], &ly[nd.begin], &ls[nd.begin], cnt, px, py, *v2, vals);
+        while (m) {
+          const int u = __builtin_ctzll(m);
+          m &= m - 1;
           const double v = vals[u];
-          if (!(v <= *v2)) continue;  // neither of the two smallest (or masked)
+          if (!(v <= *v2)) continue;
           const int j = idx[nd.begin + u];
           if (j != h0 && j != h1) offer(v, j);  // the hints are counted already
         }
@@ -693,7 +722,7 @@ struct KDTree {
       if (nd.smax == NEG || !(d2box(nd, px, py) - nd.smax < thr)) continue;
       if (nd.left < 0) {
         for (int t = nd.begin; t < nd.end; ++t) {
-          if (lm[t]) continue;
+          if (ls[t] == NEG) continue;  // masked
           const double dx = lx[t] - px, dy = ly[t] - py;
           if ((dx * dx + dy * dy) - ls[t] < thr) out->push_back(idx[t]);
         }
@@ -726,7 +755,7 @@ struct KDTree {
       const Node& nd = nodes[top.second];
       if (nd.left < 0) {
         for (int t = nd.begin; t < nd.end; ++t) {
-          if (lm[t]) continue;
+          if (ls[t] == NEG) continue;  // masked
           const double dx = lx[t] - px, dy = ly[t] - py;
           const double v = (dx * dx + dy * dy) - ls[t];
           if (v < *val || (v == *val && idx[t] < bj)) {
@@ -965,6 +994,111 @@ Certificate certify_assignment(const std::vector<double>& pb, const std::vector<
 
 }  // namespace
 
+// The searches of a window of queued bidders: for b < n, the two best items
+// of tree for the query (qx[id], qy[id]), id = ids[b], started from the
+// bidder's hints (read, not written: the caller keeps them in out[b]).
+struct Found {
+  int j, h0, h1;  // best item, and the hints the search leaves (best, second)
+  double c1, c2;  // smallest and second smallest values
+};
+struct SearchJob {
+  const KDTree* tree;
+  const double* qx;
+  const double* qy;
+  const int* ids;
+  const int* hints;
+  Found* out;
+  void operator()(int b) const {
+    const int id = ids[b];
+    Found& F = out[b];
+    int h[2] = {hints[2 * size_t(id)], hints[2 * size_t(id) + 1]};
+    F.j = tree->best2(qx[id], qy[id], &F.c1, &F.c2, h);
+    F.h0 = h[0];
+    F.h1 = h[1];
+  }
+};
+
+// Host threads that run a window's searches at once.  run(job, n) spreads
+// job(0..n-1) over the workers and the calling thread and returns when all
+// are done; the searches only read shared state.  Workers spin between
+// windows (they come microseconds apart during an auction) and yield after a
+// while.  Extra threads come from a process-wide budget (several auctions run
+// at once: the dimensions of a field, the fields of a batch), so that the
+// host is not oversubscribed; a pool that gets no thread runs everything on
+// the caller.
+class WindowPool {
+ public:
+  explicit WindowPool(int want) {
+    int got = 0;
+    for (int have = budget().load(); want > 0 && have > 0;) {
+      const int take = std::min(want, have);
+      if (budget().compare_exchange_weak(have, have - take)) {
+        got = take;
+        break;
+      }
+    }
+    for (int t = 0; t < got; ++t) th_.emplace_back([this] { loop(); });
+  }
+  ~WindowPool() {
+    stop_.store(true, std::memory_order_release);
+    gen_.fetch_add(1, std::memory_order_acq_rel);
+    for (std::thread& t : th_) t.join();
+    budget().fetch_add(int(th_.size()));
+  }
+  int threads() const { return int(th_.size()) + 1; }
+  // threads an auction asks for: half the budget (two large auctions, those
+  // of dimensions 0 and 2, usually run at once)
+  static int share() {
+    static const int s = std::max(1, budget().load() / 2);
+    return s;
+  }
+  void run(const SearchJob& job, int n) {
+    job_ = job;
+    n_ = n;
+    next_.store(0, std::memory_order_relaxed);
+    busy_.store(int(th_.size()), std::memory_order_relaxed);
+    gen_.fetch_add(1, std::memory_order_acq_rel);
+    work();
+    while (busy_.load(std::memory_order_acquire) > 0) pause();
+  }
+
+ private:
+  // threads beyond one per running auction: TS_ASSIGN_THREADS, else the CPUs
+  // this process may run on (at most 16) less two
+  static std::atomic<int>& budget() {
+    static std::atomic<int> b{[] {
+      if (const char* e = std::getenv("TS_ASSIGN_THREADS")) return std::max(0, std::atoi(e));
+      cpu_set_t set;
+      int cpus = 1;
+      if (sched_getaffinity(0, sizeof(set), &set) == 0) cpus = CPU_COUNT(&set);
+      return std::max(0, std::min(cpus, 16) - 2);
+    }()};
+    return b;
+  }
+  static void pause() { __builtin_ia32_pause(); }
+  void work() {
+    for (int i; (i = next_.fetch_add(1, std::memory_order_relaxed)) < n_;) job_(i);
+  }
+  void loop() {
+    int seen = 0;
+    for (;;) {
+      int g;
+      for (int spins = 0; (g = gen_.load(std::memory_order_acquire)) == seen;)
+        if (++spins < 20000) pause();
+        else std::this_thread::yield();
+      seen = g;
+      if (stop_.load(std::memory_order_acquire)) return;
+      work();
+      busy_.fetch_sub(1, std::memory_order_acq_rel);
+    }
+  }
+  std::vector<std::thread> th_;
+  std::atomic<int> gen_{0}, next_{0}, busy_{0};
+  std::atomic<bool> stop_{false};
+  SearchJob job_{};
+  int n_ = 0;
+};
+
 // Auction on the rectangular form of the problem.  Sending every target to
 // the diagonal costs sum diag(q); from there, point p pays
 // c'(p,q) = c(p,q) - diag(q) for taking target q (at most one point per
@@ -1007,8 +1141,24 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
   pt.build(pb.data(), pd.data(), m);
   std::vector<int> hints(2 * size_t(std::max(m, 1)), -1), rhints(2 * size_t(std::max(k, 1)), -1);
   auto cprime = [&](int i, int j) { return pair_cost(pb[i], pd[i], qb[j], qd[j]) - dq[j]; };
+  // Windows of queued bidders search at once against the state before the
+  // window (read-only), then commit in queue order as the serial auction
+  // would.  Within a phase, forward bids only raise target prices and reverse
+  // bids only lower what points pay, so every search value can only grow
+  // while a window commits: a result whose best and second-best items were
+  // not changed by an earlier commit of the window is the serial search's
+  // result (the same minimum, lowest id attaining it, and second value); any
+  // other is searched again at its turn.  The bids, prices and matching are
+  // those of the serial auction.
+  constexpr int kWindow = 128, kMinWindow = 4;
+  auto pool_owner = std::make_unique<WindowPool>(m + k >= 4096 ? WindowPool::share() : 0);
+  WindowPool& pool = *pool_owner;
+  std::vector<Found> found(kWindow);
+  std::vector<int> ttouch(k, 0), ptouch(m, 0);  // window stamp of the last change
+  int stamp = 0;
   auto set_price = [&](int j, double v) {
     pi[j] = v;
+    ttouch[j] = stamp;
     tt.update(j, dq[j] - v, false);
   };
   double eps = W / 4.0;
@@ -1020,11 +1170,35 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
     std::fill(holds.begin(), holds.end(), -1);
     queue.clear();
     for (int i = 0; i < m; ++i) queue.push_back(i);
-    int64_t fbids = 0, rbids = 0;
+    int64_t fbids = 0, rbids = 0, redone = 0, nwin = 0;
+    double twin = 0;
+    const double tphase = now_s();
+    size_t wbeg = 0, wend = 0;  // the current window of searched bidders
     for (size_t head = 0; head < queue.size(); ++head) {
+      if (head >= wend && pool.threads() > 1 && queue.size() - head >= size_t(kMinWindow)) {
+        wbeg = head;
+        wend = head + std::min(queue.size() - head, size_t(kWindow));
+        ++stamp;
+        const double tw = now_s();
+        pool.run({&tt, pb.data(), pd.data(), &queue[head], hints.data(), found.data()},
+                 int(wend - head));
+        twin += now_s() - tw;
+        ++nwin;
+      }
       const int i = queue[head];
       double c1, c2;  // the two smallest c' + pi over the targets
-      const int j = tt.best2(pb[i], pd[i], &c1, &c2, &hints[2 * size_t(i)]);
+      int j;
+      const Found* F = head < wend ? &found[head - wbeg] : nullptr;
+      if (F && (F->h0 < 0 || ttouch[F->h0] != stamp) && (F->h1 < 0 || ttouch[F->h1] != stamp)) {
+        j = F->j;
+        c1 = F->c1;
+        c2 = F->c2;
+        hints[2 * size_t(i)] = F->h0;
+        hints[2 * size_t(i) + 1] = F->h1;
+      } else {
+        if (F) ++redone;
+        j = tt.best2(pb[i], pd[i], &c1, &c2, &hints[2 * size_t(i)]);
+      }
       if (++fbids > bid_cap) throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
       if (j < 0 || dp[i] <= c1) {  // its diagonal (ties go to the diagonal)
         holds[i] = k;
@@ -1046,12 +1220,34 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       if (owner[j] < 0 && pi[j] > 0) rqueue.push_back(j);
     if (!rqueue.empty()) {
       pt.set_all(pay);
+      size_t wbeg = 0, wend = 0;
       for (size_t head = 0; head < rqueue.size(); ++head) {
+        if (head >= wend && pool.threads() > 1 && rqueue.size() - head >= size_t(kMinWindow)) {
+          wbeg = head;
+          wend = head + std::min(rqueue.size() - head, size_t(kWindow));
+          ++stamp;
+          const double tw = now_s();
+          pool.run({&pt, qb.data(), qd.data(), &rqueue[head], rhints.data(), found.data()},
+                   int(wend - head));
+          twin += now_s() - tw;
+          ++nwin;
+        }
         const int j = rqueue[head];
         if (owner[j] >= 0 || !(pi[j] > 0)) continue;
         if (++rbids > bid_cap) throw Error(TS_ERR_INTERNAL, "assignment: auction did not settle");
         double v1, v2;  // the two smallest |p - q|^2 - pay_p over the points
-        const int i1 = pt.best2(qb[j], qd[j], &v1, &v2, &rhints[2 * size_t(j)]);
+        int i1;
+        const Found* F = head < wend ? &found[head - wbeg] : nullptr;
+        if (F && (F->h0 < 0 || ptouch[F->h0] != stamp) && (F->h1 < 0 || ptouch[F->h1] != stamp)) {
+          i1 = F->j;
+          v1 = F->c1;
+          v2 = F->c2;
+          rhints[2 * size_t(j)] = F->h0;
+          rhints[2 * size_t(j) + 1] = F->h1;
+        } else {
+          if (F) ++redone;
+          i1 = pt.best2(qb[j], qd[j], &v1, &v2, &rhints[2 * size_t(j)]);
+        }
         const double g1 = dq[j] - v1, g2 = dq[j] - v2;  // pay_p - c'(p, q)
         if (i1 < 0 || g1 <= eps) {
           set_price(j, 0.0);
@@ -1062,6 +1258,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
         owner[j] = i1;
         holds[i1] = j;
         pay[i1] = cprime(i1, j) + pi[j];
+        ptouch[i1] = stamp;
         pt.update(i1, pay[i1], false);
         if (old < k) {
           owner[old] = -1;
@@ -1070,8 +1267,11 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
       }
     }
     if (trace)
-      std::fprintf(stderr, "[topsimp] auction phase %d eps %.3g bids %lld forward, %lld reverse\n",
-                   phase, eps, (long long)fbids, (long long)rbids);
+      std::fprintf(stderr,
+                   "[topsimp] auction phase %d eps %.3g bids %lld forward, %lld reverse, %lld "
+                   "searched again; %.3f s, %lld windows %.3f s\n",
+                   phase, eps, (long long)fbids, (long long)rbids, (long long)redone,
+                   now_s() - tphase, (long long)nwin, twin);
     if (eps <= eps_final) break;
     if (gap_rel > 0) {
       // dual bound: for prices pi >= 0 and u_p = the cheapest option of p,
@@ -1094,6 +1294,7 @@ double assign_auction(const std::vector<double>& pb, const std::vector<double>& 
     }
     eps = std::max(eps / 4.0, eps_final);  // a factor of 4 needs the fewest bids on noisy diagrams
   }
+  pool_owner.reset();  // the workers are not needed after the bids
   // the state as one of the square problem: target j at price pi_j - diag(q_j)
   // and the point copies at 0, except that a point on its diagonal may pay up
   // to its margin for its own copy (that headroom keeps the certificate's

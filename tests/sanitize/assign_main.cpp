@@ -1,7 +1,7 @@
 // Host-sanitizer driver of the library's assignment (Eq. (1) on the reduced
 // problem, Sec. 4.3): dense instances large enough for the epsilon-scaled
-// auction, its optimality certificate and the KD-trees and heaps around
-// them, plus small ones for the shortest-path branch and the reductions.
+// auction (the largest with its searches on several threads), its optimality
+// certificate and the KD-trees and heaps around them, plus small ones for the shortest-path branch and the reductions.
 // Built with AddressSanitizer and UndefinedBehaviorSanitizer on the host
 // code only; needs no GPU.
 #include <cmath>
@@ -16,7 +16,7 @@ int main() {
   std::mt19937_64 g(7);
   std::normal_distribution<double> nb(0.0, 0.02), nd(0.0, 0.05);
   std::uniform_real_distribution<double> u(0.0, 1.0);
-  const int sizes[][2] = {{1500, 1400}, {1800, 1650}, {40, 35}, {700, 4}, {5, 600}, {0, 7}, {9, 0}};
+  const int sizes[][2] = {{1500, 1400}, {1800, 1650}, {2300, 2100}, {40, 35}, {700, 4}, {5, 600}, {0, 7}, {9, 0}};
   for (const auto& sz : sizes) {
     const int m = sz[0], k = sz[1];
     const bool dense = m >= 1000;

@@ -159,3 +159,46 @@ def test_assignment_bad_arguments(ts):
     assert rc == -1
     rc = ts.lib().ts_assign(2, None, None, 0, None, None, out.ctypes.data, cost.ctypes.data)
     assert rc == -1
+
+
+_SERIAL_VS_THREADED = r"""
+import re, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+import paper_2407_12399_amd as ts
+rng = np.random.default_rng(77)
+m, k = 3200, 2900
+pb = rng.normal(0, 0.02, m); pd = pb + np.abs(rng.normal(0, 0.05, m))
+qb = rng.normal(0, 0.02, k); qd = qb + np.abs(rng.normal(0, 0.05, k))
+pb, pd, qb, qd = [a.astype(np.float32).astype(np.float64) for a in (pb, pd, qb, qd)]
+mt, ct = ts.assign(pb, pd, qb, qd)
+np.save(sys.argv[1], mt)
+print(repr(ct))
+"""
+
+
+def test_threaded_auction_is_the_serial_auction(ts, tmp_path):
+    """The auction searches a window of queued bidders on several threads and
+    commits them in queue order, searching again where an earlier commit of
+    the window changed the result: every phase makes the serial auction's
+    bids (forward and reverse counts equal, phase by phase) and the matching
+    is the same, match by match."""
+    import subprocess
+    import sys
+    script = tmp_path / "run.py"
+    script.write_text(_SERIAL_VS_THREADED.format(root=ROOT))
+    out = {}
+    for threads in ("0", "4"):
+        env = dict(os.environ, TS_ASSIGN_THREADS=threads, TS_TRACE="1")
+        r = subprocess.run([sys.executable, str(script), str(tmp_path / f"m{threads}.npy")],
+                           capture_output=True, text=True, env=env, timeout=600)
+        assert r.returncode == 0, r.stderr[-2000:]
+        bids = re.findall(r"auction phase (\d+) eps \S+ bids (\d+) forward, (\d+) reverse",
+                          r.stderr)
+        windows = re.findall(r"(\d+) windows", r.stderr)
+        out[threads] = (bids, float(r.stdout.strip()), np.load(tmp_path / f"m{threads}.npy"),
+                        sum(int(w) for w in windows))
+    (b0, c0, m0, w0), (b4, c4, m4, w4) = out["0"], out["4"]
+    assert len(b0) > 5 and b0 == b4
+    assert w0 == 0 and w4 > 0  # the threaded run did search windows in parallel
+    assert np.array_equal(m0, m4) and c0 == c4

@@ -3,7 +3,8 @@
 Two drivers are built in a temporary directory and run:
   - the library's host-side assignment (KD-trees, the auction, its
     optimality certificate, heaps, exact reductions; Eq. (1), Sec. 4.3) on
-    instances of up to 1800 x 1650 points and targets, through ts_assign and
+    instances of up to 2300 x 2100 points and targets (the auction's searches
+    on several threads), through ts_assign and
     ts_assign_auction; the HIP sources are compiled with the sanitizers on
     their host pass only;
   - the CPU oracle (diagram, full reduction, a short solve and one
