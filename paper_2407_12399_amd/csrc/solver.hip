@@ -1509,16 +1509,21 @@ std::vector<int> top_candidates(KDTree* tree, const std::vector<double>& ab,
 }
 
 // Indices a of the query set with some b of the tree at a positive saving
-// (same margin).
+// (same margin).  The searches of a large query set run on a WindowPool.
 std::vector<int> has_candidate(const KDTree& tree, const std::vector<double>& ab,
                                const std::vector<double>& ad, const std::vector<double>& da,
                                double scale) {
-  std::vector<int> out;
-  for (size_t a = 0; a < ab.size(); ++a) {
-    double v;
-    const int b = tree.best(ab[a], ad[a], &v);
-    if (b >= 0 && v < da[a] + 1e-9 * (da[a] + scale) + 1e-300) out.push_back(int(a));
+  const int n = int(ab.size());
+  std::vector<int> ids(n), hints(2 * size_t(n), -1);
+  for (int a = 0; a < n; ++a) ids[a] = a;
+  std::vector<Found> res(static_cast<size_t>(n));
+  {
+    WindowPool pool(n >= 4096 ? WindowPool::share() : 0);
+    pool.run({&tree, ab.data(), ad.data(), ids.data(), hints.data(), res.data()}, n);
   }
+  std::vector<int> out;
+  for (int a = 0; a < n; ++a)
+    if (res[a].j >= 0 && res[a].c1 < da[a] + 1e-9 * (da[a] + scale) + 1e-300) out.push_back(a);
   return out;
 }
 
