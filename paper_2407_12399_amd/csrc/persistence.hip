@@ -1619,7 +1619,8 @@ struct BoundaryCommon {
   int* err;
   unsigned long long* stats;
   int max_steps;
-  int wave_cap;  // queue capacity of the wave kernel (<= 256)
+  int wave_cap;   // queue capacity of the wave kernel's first pass (<= 256)
+  int wave2_cap;  // and of its second pass (<= 1024)
 };
 
 template <class Geo>
@@ -1648,16 +1649,18 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
   return uint32_t(__builtin_amdgcn_readlane(int(v), lane));
 }
 
-// A max-priority queue of up to 256 (key, ref) entries held by one wave in
-// registers, sorted descending over the index i = 64 j + lane (4 entries a
+// A max-priority queue of up to 64 R (key, ref) entries held by one wave in
+// registers, sorted descending over the index i = 64 j + lane (R entries a
 // lane; empty entries have key 0, below every edge key).  Every lane makes
 // every call, and the values returned are the same in all lanes.  A pop
-// shifts the whole list down by one place and a push finds its place with
-// four ballots and shifts the tail up: a few dozen VALU instructions instead
-// of a chain of dependent LDS accesses per heap level.
-struct WaveList {
-  static constexpr int kCap = 256;
-  uint32_t khi[4], klo[4], r[4];
+// shifts the list down by one place and a push finds its place with one
+// ballot per occupied register and shifts the tail up: a few dozen VALU
+// instructions instead of a chain of dependent LDS accesses per heap level.
+// Registers past the last entry are neither read nor moved.
+template <int R>
+struct WaveListR {
+  static constexpr int kCap = 64 * R;
+  uint32_t khi[R], klo[R], r[R];
   int n;
   int lane;
   int cap = kCap;  // may be set lower (tests of the fallback)
@@ -1666,7 +1669,7 @@ struct WaveList {
   __device__ void clear() {
     lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) khi[j] = klo[j] = r[j] = 0;
+    for (int j = 0; j < R; ++j) khi[j] = klo[j] = r[j] = 0;
     n = 0;
   }
   __device__ int size() const { return n; }
@@ -1676,11 +1679,11 @@ struct WaveList {
     *kk = top_key();
     *rr = top_ref();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {  // entry i takes entry i + 1
+    for (int j = 0; j < R; ++j) {  // entry i takes entry i + 1
       if (64 * j >= n) break;  // registers past the last entry hold zeros
-      const uint32_t ch = j < 3 ? lane_value(khi[j + 1], 0) : 0u;
-      const uint32_t cl = j < 3 ? lane_value(klo[j + 1], 0) : 0u;
-      const uint32_t cr = j < 3 ? lane_value(r[j + 1], 0) : 0u;
+      const uint32_t ch = j < R - 1 ? lane_value(khi[j + 1], 0) : 0u;
+      const uint32_t cl = j < R - 1 ? lane_value(klo[j + 1], 0) : 0u;
+      const uint32_t cr = j < R - 1 ? lane_value(r[j + 1], 0) : 0u;
       khi[j] = wave_down(khi[j], ch);
       klo[j] = wave_down(klo[j], cl);
       r[j] = wave_down(r[j], cr);
@@ -1691,9 +1694,10 @@ struct WaveList {
     if (n >= cap) return false;
     int p = 0;  // entries above the new one
 #pragma unroll
-    for (int j = 0; j < 4; ++j) p += __popcll(__ballot(join(khi[j], klo[j]) > kk));
+    for (int j = 0; j < R; ++j)  // empty registers hold keys 0, below every edge key
+      if (R <= 4 || 64 * j < n) p += __popcll(__ballot(join(khi[j], klo[j]) > kk));
 #pragma unroll
-    for (int j = 3; j >= 0; --j) {  // entry i > p takes entry i - 1
+    for (int j = R - 1; j >= 0; --j) {  // entry i > p takes entry i - 1
       if (64 * j > n) continue;  // registers past the new last entry stay zero
       const uint32_t ch = j > 0 ? lane_value(khi[j - 1], 63) : 0u;
       const uint32_t cl = j > 0 ? lane_value(klo[j - 1], 63) : 0u;
@@ -1940,17 +1944,19 @@ k_d1_boundary_lanes(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int6
                            kLaneRows);
 }
 
+constexpr int kWaveRegs = 4, kWaveRegs2 = 16;  // entries a lane in the two wave passes
 // Long columns: one column per wave, the queue in the wave's registers (up to
-// 256 edges), rows in LDS; the pops are sequential, each a few cross-lane
-// moves, with the next vertex group's code and neighbour ranks loaded ahead.
+// 64 R edges: 256, and 1024 for the columns that outgrow that), rows in LDS;
+// the pops are sequential, each a few cross-lane moves, with the next vertex
+// group's code and neighbour ranks loaded ahead.
 constexpr int kWaveRows = 1024;
-template <class Geo>
+template <class Geo, int R>
 __global__ void __launch_bounds__(64)
 k_d1_boundary_wave(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int64_t ntodo,
                    unsigned int* __restrict__ next) {
   __shared__ uint32_t s_rows[kWaveRows];
-  WaveList H;
-  H.cap = A.wave_cap;
+  WaveListR<R> H;
+  H.cap = R == kWaveRegs ? A.wave_cap : A.wave2_cap;
   for (;;) {  // columns are taken from a shared counter, so long ones do not queue up
     unsigned int w = 0;
     if (threadIdx.x == 0) w = atomicAdd(next, 1u);
@@ -3467,14 +3473,18 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     BA.stats = nullptr;
     // launch parameters, overridable for tuning (TS_D1_*); results do not depend on them
     const int pass0_steps = env_int("TS_D1_STEPS", 512, 16, 1 << 20);
-    BA.wave_cap = env_int("TS_D1_WAVE_CAP", WaveList::kCap, 4, WaveList::kCap);
+    BA.wave_cap = env_int("TS_D1_WAVE_CAP", WaveListR<kWaveRegs>::kCap, 4, WaveListR<kWaveRegs>::kCap);
+    BA.wave2_cap =
+        env_int("TS_D1_WAVE2_CAP", WaveListR<kWaveRegs2>::kCap, 4, WaveListR<kWaveRegs2>::kCap);
     int64_t ntodo = ncols;
     const uint32_t* list = nullptr;  // first pass: every column
     for (int pass = 0, kind = 0;; ++pass) {
       // kind 0 (every column): one lane per column, a small heap in LDS and
       // a bounded number of pops; kind 1: the rest, one column per wave, the
-      // queue in the wave's registers; kind 2: columns whose queue outgrows
-      // that, one column per wave with a large heap in LDS
+      // queue in the wave's registers (256 entries); kind 2: columns whose
+      // queue outgrows that, the same with 1024 entries; kind 3: columns
+      // whose queue outgrows that too, one column per wave with a large heap
+      // in LDS
       const bool lds = kind >= 1;
       uint32_t* out = todo[pass & 1];
       TS_HIP(hipMemsetAsync(nretry, 0, sizeof(unsigned int), s));
@@ -3501,10 +3511,13 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
           BoundaryArgs<decltype(G)> A;
           static_cast<BoundaryCommon&>(A) = BA;
           A.G = G;
-          if (kind == 1) {
+          if (kind == 1 || kind == 2) {
             unsigned int* next = ws.get<unsigned int>("d1.bnext", 1);
             k_fill_u32<<<1, 1, 0, s>>>(next, 1, 0u);
-            k_d1_boundary_wave<<<nb, 64, 0, s>>>(A, list, ntodo, next);
+            if (kind == 1)
+              k_d1_boundary_wave<decltype(G), kWaveRegs><<<nb, 64, 0, s>>>(A, list, ntodo, next);
+            else
+              k_d1_boundary_wave<decltype(G), kWaveRegs2><<<nb, 64, 0, s>>>(A, list, ntodo, next);
           } else {
             k_d1_boundary_lds<<<nb, 64, 0, s>>>(A, list, ntodo);
           }
@@ -3519,7 +3532,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
                      "[topsimp] d1 boundary pass %d: columns %lld %s steps %llu max %llu max heap "
                      "%llu long %llu retried %llu; log2 histogram:",
                      pass, (long long)ntodo,
-                     kind == 0 ? "lanes" : (kind == 1 ? "wave" : "lds"),
+                     kind == 0 ? "lanes" : (kind == 1 ? "wave" : (kind == 2 ? "wave1024" : "lds")),
                      h[0], h[1], h[2], h[3], h[4]);
         for (int b = 0; b < 21; ++b) std::fprintf(stderr, " %llu", h[5 + b]);
         std::fprintf(stderr, "; largest heap <= 8, 16, 32, 64, 128, more:");
@@ -3534,7 +3547,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       if (pass > 12) throw Error(TS_ERR_INTERNAL, "boundary extraction did not finish");
       list = out;
       const int done_kind = kind;
-      kind = std::min(kind + 1, 2);
+      kind = std::min(kind + 1, 3);
       if (read_scalar(bfull, s)) {
         // grow the pool keeping its contents
         // (failed reservations past the old capacity were never written)
@@ -3548,7 +3561,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         pool.cap = ncap;
         k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(keep));
         TS_HIP(hipGetLastError());
-      } else if (done_kind == 2) {
+      } else if (done_kind == 3) {
         throw Error(TS_ERR_CAPACITY, "saddle-saddle boundary exceeds the LDS heap");
       }
     }

@@ -191,13 +191,15 @@ def test_column_pool_growth(gpu, orc, monkeypatch):
     _same_pairs(gpu.diagram(_t(f)), ref)
 
 
-@pytest.mark.parametrize("steps,cap", [(16, 256), (16, 4)])
-def test_boundary_fallback_kinds(gpu, orc, monkeypatch, steps, cap):
+@pytest.mark.parametrize("steps,cap,cap2", [(16, 256, 1024), (16, 4, 1024), (16, 4, 4)])
+def test_boundary_fallback_kinds(gpu, orc, monkeypatch, steps, cap, cap2):
     """Saddle-saddle boundaries: with a first pass cut at 16 pops, the columns
-    go on to the wave-queue kernel, and with that queue cut to 4 edges, on to
-    the LDS-heap kernel; every route gives the oracle's diagram."""
+    go on to the wave-queue kernel (256 entries); with that queue cut to 4
+    edges, on to the 1024-entry wave queue; with that cut to 4 edges too, on
+    to the LDS-heap kernel; every route gives the oracle's diagram."""
     monkeypatch.setenv("TS_D1_STEPS", str(steps))
     monkeypatch.setenv("TS_D1_WAVE_CAP", str(cap))
+    monkeypatch.setenv("TS_D1_WAVE2_CAP", str(cap2))
     f = fields.workload("filament_256", seed=3, dims=(48, 40, 36))
     _same_pairs(gpu.diagram(_t(f)), orc.diagram(f))
 
