@@ -1176,6 +1176,15 @@ __global__ void k_pos_map(const int32_t* __restrict__ ids, int64_t m, int32_t* _
   if (i < m) pos_of[ids[i]] = int32_t(i);
 }
 
+// After the D0 pairing: the position of a critical edge that dies in
+// dimension 0 (state != 1) becomes -1 - position, so that the saddle-saddle
+// boundary drops such an edge after one load.
+__global__ void k_pos_drop(const int32_t* __restrict__ ids, const uint8_t* __restrict__ state,
+                           int64_t m, int32_t* __restrict__ pos_of) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < m && state[i] != 1) pos_of[ids[i]] = int32_t(-1 - i);
+}
+
 // position of critical cell `id` (checked against the list), -1 if not critical
 __device__ __forceinline__ int64_t crit_pos(const int32_t* __restrict__ pos_of,
                                             const int32_t* __restrict__ ids, int64_t m, int id) {
@@ -1608,9 +1617,9 @@ struct BoundaryCommon {
   const int32_t* order;
   const uint4* code;
   const int32_t* edge_pos_of;  // canonical edge id -> position among critical edges
+                               // (-1 - position for those that die in dimension 0)
   const int32_t* edge_ids;     // critical edge ids by position
   int64_t nedges;
-  const uint8_t* edge_state;
   ColPool pool;
   uint64_t* col_desc;
   uint32_t* retry;
@@ -1845,13 +1854,15 @@ __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint
     if (ec == 6u) {          // critical edge
       const int lo = h + S.nb(k);
       const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
-      const int64_t f = crit_pos(A.edge_pos_of, A.edge_ids, A.nedges, eid);
-      if (f < 0) {
+      // its position among the critical edges, or -1 - position if it dies
+      // in dimension 0 (dropped)
+      const int32_t f = A.edge_pos_of[eid];
+      if (f < 0 && int64_t(-1 - f) < A.nedges) continue;
+      if (f < 0 || int64_t(f) >= A.nedges || A.edge_ids[f] != eid) {
         if (lead) atomicOr(A.err, 16);
         continue;
       }
       const uint32_t row = uint32_t(f);
-      if (A.edge_state[row] != 1) continue;  // dies in dimension 0: dropped
       ++toggles;
       if (!toggle_row(Rows, rstride, &rl, rcap, row, &moved)) {
         ok = false;
@@ -3426,6 +3437,8 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
   }
 
   // ---- K7: saddle-saddle ----
+  if (ne > 0)
+    k_pos_drop<<<blocks_for(ne), 256, 0, s>>>(R->cid[1], estate, ne, edge_pos_of);
   unsigned int* ncols_d = ws.get<unsigned int>("d1.ncols", 1);
   TS_HIP(hipMemsetAsync(ncols_d, 0, sizeof(unsigned int), s));
   uint32_t* cols = ws.get<uint32_t>("d1.cols", ntri + 1);
@@ -3466,7 +3479,6 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     BA.edge_pos_of = edge_pos_of;
     BA.edge_ids = R->cid[1];
     BA.nedges = ne;
-    BA.edge_state = estate;
     BA.nretry = nretry;
     BA.pool_full = bfull;
     BA.err = err;
