@@ -1157,6 +1157,13 @@ __global__ void k_iota_from(uint32_t* a, int64_t n, uint32_t base) {
   if (i < n) a[i] = base + uint32_t(i);
 }
 
+// sort keys that order a list of columns by decreasing index
+__global__ void k_desc_keys(const uint32_t* __restrict__ list, int64_t n, uint32_t top,
+                            uint32_t* __restrict__ keys) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = top - list[i];
+}
+
 __global__ void k_iota(uint32_t* a, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = uint32_t(i);
@@ -1659,18 +1666,29 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
 }
 
 // A max-priority queue of up to 64 R (key, ref) entries held by one wave in
-// registers, sorted descending over the index i = 64 j + lane (R entries a
-// lane; empty entries have key 0, below every edge key).  Every lane makes
-// every call, and the values returned are the same in all lanes.  A pop
-// shifts the list down by one place and a push finds its place with one
-// ballot per occupied register and shifts the tail up: a few dozen VALU
-// instructions instead of a chain of dependent LDS accesses per heap level.
-// Registers past the last entry are neither read nor moved.
+// registers, as a sorted run in the physical slots i = 64 j + lane (R slots a
+// lane): slots [0, off) are free, holding the all-ones key (above every edge
+// key), slots [off, off + n) hold the entries sorted descending, and the
+// slots after them key 0 (below every edge key).  Every lane makes every
+// call, and the values returned are the same in all lanes.
+//  - A pop reads slot off and frees it (off + 1); when the whole first
+//    register is free, the registers move down by one.
+//  - A push finds its place p with one ballot per register until the first
+//    register that is not entirely above the new key.  If a free slot
+//    precedes the run and p lies in the first register, the entries above
+//    the new one move down by one slot (a single register, a few VALU
+//    instructions): the common case of an expansion, whose first new edge
+//    stays near the top.  Otherwise the entries after p move up by one,
+//    register by register from the last occupied one down to p's, with the
+//    carries across registers read from lane 63; registers entirely above p
+//    are not touched.  When the slots run out while some are free, the run
+//    is moved down to slot 0 first (cross-lane permutes).
 template <int R>
 struct WaveListR {
   static constexpr int kCap = 64 * R;
   uint32_t khi[R], klo[R], r[R];
-  int n;
+  int n;    // entries
+  int off;  // free slots before them (< 64)
   int lane;
   int cap = kCap;  // may be set lower (tests of the fallback)
   __device__ static bool leader() { return (threadIdx.x & 63) == 0; }
@@ -1680,34 +1698,86 @@ struct WaveListR {
 #pragma unroll
     for (int j = 0; j < R; ++j) khi[j] = klo[j] = r[j] = 0;
     n = 0;
+    off = 0;
   }
   __device__ int size() const { return n; }
-  __device__ uint64_t top_key() const { return join(lane_value(khi[0], 0), lane_value(klo[0], 0)); }
-  __device__ uint32_t top_ref() const { return lane_value(r[0], 0); }
+  __device__ uint64_t top_key() const {
+    return join(lane_value(khi[0], off), lane_value(klo[0], off));
+  }
+  __device__ uint32_t top_ref() const { return lane_value(r[0], off); }
   __device__ void pop(uint64_t* kk, uint32_t* rr) {
     *kk = top_key();
     *rr = top_ref();
-#pragma unroll
-    for (int j = 0; j < R; ++j) {  // entry i takes entry i + 1
-      if (64 * j >= n) break;  // registers past the last entry hold zeros
-      const uint32_t ch = j < R - 1 ? lane_value(khi[j + 1], 0) : 0u;
-      const uint32_t cl = j < R - 1 ? lane_value(klo[j + 1], 0) : 0u;
-      const uint32_t cr = j < R - 1 ? lane_value(r[j + 1], 0) : 0u;
-      khi[j] = wave_down(khi[j], ch);
-      klo[j] = wave_down(klo[j], cl);
-      r[j] = wave_down(r[j], cr);
-    }
+    if (lane == off) khi[0] = klo[0] = ~0u;
+    ++off;
     --n;
+    if (n == 0) {  // empty: no free slots either (the later registers hold zeros)
+      khi[0] = klo[0] = 0;
+      off = 0;
+    } else if (off == 64) {  // the first register is free: drop it
+#pragma unroll
+      for (int j = 0; j + 1 < R; ++j) {
+        khi[j] = khi[j + 1];
+        klo[j] = klo[j + 1];
+        r[j] = r[j + 1];
+      }
+      khi[R - 1] = klo[R - 1] = r[R - 1] = 0;
+      off = 0;
+    }
+  }
+  // move the run down to slot 0 (slot i takes slot i + off)
+  __device__ void compact() {
+    const int src = lane + off, sl = src & 63;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t ah = __shfl(khi[j], sl), al = __shfl(klo[j], sl), ar = __shfl(r[j], sl);
+      uint32_t bh = 0, bl = 0, br = 0;
+      if (j + 1 < R) {
+        bh = __shfl(khi[j + 1], sl);
+        bl = __shfl(klo[j + 1], sl);
+        br = __shfl(r[j + 1], sl);
+      }
+      khi[j] = src >= 64 ? bh : ah;
+      klo[j] = src >= 64 ? bl : al;
+      r[j] = src >= 64 ? br : ar;
+    }
+    off = 0;
   }
   __device__ bool push(uint64_t kk, uint32_t rr) {
     if (n >= cap) return false;
-    int p = 0;  // entries above the new one
+    int p = kCap;  // slots above the new entry (free slots count as above)
 #pragma unroll
-    for (int j = 0; j < R; ++j)  // empty registers hold keys 0, below every edge key
-      if (R <= 4 || 64 * j < n) p += __popcll(__ballot(join(khi[j], klo[j]) > kk));
+    for (int j = 0; j < R; ++j) {
+      const int c = __popcll(__ballot(join(khi[j], klo[j]) > kk));
+      if (c < 64) {  // registers are sorted: the first one not entirely above
+        p = 64 * j + c;
+        break;
+      }
+    }
+    if (off > 0 && p <= 64) {  // entries above move down into the free slot before them
+      const uint32_t dh = wave_down(khi[0], 0u), dl = wave_down(klo[0], 0u),
+                     dr = wave_down(r[0], 0u);
+      if (lane >= off - 1 && lane < p - 1) {
+        khi[0] = dh;
+        klo[0] = dl;
+        r[0] = dr;
+      } else if (lane == p - 1) {
+        khi[0] = uint32_t(kk >> 32);
+        klo[0] = uint32_t(kk);
+        r[0] = rr;
+      }
+      --off;
+      ++n;
+      return true;
+    }
+    if (off + n >= kCap) {  // no slot after the run: move it to slot 0 first
+      p -= off;
+      compact();
+    }
+    const int last = off + n;  // the slot of the last entry after the push
 #pragma unroll
-    for (int j = R - 1; j >= 0; --j) {  // entry i > p takes entry i - 1
-      if (64 * j > n) continue;  // registers past the new last entry stay zero
+    for (int j = R - 1; j >= 0; --j) {  // slot i > p takes slot i - 1
+      if (64 * j > last || 64 * j + 63 < p) continue;  // past the run, or entirely above p
       const uint32_t ch = j > 0 ? lane_value(khi[j - 1], 63) : 0u;
       const uint32_t cl = j > 0 ? lane_value(klo[j - 1], 63) : 0u;
       const uint32_t cr = j > 0 ? lane_value(r[j - 1], 63) : 0u;
@@ -1951,8 +2021,10 @@ k_d1_boundary_lanes(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int6
   H.cap = kLaneHeap;
   for (int64_t w = int64_t(blockIdx.x) * kLaneThreads + threadIdx.x; w < ntodo;
        w += int64_t(gridDim.x) * kLaneThreads)
-    boundary_column<false>(A, todo ? todo[w] : uint32_t(w), H, s_rows + threadIdx.x, kLaneThreads,
-                           kLaneRows);
+    // every column, the last first: the columns of the highest triangles
+    // have the longest expansions, and the blocks are dispatched in order
+    boundary_column<false>(A, todo ? todo[w] : uint32_t(ntodo - 1 - w), H, s_rows + threadIdx.x,
+                           kLaneThreads, kLaneRows);
 }
 
 constexpr int kWaveRegs = 4, kWaveRegs2 = 16;  // entries a lane in the two wave passes
@@ -3560,6 +3632,16 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       list = out;
       const int done_kind = kind;
       kind = std::min(kind + 1, 3);
+      if (kind <= 2 && ntodo > 1) {
+        // the wave passes take their columns in order from a shared counter:
+        // the highest columns, whose expansions are the longest, go first so
+        // that they do not start after the bulk and set the pass's length
+        uint32_t* keys = ws.get<uint32_t>("d1.retry_keys", ncols + 1);
+        k_desc_keys<<<blocks_for(ntodo), 256, 0, s>>>(list, ntodo, uint32_t(ncols - 1), keys);
+        int bits = 1;
+        while (bits < 32 && (uint64_t(1) << bits) < uint64_t(ncols)) ++bits;
+        radix_sort_u32(ws, keys, out, size_t(ntodo), 0, bits, s);
+      }
       if (read_scalar(bfull, s)) {
         // grow the pool keeping its contents
         // (failed reservations past the old capacity were never written)
