@@ -183,12 +183,43 @@ uint64_t pkey(int dim, int vb, int vd) {
 void canonical_classes(const std::vector<Pt>& P, const std::vector<int>& red,
                        const std::vector<Tgt>& T, std::vector<int>* phi);
 
+// std::sort of a large vector of distinct keys on several host threads:
+// sorted chunks, merged pairwise (the keys are distinct, so the result is the
+// serial sort's).
+template <class T>
+void sort_parallel(std::vector<T>& v) {
+  const size_t n = v.size();
+  const int nt = int(std::min<size_t>(8, std::max<size_t>(1, n >> 16)));
+  if (nt < 2) {
+    std::sort(v.begin(), v.end());
+    return;
+  }
+  std::vector<size_t> cut(size_t(nt) + 1);
+  for (int t = 0; t <= nt; ++t) cut[t] = n * size_t(t) / size_t(nt);
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1]); });
+    for (std::thread& x : th) x.join();
+  }
+  for (size_t w = 1; w < size_t(nt); w *= 2) {  // merge runs of w chunks pairwise
+    std::vector<std::thread> th;
+    for (size_t a = 0; a + w < size_t(nt); a += 2 * w) {
+      const size_t lo = cut[a], mid = cut[a + w], hi = cut[std::min(a + 2 * w, size_t(nt))];
+      th.emplace_back([&v, lo, mid, hi] {
+        std::inplace_merge(v.begin() + lo, v.begin() + mid, v.begin() + hi);
+      });
+    }
+    for (std::thread& x : th) x.join();
+  }
+}
+
 // Only points in a class of two or more, or matched into a target class of
 // two or more, can change; the others are left out of the class bookkeeping.
 void canonical_form(const std::vector<Pt>& P, const std::vector<int>& red, const std::vector<Tgt>& T,
                     std::vector<int>* phi) {
   auto multi = [](std::vector<std::pair<uint64_t, int>>& v) {  // members of classes of >= 2
-    std::sort(v.begin(), v.end());
+    sort_parallel(v);  // (key, point) pairs are distinct
     std::vector<int> idx;
     for (size_t a = 0; a < v.size();) {
       size_t b = a + 1;
