@@ -1892,6 +1892,91 @@ __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint
   typename std::conditional<kWave, RanksWave<Site>, RanksDirect<Site>>::type N(
       A.rank, A.code, S, A.G.total() - 1);
   const bool lead = Q::leader();
+  if constexpr (kWave) {
+    // One vertex group at a time: the group's entries leave the queue
+    // together, as a 14-bit set of star indices (mod 2: equal copies
+    // cancel); the group is expanded inside that set, the highest-ranked
+    // neighbour first (the order the queue would give them): an edge paired
+    // with a star triangle (h, o, n2) flips n2 in the set and sends the edge
+    // between o and n2, which belongs to a lower vertex, to the queue.
+    const int ln = threadIdx.x & 63;
+    while (ok && H.size() > 0) {
+      maxlen = max(maxlen, H.size());
+      const uint32_t rh = uint32_t(H.top_key() >> 32);
+      const int h = int(H.top_ref() >> 4);
+      uint32_t M = 0;
+      while (H.size() > 0 && uint32_t(H.top_key() >> 32) == rh) {
+        if (++steps > A.max_steps) {
+          ok = false;
+          break;
+        }
+        uint64_t kk;
+        uint32_t rr;
+        H.pop(&kk, &rr);
+        M ^= 1u << (rr & 15u);
+      }
+      if (!ok) break;
+      ++groups;
+      code_h = N.start(h);
+      if (H.size() > 0) N.hint(int(H.top_ref() >> 4));
+      const uint32_t myrank = N.cur;  // lane j: rank of neighbour j
+      while (M) {
+        if (++steps > A.max_steps) {
+          ok = false;
+          break;
+        }
+        // the neighbour of highest rank in M (ranks are distinct)
+        uint32_t v = (ln < 14 && ((M >> ln) & 1u)) ? myrank + 1u : 0u;
+        v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xF, 0xF, false)));
+        v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xF, 0xF, false)));
+        v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xF, 0xF, false)));
+        v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xF, 0xF, false)));
+        const uint32_t top = lane_value(v, 15);
+        const uint64_t at =
+            __ballot(ln < 14 && ((M >> ln) & 1u) && myrank + 1u == top);
+        if (at == 0) {  // cannot happen: M holds star indices below 14
+          if (lead) atomicOr(A.err, 128);
+          ok = false;
+          break;
+        }
+        const int k = __ffsll((unsigned long long)at) - 1;
+        M &= ~(1u << k);
+        const uint32_t ec = edge_code(code_h, k);
+        if (ec == 7u) continue;  // paired with its vertex: the path ends
+        if (ec == 6u) {          // critical edge
+          const int lo = h + S.nb(k);
+          const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
+          const int32_t f = A.edge_pos_of[eid];
+          if (f < 0 && int64_t(-1 - f) < A.nedges) continue;  // dies in dimension 0
+          if (f < 0 || int64_t(f) >= A.nedges || A.edge_ids[f] != eid) {
+            if (lead) atomicOr(A.err, 16);
+            continue;
+          }
+          ++toggles;
+          if (!toggle_row(Rows, rstride, &rl, rcap, uint32_t(f), &moved)) {
+            ok = false;
+            break;
+          }
+          continue;
+        }
+        const uint32_t stp = c_st.edge_step[k][ec];
+        if (!(stp >> 31)) {
+          if (lead) atomicOr(A.err, 128);
+          ok = false;
+          break;
+        }
+        const int k2 = int(stp & 15u);
+        ++expands;
+        M ^= 1u << k2;  // the edge (h, n2)
+        const uint32_t ro = lane_value(myrank, k), rn = lane_value(myrank, k2);
+        if (ro > rn) {
+          ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(h + S.nb(k)) << 4) | ((stp >> 4) & 15u));
+        } else {
+          ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(h + S.nb(k2)) << 4) | ((stp >> 8) & 15u));
+        }
+      }
+    }
+  } else
   while (ok && H.size() > 0) {
     if (++steps > A.max_steps) {
       ok = false;
