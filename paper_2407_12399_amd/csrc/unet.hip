@@ -2,7 +2,10 @@
 // 3x3x3 convolutions) that maps (normalised field, signal-vertex mask) to a
 // proposed change g0 - f, with its forward and backward passes and an Adam
 // step.  Convolutions are implicit GEMMs on BF16 MFMA tiles with FP32
-// accumulation; activations are BF16, parameters and gradients FP32.
+// accumulation; activations are BF16, parameters and gradients FP32.  Where
+// the channel count allows it, the forward convolutions use gfx950's
+// double-K BF16 MFMAs (32x32x16, 16x16x32): each lane supplies eight
+// consecutive channels, half the instructions of the 8- and 16-deep forms.
 //
 // Layout: a volume of D x H x W voxels is stored channels-last, voxel
 // v = x + W * (y + H * z), element (v, c) at v * C + c.  A convolution's
@@ -22,7 +25,13 @@ namespace ts {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// eight BF16 values (16 bytes, aligned) as an MFMA operand
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
 
 inline unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
@@ -43,8 +52,12 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 // 8 * (i / 4) + 4 * (l / 32) + i % 4, column l % 32.  Cin is a multiple of 8.
 // Outputs: Yf (FP32, before the activation) and Yb (BF16, after the optional
 // ReLU); either may be null.  The backward data pass uses the same kernel with
-// flipped, transposed weights.
+// flipped, transposed weights.  kWide (Cin a multiple of 16): the 32x32x16
+// MFMA, lane l supplying channels 8 * (l / 32) .. + 7 of a 16-channel step
+// (A and B take the same channels in every lane, so the sum over k is the
+// convolution's sum over channels whatever order the hardware gives k).
 // ---------------------------------------------------------------------------
+template <bool kWide>
 __global__ void __launch_bounds__(256)
 k_conv_fwd(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
            const uint16_t* __restrict__ Wt, const float* __restrict__ bias, int Cout, int relu,
@@ -71,13 +84,23 @@ k_conv_fwd(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
     const bool inside = v < V && x + dx >= 0 && x + dx < W && y + dy >= 0 && y + dy < H &&
                         z + dz >= 0 && z + dz < D;
     const int64_t nb = v + dx + int64_t(W) * (dy + int64_t(H) * dz);
-    const uint16_t* xa = X + nb * Cin + 4 * half;
-    const uint16_t* wb = Wt + (int64_t(t) * Cout + co) * Cin + 4 * half;
-    for (int c0 = 0; c0 < Cin; c0 += 8) {
-      bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
-      if (inside) a = *reinterpret_cast<const bf16x4*>(xa + c0);
-      if (co < Cout) b = *reinterpret_cast<const bf16x4*>(wb + c0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    const int sub = kWide ? 8 * half : 4 * half;
+    const uint16_t* xa = X + nb * Cin + sub;
+    const uint16_t* wb = Wt + (int64_t(t) * Cout + co) * Cin + sub;
+    if constexpr (kWide) {
+      for (int c0 = 0; c0 < Cin; c0 += 16) {
+        bf16x8 a = {}, b = {};
+        if (inside) a = load8(xa + c0);
+        if (co < Cout) b = load8(wb + c0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
+      for (int c0 = 0; c0 < Cin; c0 += 8) {
+        bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+        if (inside) a = *reinterpret_cast<const bf16x4*>(xa + c0);
+        if (co < Cout) b = *reinterpret_cast<const bf16x4*>(wb + c0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+      }
     }
   }
   const int cc = tc * 32 + m;
@@ -99,8 +122,11 @@ k_conv_fwd(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
 // voxels x 16 output channels with four 16x16x16 BF16 MFMAs per k step, which
 // share the step's weights.  Lane l supplies row l % 16 of A (voxel) and column
 // l % 16 of B (output channel) at k = 4 * (l / 16) .. + 3; accumulator i of
-// lane l is row 4 * (l / 16) + i, column l % 16.
+// lane l is row 4 * (l / 16) + i, column l % 16.  kWide (Cin a multiple of
+// 32): the 16x16x32 MFMA, lane l supplying channels 8 * (l / 16) .. + 7 of a
+// 32-channel step.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <bool kWide>
 __global__ void __launch_bounds__(256)
 k_conv_fwd16(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
              const uint16_t* __restrict__ Wt, const float* __restrict__ bias, int relu,
@@ -130,16 +156,28 @@ k_conv_fwd16(const uint16_t* __restrict__ X, int D, int H, int W, int Cin,
     for (int s = 0; s < 4; ++s) {
       inside[s] = v[s] < V && x[s] + dx >= 0 && x[s] + dx < W && y[s] + dy >= 0 &&
                   y[s] + dy < H && z[s] + dz >= 0 && z[s] + dz < D;
-      xa[s] = X + (v[s] + dx + int64_t(W) * (dy + int64_t(H) * dz)) * Cin + 4 * q;
+      xa[s] = X + (v[s] + dx + int64_t(W) * (dy + int64_t(H) * dz)) * Cin + (kWide ? 8 : 4) * q;
     }
-    const uint16_t* wb = Wt + (int64_t(t) * 16 + m) * Cin + 4 * q;
-    for (int c0 = 0; c0 < Cin; c0 += 16) {
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(wb + c0);
+    const uint16_t* wb = Wt + (int64_t(t) * 16 + m) * Cin + (kWide ? 8 : 4) * q;
+    if constexpr (kWide) {
+      for (int c0 = 0; c0 < Cin; c0 += 32) {
+        const bf16x8 b = load8(wb + c0);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        bf16x4 a = {0, 0, 0, 0};
-        if (inside[s]) a = *reinterpret_cast<const bf16x4*>(xa[s] + c0);
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+        for (int s = 0; s < 4; ++s) {
+          bf16x8 a = {};
+          if (inside[s]) a = load8(xa[s] + c0);
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+        }
+      }
+    } else {
+      for (int c0 = 0; c0 < Cin; c0 += 16) {
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(wb + c0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          bf16x4 a = {0, 0, 0, 0};
+          if (inside[s]) a = *reinterpret_cast<const bf16x4*>(xa[s] + c0);
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+        }
       }
     }
   }
@@ -198,6 +236,38 @@ k_conv_wgrad(const uint16_t* __restrict__ dY, const uint16_t* __restrict__ X, in
         }
       }
       acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+  } else if ((W & 7) == 0) {
+    // The 32x32x16 MFMA: the lane's eight voxels vb .. vb + 7 (vb = k0 + 8 *
+    // half, a multiple of 8) share a row because W is a multiple of 8; their
+    // coordinates advance by 16 voxels per step without divisions.
+    const int64_t s0 = v0 + 8 * half;
+    int xb = int(s0 % W), yb = int((s0 / W) % H), zb = int(s0 / (int64_t(W) * H));
+    const int64_t shift = dx + int64_t(W) * (dy + int64_t(H) * dz);
+    for (int64_t k0 = v0; k0 < v1; k0 += 16) {
+      uint16_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0}, b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      const int64_t vb = k0 + 8 * half;
+      if (vb < v1) {
+        const bool row_ok = yb + dy >= 0 && yb + dy < H && zb + dz >= 0 && zb + dz < D;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int64_t v = vb + i;
+          if (v >= v1) continue;
+          if (co < Cout) a[i] = dY[v * Cout + co];
+          if (row_ok && ci < Cin && xb + i + dx >= 0 && xb + i + dx < W)
+            b[i] = X[(v + shift) * Cin + ci];
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+      xb += 16;
+      while (xb >= W) {
+        xb -= W;
+        if (++yb == H) {
+          yb = 0;
+          ++zb;
+        }
+      }
     }
   } else {
     // The lane's four voxels vb .. vb + 3 (vb = k0 + 4 * half, a multiple of 4)
@@ -485,13 +555,21 @@ void conv_fwd(ts_ctx* ctx, const uint16_t* X, const Vol& vol, int cin, const uin
               const float* bias, int cout, bool relu, float* Yf, uint16_t* Yb) {
   if (cout == 16 && cin % 16 == 0) {
     const int64_t waves = (vol.V() + 63) / 64;
-    k_conv_fwd16<<<nblk(waves * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt, bias,
-                                                             relu ? 1 : 0, Yf, Yb);
+    if (cin % 32 == 0)
+      k_conv_fwd16<true><<<nblk(waves * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt,
+                                                                     bias, relu ? 1 : 0, Yf, Yb);
+    else
+      k_conv_fwd16<false><<<nblk(waves * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt,
+                                                                      bias, relu ? 1 : 0, Yf, Yb);
     return;
   }
   const int64_t tiles = ((vol.V() + 31) / 32) * ((cout + 31) / 32);
-  k_conv_fwd<<<nblk(tiles * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt, bias, cout,
-                                                         relu ? 1 : 0, Yf, Yb);
+  if (cin % 16 == 0)
+    k_conv_fwd<true><<<nblk(tiles * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt, bias,
+                                                                 cout, relu ? 1 : 0, Yf, Yb);
+  else
+    k_conv_fwd<false><<<nblk(tiles * 64), 256, 0, ctx->stream>>>(X, vol.D, vol.H, vol.W, cin, Wt,
+                                                                  bias, cout, relu ? 1 : 0, Yf, Yb);
 }
 
 void forward(ts_ctx* ctx, const Net& N, const float* params, const float* input, const Vol& v0,
