@@ -1854,9 +1854,10 @@ struct RanksWave {
   }
 };
 
-template <bool kWave, class Q, class Geo>
+template <bool kWave, class Q, class Geo, bool kLaneGroup = false>
 __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint32_t c, Q& H,
-                                                uint32_t* Rows, int64_t rstride, int rcap) {
+                                                uint32_t* Rows, int64_t rstride, int rcap,
+                                                uint32_t* Rk = nullptr) {
   const uint32_t ti = A.cols[c];
   const int id = A.tri_ids[ti];
   const int y = A.order[A.tri_keys[ti] >> 12];
@@ -1969,6 +1970,82 @@ __device__ __forceinline__ void boundary_column(const BoundaryArgs<Geo>& A, uint
         ++expands;
         M ^= 1u << k2;  // the edge (h, n2)
         const uint32_t ro = lane_value(myrank, k), rn = lane_value(myrank, k2);
+        if (ro > rn) {
+          ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(h + S.nb(k)) << 4) | ((stp >> 4) & 15u));
+        } else {
+          ok = H.push((uint64_t(rn) << 32) | ro, (uint32_t(h + S.nb(k2)) << 4) | ((stp >> 8) & 15u));
+        }
+      }
+    }
+  } else if constexpr (kLaneGroup) {
+    // The same group expansion by one lane: the ranks of the set's members
+    // (star index k -> rank) are kept in Rk[k * rstride] (LDS), and the
+    // highest is found by a scan over the set, which holds a few members.
+    while (ok && H.size() > 0) {
+      maxlen = max(maxlen, H.size());
+      const uint32_t rh = uint32_t(H.top_key() >> 32);
+      const int h = int(H.top_ref() >> 4);
+      uint32_t M = 0;
+      while (H.size() > 0 && uint32_t(H.top_key() >> 32) == rh) {
+        if (++steps > A.max_steps) {
+          ok = false;
+          break;
+        }
+        uint64_t kk;
+        uint32_t rr;
+        H.pop(&kk, &rr);
+        const int kb = int(rr & 15u);
+        M ^= 1u << kb;
+        Rk[int64_t(kb) * rstride] = uint32_t(kk);
+      }
+      if (!ok) break;
+      ++groups;
+      code_h = N.start(h);
+      while (M) {
+        if (++steps > A.max_steps) {
+          ok = false;
+          break;
+        }
+        int k = -1;
+        uint32_t ro = 0;
+        for (uint32_t m = M; m; m &= m - 1) {
+          const int b = __ffs(m) - 1;
+          const uint32_t rb = Rk[int64_t(b) * rstride];
+          if (k < 0 || rb > ro) {
+            k = b;
+            ro = rb;
+          }
+        }
+        M &= ~(1u << k);
+        const uint32_t ec = edge_code(code_h, k);
+        if (ec == 7u) continue;  // paired with its vertex: the path ends
+        if (ec == 6u) {          // critical edge
+          const int lo = h + S.nb(k);
+          const int eid = k < 7 ? 7 * h + k : 7 * lo + (k - 7);
+          const int32_t f = A.edge_pos_of[eid];
+          if (f < 0 && int64_t(-1 - f) < A.nedges) continue;  // dies in dimension 0
+          if (f < 0 || int64_t(f) >= A.nedges || A.edge_ids[f] != eid) {
+            atomicOr(A.err, 16);
+            continue;
+          }
+          ++toggles;
+          if (!toggle_row(Rows, rstride, &rl, rcap, uint32_t(f), &moved)) {
+            ok = false;
+            break;
+          }
+          continue;
+        }
+        const uint32_t stp = c_st.edge_step[k][ec];
+        if (!(stp >> 31)) {
+          atomicOr(A.err, 128);
+          ok = false;
+          break;
+        }
+        const int k2 = int(stp & 15u);
+        ++expands;
+        const uint32_t rn = N.get(k2);
+        M ^= 1u << k2;  // the edge (h, n2)
+        Rk[int64_t(k2) * rstride] = rn;
         if (ro > rn) {
           ok = H.push((uint64_t(ro) << 32) | rn, (uint32_t(h + S.nb(k)) << 4) | ((stp >> 4) & 15u));
         } else {
@@ -2099,6 +2176,7 @@ k_d1_boundary_lanes(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int6
   __shared__ uint64_t s_key[kLaneHeap * kLaneThreads];
   __shared__ uint32_t s_ref[kLaneHeap * kLaneThreads];
   __shared__ uint32_t s_rows[kLaneRows * kLaneThreads];
+  __shared__ uint32_t s_rk[14 * kLaneThreads];  // ranks of a vertex group's members
   LaneHeap H;
   H.key = s_key + threadIdx.x;
   H.ref = s_ref + threadIdx.x;
@@ -2108,8 +2186,9 @@ k_d1_boundary_lanes(BoundaryArgs<Geo> A, const uint32_t* __restrict__ todo, int6
        w += int64_t(gridDim.x) * kLaneThreads)
     // every column, the last first: the columns of the highest triangles
     // have the longest expansions, and the blocks are dispatched in order
-    boundary_column<false>(A, todo ? todo[w] : uint32_t(ntodo - 1 - w), H, s_rows + threadIdx.x,
-                           kLaneThreads, kLaneRows);
+    boundary_column<false, LaneHeap, Geo, true>(A, todo ? todo[w] : uint32_t(ntodo - 1 - w), H,
+                                                s_rows + threadIdx.x, kLaneThreads, kLaneRows,
+                                                s_rk + threadIdx.x);
 }
 
 constexpr int kWaveRegs = 4, kWaveRegs2 = 16;  // entries a lane in the two wave passes
