@@ -2285,19 +2285,33 @@ __global__ void k_d1_round_next(unsigned int* __restrict__ cnt, unsigned int* __
 
 // pdesc[p] = the column of p's owner (after the claims of a round, the owner
 // of every claimed pivot keeps its column for the rest of the round), so that
-// a reduction step loads the owner and its column at once.
+// a reduction step loads the owner and its column at once.  An owner column of
+// at most kInlineRows + 1 rows also has its rows after the pivot in
+// prow[2p .. 2p + 1] (zeros after the last), so that the wave reduction reads
+// them with the descriptor instead of after it.
+constexpr uint32_t kInlineRows = 8;
 __global__ void k_d1_publish(const uint64_t* __restrict__ col_desc, const uint32_t* __restrict__ pool,
                              const unsigned int* __restrict__ owner, const uint32_t* __restrict__ list,
                              const unsigned int* __restrict__ cnt, int64_t nall,
-                             uint64_t* __restrict__ pdesc) {
+                             uint64_t* __restrict__ pdesc, uint4* __restrict__ prow) {
   const int64_t n = list ? int64_t(cnt[2]) : nall;
   for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
        j += int64_t(gridDim.x) * blockDim.x) {
     const uint32_t c = list ? list[j] : uint32_t(j);
     const uint64_t d = col_desc[c];
-    if ((d & 0xFFFFFFu) == 0) continue;
-    const uint32_t piv = pool[d >> 24];
-    if (owner[piv] == c) pdesc[piv] = d;
+    const uint32_t len = uint32_t(d & 0xFFFFFFu);
+    if (len == 0) continue;
+    const uint64_t off = d >> 24;
+    const uint32_t piv = pool[off];
+    if (owner[piv] != c) continue;
+    pdesc[piv] = d;
+    if (len <= kInlineRows + 1) {
+      uint32_t r[kInlineRows];
+#pragma unroll
+      for (uint32_t i = 0; i < kInlineRows; ++i) r[i] = 1 + i < len ? pool[off + 1 + i] : 0u;
+      prow[2 * int64_t(piv)] = make_uint4(r[0], r[1], r[2], r[3]);
+      prow[2 * int64_t(piv) + 1] = make_uint4(r[4], r[5], r[6], r[7]);
+    }
   }
 }
 
@@ -2388,7 +2402,7 @@ __device__ uint32_t wave_xor(const uint32_t* A, uint32_t a, const uint32_t* B, u
 // workgroup kernel).
 __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
                               const ColPool& pc, const unsigned int* __restrict__ owner,
-                              const uint64_t* __restrict__ pdesc,
+                              const uint64_t* __restrict__ pdesc, const uint4* __restrict__ prow,
                               int* __restrict__ err, uint32_t fin, uint32_t* bufA, uint32_t* bufB,
                               uint32_t* bufO, unsigned long long* __restrict__ stats) {
   const unsigned lane = lane_id();
@@ -2409,6 +2423,7 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
   // row left after cancelling, is known from the two columns' heads)
   unsigned int o = owner[cur[0]];
   uint64_t od = pdesc[cur[0]];
+  uint4 or0 = prow[2 * int64_t(cur[0])], or1 = prow[2 * int64_t(cur[0]) + 1];
   for (int steps = 0;; ++steps) {
     if (steps > (1 << 20)) {  // pivots strictly decrease: cannot happen
       if (lane == 0) atomicOr(err, 512);
@@ -2425,7 +2440,16 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
       break;  // write back what we have; the next round hands it on
     }
     const uint64_t ooff = od >> 24;
-    for (uint32_t i = lane; i < olen; i += 64) bufB[i] = pool[ooff + i];
+    if (olen <= kInlineRows + 1) {  // the rows came with the descriptor
+      const uint32_t e[kInlineRows] = {or0.x, or0.y, or0.z, or0.w, or1.x, or1.y, or1.z, or1.w};
+      uint32_t v = cur[0];  // the owner's pivot is the current pivot
+#pragma unroll
+      for (uint32_t t = 0; t < kInlineRows; ++t)
+        if (lane == t + 1) v = e[t];
+      if (lane < olen) bufB[lane] = v;
+    } else {
+      for (uint32_t i = lane; i < olen; i += 64) bufB[i] = pool[ooff + i];
+    }
     wave_sync();
     const unsigned int o_step = o;  // the owner added in this step
     uint32_t hi = 1, hj = 1;  // both heads are the pivot
@@ -2437,6 +2461,8 @@ __device__ int d1_reduce_wave(uint32_t c, uint64_t* __restrict__ col_desc, uint3
       const uint32_t np = hi < len && (hj >= olen || cur[hi] > bufB[hj]) ? cur[hi] : bufB[hj];
       o = owner[np];
       od = pdesc[np];
+      or0 = prow[2 * int64_t(np)];
+      or1 = prow[2 * int64_t(np) + 1];
     }
     const uint32_t w = wave_xor(cur, len, bufB, olen, nxt);
     changed = true;
@@ -2967,7 +2993,7 @@ k_d1_reduce_lanes(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, 
 __global__ void __launch_bounds__(64 * kRedWaves)
 k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
                  const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
-                 unsigned int* __restrict__ mark,
+                 const uint4* __restrict__ prow, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
                  int* __restrict__ pool_full, uint32_t* __restrict__ long_list,
@@ -2982,7 +3008,7 @@ k_d1_reduce_wave(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   const unsigned nw = gridDim.x * kRedWaves;
   for (unsigned int j = gw; j < n1; j += nw) {
     const uint32_t c = list[j];
-    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, pdesc, err, fin, s_buf[wave][0], s_buf[wave][1],
+    int r = d1_reduce_wave(c, col_desc, pool, pc, owner, pdesc, prow, err, fin, s_buf[wave][0], s_buf[wave][1],
                            s_buf[wave][2], stats);
     if (r < 0) {  // too long for the wave: handled by a whole workgroup this round
       if (lane == 0) long_list[atomicAdd(&cnt[3], 1u)] = c;
@@ -3843,6 +3869,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
     ctx->timer.start("K7 d1 reduction");
     unsigned int* owner = ws.get<unsigned int>("d1.owner", ne + 1);
     uint64_t* pdesc = ws.get<uint64_t>("d1.pdesc", ne + 1);
+    uint4* prow = ws.get<uint4>("d1.prow", 2 * (ne + 1));
     unsigned int* mark = ws.get<unsigned int>("d1.mark", ncols + 1);
     uint32_t* listA = ws.get<uint32_t>("d1.listA", ncols + 1);
     uint32_t* listB = ws.get<uint32_t>("d1.listB", ncols + 1);
@@ -3871,7 +3898,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
       k_set_u64<<<1, 1, 0, s>>>(pool.top, uint64_t(live));
       // owners' columns moved: publish them again
       k_d1_publish<<<blocks_for(ncols), 256, 0, s>>>(col_desc, pool.data, owner, nullptr, nullptr,
-                                                     ncols, pdesc);
+                                                     ncols, pdesc, prow);
       TS_HIP(hipGetLastError());
       pool_hint = std::max(pool_hint, pool_cap);
     };
@@ -3921,12 +3948,12 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
         for (int it = 0; it < kCheckEvery; ++it) {
           ++rounds;
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
-          k_d1_publish<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, A, cnt, 0, pdesc);
+          k_d1_publish<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, A, cnt, 0, pdesc, prow);
           k_d1_reduce_lanes<<<lgrid, kRedLanes, 0, s>>>(col_desc, pool.data, pool, owner, pdesc, mark,
                                                           round_d, A, B, cnt, err, pool_full,
                                                           wave_list, rstats);
           k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
-                                                            mark,
+                                                            prow, mark,
                                                             round_d, wave_list, B, cnt, err, pool_full,
                                                             long_list, rstats);
           k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
