@@ -2651,7 +2651,7 @@ constexpr uint32_t kLongCap = 12288;
 __global__ void __launch_bounds__(kLongThreads)
 k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
                  const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
-                 unsigned int* __restrict__ mark,
+                 const uint4* __restrict__ prow, unsigned int* __restrict__ mark,
                  unsigned int* __restrict__ round_ptr, const uint32_t* __restrict__ long_list,
                  uint32_t* __restrict__ next, unsigned int* __restrict__ cnt, int* __restrict__ err,
                  int* __restrict__ pool_full, unsigned long long* __restrict__ stats) {
@@ -2669,6 +2669,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   __shared__ int s_pf;
   __shared__ unsigned int s_po;
   __shared__ uint64_t s_pod;
+  // the inline rows of the current owner, and those loaded with the next one
+  __shared__ uint4 s_rec[2], s_prf[2];
   const unsigned int nlong = cnt[3];
   const unsigned int round = *round_ptr;
   const uint32_t fin = cnt[4];  // owners below it are final
@@ -2703,10 +2705,14 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           if (s_pf) {
             o = s_po;
             od = s_pod;
+            s_rec[0] = s_prf[0];
+            s_rec[1] = s_prf[1];
           } else {
             const uint32_t piv = s_lds ? s_col[cur][0] : pool[s_off];
             o = owner[piv];
             od = pdesc[piv];
+            s_rec[0] = prow[2 * int64_t(piv)];
+            s_rec[1] = prow[2 * int64_t(piv) + 1];
           }
           s_pf = 0;
           if (o == c) {
@@ -2749,7 +2755,14 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         __syncthreads();
       }
       if (s_lds) {
-        for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
+        if (s_olen <= kInlineRows + 1) {  // the rows came with the descriptor
+          if (threadIdx.x < s_olen)
+            s_own[threadIdx.x] = threadIdx.x == 0
+                                     ? s_col[cur][0]  // the owner's pivot is the current pivot
+                                     : reinterpret_cast<const uint32_t*>(s_rec)[threadIdx.x - 1];
+        } else {
+          for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
+        }
         __syncthreads();
         if (stats) {
           const uint64_t t = wall_clock64();
@@ -2758,6 +2771,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         }
         unsigned int po = 0;
         uint64_t pod = 0;
+        uint4 pr0 = make_uint4(0, 0, 0, 0), pr1 = make_uint4(0, 0, 0, 0);
         bool pf = false;
         if (threadIdx.x == 0) {
           const uint32_t* X = s_col[cur];
@@ -2770,6 +2784,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
             const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > s_own[hj]) ? X[hi] : s_own[hj];
             po = owner[np];
             pod = pdesc[np];
+            pr0 = prow[2 * int64_t(np)];
+            pr1 = prow[2 * int64_t(np) + 1];
             pf = true;
           }
         }
@@ -2788,6 +2804,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           if (pf) {
             s_po = po;
             s_pod = pod;
+            s_prf[0] = pr0;
+            s_prf[1] = pr1;
             s_pf = 1;
           }
         }
@@ -3957,7 +3975,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
                                                             round_d, wave_list, B, cnt, err, pool_full,
                                                             long_list, rstats);
           k_d1_reduce_long<<<64, kLongThreads, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
-                                                       mark,
+                                                       prow, mark,
                                                        round_d, long_list, B, cnt, err, pool_full,
                                                        rstats);
           k_d1_round_next<<<1, 1, 0, s>>>(cnt, round_d);
