@@ -2889,7 +2889,8 @@ __device__ __forceinline__ void load_col(const uint32_t* __restrict__ src, uint3
 // returns as d1_reduce_wave: 0 owner, 1 again next round, 2 pool full, -1 deferred
 __device__ int d1_reduce_lane(uint32_t c, uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool,
                               const ColPool& pc, const unsigned int* __restrict__ owner,
-                              const uint64_t* __restrict__ pdesc, int* __restrict__ err, uint32_t fin,
+                              const uint64_t* __restrict__ pdesc, const uint4* __restrict__ prow,
+                              int* __restrict__ err, uint32_t fin,
                               uint32_t* cur, uint32_t* nxt, uint32_t* own, int* adds) {
   const uint64_t d = col_desc[c];
   uint32_t len = uint32_t(d & 0xFFFFFFu);
@@ -2903,6 +2904,7 @@ __device__ int d1_reduce_lane(uint32_t c, uint64_t* __restrict__ col_desc, uint3
     const uint32_t piv = cur[0];
     const unsigned int o = owner[piv];
     const uint64_t od = pdesc[piv];
+    const uint4 r0 = prow[2 * int64_t(piv)], r1 = prow[2 * int64_t(piv) + 1];  // with od
     if (o == c) {
       result = 0;
       break;
@@ -2913,7 +2915,14 @@ __device__ int d1_reduce_lane(uint32_t c, uint64_t* __restrict__ col_desc, uint3
       if (!changed) return -1;
       break;  // write back what we have; the next round hands it on
     }
-    load_col(pool + (od >> 24), olen, own);
+    if (olen <= kInlineRows + 1) {  // the rows came with the descriptor
+      const uint32_t e[kInlineRows + 1] = {piv, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+      for (uint32_t i = 0; i <= kInlineRows; ++i)
+        if (i < olen) own[i * kRedLanes] = e[i];
+    } else {
+      load_col(pool + (od >> 24), olen, own);
+    }
     // symmetric difference of the two descending lists
     uint32_t i = 0, j = 0, w = 0;
     while (i < len && j < olen) {
@@ -2970,6 +2979,7 @@ __device__ __forceinline__ void wave_append(bool flag, uint32_t v, uint32_t* __r
 __global__ void __launch_bounds__(kRedLanes)
 k_d1_reduce_lanes(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, ColPool pc,
                   const unsigned int* __restrict__ owner, const uint64_t* __restrict__ pdesc,
+                  const uint4* __restrict__ prow,
                   unsigned int* __restrict__ mark, unsigned int* __restrict__ round_ptr,
                   const uint32_t* __restrict__ list, uint32_t* __restrict__ next,
                   unsigned int* __restrict__ cnt, int* __restrict__ err, int* __restrict__ pool_full,
@@ -2989,7 +2999,7 @@ k_d1_reduce_lanes(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, 
     const bool live = j < n1;
     const uint32_t c = live ? list[j] : 0u;
     int adds = 0;
-    const int r = live ? d1_reduce_lane(c, col_desc, pool, pc, owner, pdesc, err, fin, cur, nxt, own,
+    const int r = live ? d1_reduce_lane(c, col_desc, pool, pc, owner, pdesc, prow, err, fin, cur, nxt, own,
                                         &adds)
                        : 0;
     if (r == 2) atomicOr(pool_full, 1);
@@ -3967,7 +3977,7 @@ void compute_persistence(ts_ctx* ctx, const float* f, const Grid& g, Persistence
           ++rounds;
           k_d1_claim<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, mark, round_d, A, cnt);
           k_d1_publish<<<grid, 256, 0, s>>>(col_desc, pool.data, owner, A, cnt, 0, pdesc, prow);
-          k_d1_reduce_lanes<<<lgrid, kRedLanes, 0, s>>>(col_desc, pool.data, pool, owner, pdesc, mark,
+          k_d1_reduce_lanes<<<lgrid, kRedLanes, 0, s>>>(col_desc, pool.data, pool, owner, pdesc, prow, mark,
                                                           round_d, A, B, cnt, err, pool_full,
                                                           wave_list, rstats);
           k_d1_reduce_wave<<<wgrid, 64 * kRedWaves, 0, s>>>(col_desc, pool.data, pool, owner, pdesc,
