@@ -2671,6 +2671,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
   __shared__ uint64_t s_pod;
   // the inline rows of the current owner, and those loaded with the next one
   __shared__ uint4 s_rec[2], s_prf[2];
+  // a short owner's rows: their places in the working column, and hits
+  __shared__ uint32_t s_fpos[kInlineRows], s_fhit[kInlineRows];
   const unsigned int nlong = cnt[3];
   const unsigned int round = *round_ptr;
   const uint32_t fin = cnt[4];  // owners below it are final
@@ -2789,9 +2791,64 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
             pf = true;
           }
         }
-        // merged into s_col[cur ^ 1], compacted back into s_col[cur]
-        const uint32_t w =
-            block_xor_merge(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_col[cur], s_wave);
+        uint32_t w;
+        if (s_olen <= kInlineRows + 1) {
+          // A short owner (most of the additions of the long chains): each of
+          // its rows below the pivot is searched in the working column (a hit
+          // deletes that element, a miss inserts the row before position
+          // pos), then every element moves once to its new place in
+          // s_col[cur ^ 1], which becomes the working column: no merge and no
+          // prefix scan.  Element i > 0 moves by -1 (the pivot) - (hits
+          // before i) + (misses at or before i); the miss of row k lands at
+          // pos - 1 - (hits before pos) + (misses of earlier rows).
+          const uint32_t m = s_olen - 1, n = s_len;
+          const uint32_t* Wc = s_col[cur];
+          if (threadIdx.x < m) {
+            const uint32_t v = s_own[threadIdx.x + 1];
+            const uint32_t pos = count_greater(Wc, n, v);
+            s_fpos[threadIdx.x] = pos;
+            s_fhit[threadIdx.x] = (pos < n && Wc[pos] == v) ? 1u : 0u;
+          }
+          __syncthreads();
+          uint32_t fp[kInlineRows], fh[kInlineRows], nh = 0;
+#pragma unroll
+          for (uint32_t k = 0; k < kInlineRows; ++k) {
+            fp[k] = k < m ? s_fpos[k] : 0xFFFFFFFFu;
+            fh[k] = k < m ? s_fhit[k] : 0u;
+            nh += fh[k];
+          }
+          uint32_t* out = s_col[cur ^ 1];
+          for (uint32_t i = threadIdx.x + 1; i < n; i += kLongThreads) {
+            int shift = -1;
+            bool del = false;
+#pragma unroll
+            for (uint32_t k = 0; k < kInlineRows; ++k) {
+              if (k >= m) continue;
+              if (fh[k]) {
+                if (fp[k] < i) --shift;
+                else if (fp[k] == i) del = true;
+              } else if (fp[k] <= i) {
+                ++shift;
+              }
+            }
+            if (!del) out[int(i) + shift] = Wc[i];
+          }
+          if (threadIdx.x < m && !s_fhit[threadIdx.x]) {
+            const uint32_t pk = s_fpos[threadIdx.x];
+            int at = int(pk) - 1;
+            for (uint32_t k = 0; k < m; ++k) {
+              if (s_fhit[k] && s_fpos[k] < pk) --at;
+              if (!s_fhit[k] && k < threadIdx.x) ++at;
+            }
+            out[at] = s_own[threadIdx.x + 1];
+          }
+          __syncthreads();
+          cur ^= 1;
+          w = n - 1 - nh + (m - nh);
+        } else {
+          // merged into s_col[cur ^ 1], compacted back into s_col[cur]
+          w = block_xor_merge(s_col[cur], s_len, s_own, s_olen, s_col[cur ^ 1], s_col[cur], s_wave);
+        }
         if (stats) {
           const uint64_t t = wall_clock64();
           tph[2] += t - tmark;
