@@ -2757,15 +2757,14 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         __syncthreads();
       }
       if (s_lds) {
-        if (s_olen <= kInlineRows + 1) {  // the rows came with the descriptor
-          if (threadIdx.x < s_olen)
-            s_own[threadIdx.x] = threadIdx.x == 0
-                                     ? s_col[cur][0]  // the owner's pivot is the current pivot
-                                     : reinterpret_cast<const uint32_t*>(s_rec)[threadIdx.x - 1];
-        } else {
+        // a short owner's rows after its pivot (the current pivot) came with
+        // the descriptor and are read from s_rec; a longer one is loaded
+        const bool short_owner = s_olen <= kInlineRows + 1;
+        const uint32_t* rec = reinterpret_cast<const uint32_t*>(s_rec);
+        if (!short_owner) {
           for (uint32_t i = threadIdx.x; i < s_olen; i += kLongThreads) s_own[i] = pool[s_ooff + i];
+          __syncthreads();
         }
-        __syncthreads();
         if (stats) {
           const uint64_t t = wall_clock64();
           tph[1] += t - tmark;
@@ -2777,13 +2776,14 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
         bool pf = false;
         if (threadIdx.x == 0) {
           const uint32_t* X = s_col[cur];
+          auto own = [&](uint32_t j) { return short_owner ? rec[j - 1] : s_own[j]; };  // j >= 1
           uint32_t hi = 1, hj = 1;  // both heads are the pivot
-          while (hi < s_len && hj < s_olen && X[hi] == s_own[hj]) {
+          while (hi < s_len && hj < s_olen && X[hi] == own(hj)) {
             ++hi;
             ++hj;
           }
           if (hi < s_len || hj < s_olen) {
-            const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > s_own[hj]) ? X[hi] : s_own[hj];
+            const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > own(hj)) ? X[hi] : own(hj);
             po = owner[np];
             pod = pdesc[np];
             pr0 = prow[2 * int64_t(np)];
@@ -2792,7 +2792,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           }
         }
         uint32_t w;
-        if (s_olen <= kInlineRows + 1) {
+        if (short_owner) {
           // A short owner (most of the additions of the long chains): each of
           // its rows below the pivot is searched in the working column (a hit
           // deletes that element, a miss inserts the row before position
@@ -2804,7 +2804,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           const uint32_t m = s_olen - 1, n = s_len;
           const uint32_t* Wc = s_col[cur];
           if (threadIdx.x < m) {
-            const uint32_t v = s_own[threadIdx.x + 1];
+            const uint32_t v = rec[threadIdx.x];
             const uint32_t pos = count_greater(Wc, n, v);
             s_fpos[threadIdx.x] = pos;
             s_fhit[threadIdx.x] = (pos < n && Wc[pos] == v) ? 1u : 0u;
@@ -2840,7 +2840,7 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
               if (s_fhit[k] && s_fpos[k] < pk) --at;
               if (!s_fhit[k] && k < threadIdx.x) ++at;
             }
-            out[at] = s_own[threadIdx.x + 1];
+            out[at] = rec[threadIdx.x];
           }
           __syncthreads();
           cur ^= 1;
