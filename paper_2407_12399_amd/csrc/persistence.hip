@@ -2866,7 +2866,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
             s_pf = 1;
           }
         }
-        __syncthreads();
+        // no barrier here: only thread 0 wrote, and only thread 0 reads
+        // before the barrier after the next decision
         if (stats) {
           const uint64_t t = wall_clock64();
           tph[3] += t - tmark;
