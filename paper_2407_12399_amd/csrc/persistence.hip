@@ -2803,11 +2803,27 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           // pos - 1 - (hits before pos) + (misses of earlier rows).
           const uint32_t m = s_olen - 1, n = s_len;
           const uint32_t* Wc = s_col[cur];
-          if (threadIdx.x < m) {
-            const uint32_t v = rec[threadIdx.x];
-            const uint32_t pos = count_greater(Wc, n, v);
-            s_fpos[threadIdx.x] = pos;
-            s_fhit[threadIdx.x] = (pos < n && Wc[pos] == v) ? 1u : 0u;
+          // wave k < m places row k: a 64-way search (64 samples a level,
+          // compared in one step, counted with a ballot) needs three
+          // dependent LDS reads for the longest columns instead of fourteen
+          const uint32_t wv = threadIdx.x >> 6, ln = threadIdx.x & 63u;
+          if (wv < m) {
+            const uint32_t v = rec[wv];
+            uint32_t lo = 0, hi = n;  // the count of elements above v lies in [lo, hi]
+            while (hi - lo > 64) {
+              const uint32_t span = hi - lo;
+              const uint32_t at = lo + uint32_t((uint64_t(ln + 1) * span) / 65);
+              const int c = __popcll(__ballot(Wc[at] > v));  // samples above v
+              const uint32_t lo2 = c == 0 ? lo : lo + uint32_t((uint64_t(c) * span) / 65) + 1;
+              const uint32_t hi2 = c == 64 ? hi : lo + uint32_t((uint64_t(c + 1) * span) / 65);
+              lo = lo2;
+              hi = hi2;
+            }
+            const uint32_t pos = lo + uint32_t(__popcll(__ballot(ln < hi - lo && Wc[lo + ln] > v)));
+            if (ln == 0) {
+              s_fpos[wv] = pos;
+              s_fhit[wv] = (pos < n && Wc[pos] == v) ? 1u : 0u;
+            }
           }
           __syncthreads();
           uint32_t fp[kInlineRows], fh[kInlineRows], nh = 0;
