@@ -2695,6 +2695,28 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
       for (uint32_t i = threadIdx.x; i < s_len; i += kLongThreads) s_col[0][i] = pool[s_off + i];
     __syncthreads();
     for (int steps = 0;; ++steps) {
+      // the next owner, loaded by thread 0 during this addition
+      unsigned int po = 0;
+      uint64_t pod = 0;
+      uint4 pr0 = make_uint4(0, 0, 0, 0), pr1 = make_uint4(0, 0, 0, 0);
+      bool pf = false;
+      // the next pivot from the heads of the working column and the owner
+      // (both heads are the pivot); its owner's loads are issued at once
+      auto prefetch_next = [&](const uint32_t* X, auto own) {
+        uint32_t hi = 1, hj = 1;
+        while (hi < s_len && hj < s_olen && X[hi] == own(hj)) {
+          ++hi;
+          ++hj;
+        }
+        if (hi < s_len || hj < s_olen) {
+          const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > own(hj)) ? X[hi] : own(hj);
+          po = owner[np];
+          pod = pdesc[np];
+          pr0 = prow[2 * int64_t(np)];
+          pr1 = prow[2 * int64_t(np) + 1];
+          pf = true;
+        }
+      };
       if (threadIdx.x == 0) {
         s_state = -1;
         s_spill = 0;
@@ -2725,6 +2747,12 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
             s_olen = uint32_t(od & 0xFFFFFFu);
             s_ooff = od >> 24;
             if (s_lds && (s_olen > kLongCap || s_len + s_olen > kLongCap)) s_spill = 1;
+            if (s_lds && !s_spill && s_olen <= kInlineRows + 1) {
+              // a short owner: its rows are at hand, so the next owner's
+              // loads are issued before the barrier
+              const uint32_t* rec = reinterpret_cast<const uint32_t*>(s_rec);
+              prefetch_next(s_col[cur], [&](uint32_t j) { return rec[j - 1]; });
+            }
           }
         }
       }
@@ -2770,27 +2798,8 @@ k_d1_reduce_long(uint64_t* __restrict__ col_desc, uint32_t* __restrict__ pool, C
           tph[1] += t - tmark;
           tmark = t;
         }
-        unsigned int po = 0;
-        uint64_t pod = 0;
-        uint4 pr0 = make_uint4(0, 0, 0, 0), pr1 = make_uint4(0, 0, 0, 0);
-        bool pf = false;
-        if (threadIdx.x == 0) {
-          const uint32_t* X = s_col[cur];
-          auto own = [&](uint32_t j) { return short_owner ? rec[j - 1] : s_own[j]; };  // j >= 1
-          uint32_t hi = 1, hj = 1;  // both heads are the pivot
-          while (hi < s_len && hj < s_olen && X[hi] == own(hj)) {
-            ++hi;
-            ++hj;
-          }
-          if (hi < s_len || hj < s_olen) {
-            const uint32_t np = hi < s_len && (hj >= s_olen || X[hi] > own(hj)) ? X[hi] : own(hj);
-            po = owner[np];
-            pod = pdesc[np];
-            pr0 = prow[2 * int64_t(np)];
-            pr1 = prow[2 * int64_t(np) + 1];
-            pf = true;
-          }
-        }
+        if (threadIdx.x == 0 && !short_owner)  // (for a short owner: issued in the decision)
+          prefetch_next(s_col[cur], [&](uint32_t j) { return s_own[j]; });
         uint32_t w;
         if (short_owner) {
           // A short owner (most of the additions of the long chains): each of
