@@ -461,6 +461,9 @@ struct HotTables {
   uint16_t tet_nbm[24];
   uint8_t tri_tet[36][2];
   uint8_t pair_tri[14][14];
+  // the two star tets on triangle t and the neighbour each adds to it:
+  // bytes (tet 0, its third neighbour, tet 1, its third neighbour)
+  uint32_t tri_info[36];
 };
 
 // LDS of the lower-star kernel: per-lane slot tables and the block's
@@ -481,6 +484,13 @@ __device__ __forceinline__ void load_hot_tables(HotTables& T) {
     T.tri_nbm[tid] = c_st.tri_nbm[tid];
     T.tri_tet[tid][0] = c_st.tri_tet[tid][0];
     T.tri_tet[tid][1] = c_st.tri_tet[tid][1];
+    uint32_t info = 0;
+    for (int i = 0; i < 2; ++i) {
+      const uint32_t q = c_st.tri_tet[tid][i];
+      const uint32_t c = uint32_t(ffs32(uint32_t(c_st.tet_nbm[q]) & ~uint32_t(c_st.tri_nbm[tid])));
+      info |= (q | (c << 8)) << (16 * i);
+    }
+    T.tri_info[tid] = info;
   }
   if (tid < 24) T.tet_nbm[tid] = c_st.tet_nbm[tid];
   if (tid < 196) T.pair_tri[tid / 14][tid % 14] = c_st.pair_tri[tid / 14][tid % 14];
@@ -555,7 +565,9 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
   const auto S = G.site(active ? v : 0);
   int rx = 0;
   uint32_t low = 0;
-  uint64_t pos = 0;  // nibble k: position of neighbour k among lower neighbours
+  // nibble k: position of neighbour k among the lower neighbours, 15 for a
+  // neighbour that is not lower
+  uint64_t pos = 0;
   uint32_t critE = 0, critQ = 0;
   uint64_t critT = 0;
   uint64_t ecode = 0;          // 3 bits per neighbour
@@ -575,16 +587,28 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
         if (r[k] < rx) low |= 1u << k;
       }
     }
+    // position of lower neighbour k = the number of neighbours of lower rank
+    // (the others, and missing ones at INT_MAX, rank above it), counted once
+    // per pair: p[j] starts at the 13 - j pairs (j, k > j) and loses those
+    // where r[j] is the larger; ranks are distinct, so this is exact wherever
+    // r[j] ties with no other rank, that is for every lower neighbour
+    uint32_t pk[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) pk[k] = uint32_t(13 - k);
+#pragma unroll
+    for (int k = 1; k < 14; ++k)
+#pragma unroll
+      for (int j = 0; j < k; ++j) {
+        const uint32_t c = r[j] < r[k] ? 1u : 0u;
+        pk[k] += c;
+        pk[j] -= c;
+      }
     uint64_t bypos = 0;  // nibble p: neighbour at position p
 #pragma unroll
     for (int k = 0; k < 14; ++k) {
-      if ((low >> k) & 1u) {
-        uint32_t p = 0;
-#pragma unroll
-        for (int j = 0; j < 14; ++j) p += (((low >> j) & 1u) && r[j] < r[k]) ? 1u : 0u;
-        pos |= uint64_t(p) << (4 * k);
-        bypos |= uint64_t(k) << (4 * p);
-      }
+      const bool lk = (low >> k) & 1u;
+      pos |= uint64_t(lk ? pk[k] : 15u) << (4 * k);
+      if (lk) bypos |= uint64_t(k) << (4 * pk[k]);
     }
     if (low == 0) {
       down_out[v] = v;
@@ -620,28 +644,21 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
           SLOT_CELL(s) = uint8_t((2u << 6) | t);
           CELL_SLOT(14 + t) = uint8_t(s);
           ++s;
-          // tets on triangle t whose third neighbour is lower than b
+          // tets on triangle t whose third neighbour is lower than b (a
+          // neighbour that is not lower has position 15 > Q), by increasing
+          // position of that neighbour
+          const uint32_t ti = T.tri_info[t];
+          const uint32_t q0 = ti & 255u, q1 = (ti >> 16) & 255u;
+          const uint32_t r0 = nib(pos, int((ti >> 8) & 255u)), r1 = nib(pos, int(ti >> 24));
+          const bool in0 = r0 < uint32_t(Q), in1 = r1 < uint32_t(Q);
           int qa = -1, qb = -1;
-          uint32_t ra = 0, rb = 0;
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int q = T.tri_tet[t][i];
-            if (!((Lq >> q) & 1u)) continue;
-            const uint32_t third = uint32_t(T.tet_nbm[q]) & ~uint32_t(T.tri_nbm[t]);
-            const uint32_t rp = nib(pos, ffs32(third));
-            if (rp >= uint32_t(Q)) continue;
-            if (qa < 0) {
-              qa = q;
-              ra = rp;
-            } else {
-              qb = q;
-              rb = rp;
-            }
-          }
-          if (qb >= 0 && rb < ra) {
-            const int tq = qa;
-            qa = qb;
-            qb = tq;
+          if (in0 && in1) {
+            qa = int(r0 < r1 ? q0 : q1);
+            qb = int(r0 < r1 ? q1 : q0);
+          } else if (in0) {
+            qa = int(q0);
+          } else if (in1) {
+            qa = int(q1);
           }
           if (qa >= 0) {
             SLOT_CELL(s) = uint8_t((3u << 6) | qa);
