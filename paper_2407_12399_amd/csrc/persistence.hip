@@ -464,6 +464,8 @@ struct HotTables {
   // the two star tets on triangle t and the neighbour each adds to it:
   // bytes (tet 0, its third neighbour, tet 1, its third neighbour)
   uint32_t tri_info[36];
+  // neighbours b with a star triangle on (k, b) (14-bit mask)
+  uint16_t edge_adj[14];
 };
 
 // LDS of the lower-star kernel: per-lane slot tables and the block's
@@ -493,6 +495,12 @@ __device__ __forceinline__ void load_hot_tables(HotTables& T) {
     T.tri_info[tid] = info;
   }
   if (tid < 24) T.tet_nbm[tid] = c_st.tet_nbm[tid];
+  if (tid < 14) {
+    uint32_t adj = 0;
+    for (int b = 0; b < 14; ++b)
+      if (c_st.pair_tri[tid][b] != 255) adj |= 1u << b;
+    T.edge_adj[tid] = uint16_t(adj);
+  }
   if (tid < 196) T.pair_tri[tid / 14][tid % 14] = c_st.pair_tri[tid / 14][tid % 14];
 }
 
@@ -615,11 +623,7 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
     } else {
       const int k0 = int(nib(bypos, 0));
       down_out[v] = v + S.nb(k0);
-      uint64_t Lt = 0;
-      uint32_t Lq = 0;
-#pragma unroll
-      for (int t = 0; t < 36; ++t)
-        if ((uint32_t(T.tri_nbm[t]) & low) == uint32_t(T.tri_nbm[t])) Lt |= 1ull << t;
+      uint32_t Lq = 0;  // lower tets
 #pragma unroll
       for (int q = 0; q < 24; ++q)
         if ((uint32_t(T.tet_nbm[q]) & low) == uint32_t(T.tet_nbm[q])) Lq |= 1u << q;
@@ -682,21 +686,25 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
         if (sl < 64) m0 |= 1ull << sl;
         else m1 |= 1ull << (sl - 64);
       };
+      // edge k was just paired (k is in Ec): a lower triangle (k, b) now has
+      // one unpaired face exactly when edge b is unpaired
       auto push_edge_cof = [&](int k) {
-        uint64_t m = T.edge_trim[k] & Lt;
+        uint32_t m = uint32_t(T.edge_adj[k]) & low & ~Ec;
         while (m) {
-          const int t = ffs64(m);
+          const int b = ffs32(m);
           m &= m - 1;
-          if (__popc(uint32_t(T.tri_nbm[t]) & ~Ec) == 1)
-            set_slot(O0, O1, CELL_SLOT(14 + t));
+          set_slot(O0, O1, CELL_SLOT(14 + T.pair_tri[k][b]));
         }
       };
+      // triangle t was just paired: of its two star tets, the lower ones left
+      // with one unpaired face
       auto push_tri_cof = [&](int t) {
-        uint32_t m = T.tri_tetm[t] & Lq;
-        while (m) {
-          const int q = ffs32(m);
-          m &= m - 1;
-          if (__popcll(T.tet_trim[q] & ~Tc) == 1) set_slot(O0, O1, CELL_SLOT(50 + q));
+        const uint32_t ti = T.tri_info[t];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int q = int((ti >> (16 * i)) & 255u);
+          if (((Lq >> q) & 1u) && __popcll(T.tet_trim[q] & ~Tc) == 1)
+            set_slot(O0, O1, CELL_SLOT(50 + q));
         }
       };
       auto set_tcode = [&](int t, uint32_t c) {
@@ -717,6 +725,10 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
           }
           const uint32_t cc = SLOT_CELL(sl);
           const int dim = int(cc >> 6), idx = int(cc & 63u);
+          // a triangle pairs with its unpaired edge, a tet with its unpaired
+          // triangle; then the paired triangle's tets (and the paired edge's
+          // triangles) are pushed, once for both kinds
+          int tri = -1, edge = -1;
           if (dim == 2) {
             if ((Tc >> idx) & 1ull) continue;
             const uint32_t u = uint32_t(T.tri_nbm[idx]) & ~Ec;
@@ -729,8 +741,8 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
             Tc |= 1ull << idx;
             const uint32_t j = __popcll(T.edge_trim[k] & ((1ull << idx) - 1ull));
             ecode |= uint64_t(j) << (3 * k);
-            push_tri_cof(idx);
-            push_edge_cof(k);
+            tri = idx;
+            edge = k;
           } else {
             if ((Qc >> idx) & 1u) continue;
             const uint64_t u = T.tet_trim[idx] & ~Tc;
@@ -742,8 +754,10 @@ __device__ __forceinline__ void k3_block(const int32_t* __restrict__ rank, const
             Tc |= 1ull << t;
             Qc |= 1u << idx;
             set_tcode(t, T.tri_tet[t][0] == idx ? 2u : 3u);
-            push_tri_cof(t);
+            tri = t;
           }
+          push_tri_cof(tri);
+          if (edge >= 0) push_edge_cof(edge);
         }
         if (!(Z0 | Z1)) break;
         int sl;
@@ -902,7 +916,8 @@ k_gradient(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ code_out
 
 // Work queue of 3D tiles for the persistent form of the lower-star kernel: the
 // tiles of field f are items tile_base[f] .. tile_base[f + 1] - 1, numbered x
-// fastest within the field; a tile holds tx * ty * tz = kGradThreads vertices.
+// fastest within the field; a tile holds tx * ty * tz = kGradThreads vertices,
+// with tx and ty powers of two.
 // tx == 0 instead makes item i the run of vertex ids i * kGradThreads ..
 // (i + 1) * kGradThreads - 1 over all fields (no idle lanes at field edges).
 // The items are split into kTileQueues contiguous ranges, one queue each;
@@ -939,6 +954,10 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
   __shared__ K3Shared sh;
   __shared__ HotTables T;
   __shared__ int64_t s_item[kK3Batch];
+  // per item of the round: (first vertex, vertices of the field left from
+  // the tile's corner along x, y and z) and the field's y and z strides
+  __shared__ int4 s_tile[kK3Batch];
+  __shared__ int2 s_stride[kK3Batch];
   __shared__ uint16_t s_order[kK3Batch * kGradThreads];  // batch slots sorted by work
   __shared__ unsigned int s_hist[16];
   __shared__ int s_next;
@@ -946,28 +965,38 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
   const int tid = threadIdx.x;
   const unsigned lane = threadIdx.x & 63u;
   const bool runs = q.tx == 0;
-  const int tx = runs ? 1 : q.tx, ty = runs ? 1 : q.ty;
-  // vertex of lane position `pos` of item `item` (act: inside its field)
-  auto vertex = [&](int64_t item, int pos, bool* act) -> int {
-    if (item < 0) {
-      *act = false;
-      return 0;
+  // lane position -> tile coordinates (tile sides are powers of two; a run is
+  // one row of kGradThreads)
+  const int sx = ffs32(uint32_t(runs ? kGradThreads : q.tx)), sy = runs ? 0 : ffs32(uint32_t(q.ty));
+  const int mx = (1 << sx) - 1, my = (1 << sy) - 1;
+  // the corner and extent of item `item` (once per item, on one lane)
+  auto place = [&](int b, int64_t item) {
+    int4 t = make_int4(0, 0, 0, 0);  // no item: no lane is inside
+    int2 st = make_int2(0, 0);
+    if (item >= 0 && runs) {
+      const int64_t v0 = item * kGradThreads;
+      t = make_int4(int(v0), int(min<int64_t>(G.total() - v0, kGradThreads)), 1, 1);
+    } else if (item >= 0) {
+      int f = 0;
+      while (f + 1 < q.nf && item >= q.tile_base[f + 1]) ++f;
+      const int4 fd = q.field[f];
+      const int nbx = (fd.y + q.tx - 1) / q.tx, nby = (fd.z + q.ty - 1) / q.ty;
+      const int64_t i = item - q.tile_base[f];
+      const int bx = int(i % nbx), by = int((i / nbx) % nby), bz = int(i / (int64_t(nbx) * nby));
+      const int x = bx * q.tx, y = by * q.ty, z = bz * q.tz;
+      t = make_int4(fd.x + x + fd.y * (y + fd.z * z), fd.y - x, fd.z - y, fd.w - z);
+      st = make_int2(fd.y, fd.y * fd.z);
     }
-    if (runs) {
-      const int64_t v = item * kGradThreads + pos;
-      *act = v < G.total();
-      return *act ? int(v) : 0;
-    }
-    int f = 0;
-    while (f + 1 < q.nf && item >= q.tile_base[f + 1]) ++f;
-    const int4 fd = q.field[f];
-    const int nbx = (fd.y + q.tx - 1) / q.tx, nby = (fd.z + q.ty - 1) / q.ty;
-    const int64_t t = item - q.tile_base[f];
-    const int bx = int(t % nbx), by = int((t / nbx) % nby), bz = int(t / (int64_t(nbx) * nby));
-    const int lx = pos % tx, ly = (pos / tx) % ty, lz = pos / (tx * ty);
-    const int x = bx * q.tx + lx, y = by * q.ty + ly, z = bz * q.tz + lz;
-    *act = x < fd.y && y < fd.z && z < fd.w;
-    return *act ? fd.x + x + fd.y * (y + fd.z * z) : 0;
+    s_tile[b] = t;
+    s_stride[b] = st;
+  };
+  // vertex of lane position `pos` of the round's item b (act: inside its field)
+  auto vertex = [&](int b, int pos, bool* act) -> int {
+    const int4 t = s_tile[b];
+    const int2 st = s_stride[b];
+    const int lx = pos & mx, ly = (pos >> sx) & my, lz = pos >> (sx + sy);
+    *act = lx < t.y && ly < t.z && lz < t.w;
+    return *act ? t.x + lx + st.x * ly + st.y * lz : 0;
   };
   int probe = 0;  // queues tried so far (uniform over the workgroup)
   for (;;) {
@@ -983,6 +1012,7 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
             break;
           }
         }
+        place(b, s_item[b]);
       }
       s_next = 0;
     }
@@ -996,7 +1026,7 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
 #pragma unroll
     for (int b = 0; b < kK3Batch; ++b) {
       bool act;
-      const int v = vertex(s_item[b], tid, &act);
+      const int v = vertex(b, tid, &act);
       int c = 0;
       if (act) {
         const auto S0 = G.site(v);
@@ -1036,7 +1066,7 @@ k_gradient_tiles(const int32_t* __restrict__ rank, Geo G, uint4* __restrict__ co
       if (g >= kGroups) break;
       const int slot = s_order[(kGroups - 1 - g) * 64 + int(lane)];  // heaviest first
       bool act;
-      const int v = vertex(s_item[slot / kGradThreads], slot % kGradThreads, &act);
+      const int v = vertex(slot / kGradThreads, slot % kGradThreads, &act);
       k3_block<true>(rank, G, code_out, down_out, co, T, sh, act, v);
     }
   }
