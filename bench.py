@@ -59,16 +59,16 @@ ORDER_STAGES = ("K1 order keys", "K1 radix sort", "K2 rank")
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (fetch x2.0, write x1.0).  It belongs to the kernel source and
 # tile shape it was measured on: another source or shape reports null.
-K3_COUNTERS = {"source_sha1": "ec48bf4d5c5b971035706d93d464dbd1e410af82", "tiles": (8, 8, 4),
-               "dims": (256, 256, 256), "fetch_kib": 51383.0, "write_kib": 515305.0,
+K3_COUNTERS = {"source_sha1": "c48288b8a31192466980e48d1e6f163af1e4d89b", "tiles": (8, 8, 4),
+               "dims": (256, 256, 256), "fetch_kib": 54614.4, "write_kib": 515074.0,
                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # SQ_INSTS_VALU of the same launch divided by the vertex count / 64 (wave-level
 # VALU instructions per 64 vertices; the waves are persistent, so SQ_WAVES
 # counts workgroups, not vertices)
-K3_VALU_PER_64 = {"source_sha1": "ec48bf4d5c5b971035706d93d464dbd1e410af82", "tiles": (8, 8, 4),
-                  "valu": 10066.9}
+K3_VALU_PER_64 = {"source_sha1": "c48288b8a31192466980e48d1e6f163af1e4d89b", "tiles": (8, 8, 4),
+                  "valu": 7397.6}
 # untimed persistence maps before timing: the launch tuner tries 7 K3 tile
 # shapes and 5 D1 block sizes, one per map
 WARM_MAPS = 7
